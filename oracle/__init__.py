@@ -1,0 +1,277 @@
+"""CPU oracle for the PageRank pipeline kernels K0..K3 (test infrastructure).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It wraps ``ppo.c`` -- a plain,
+single-threaded FP64 C implementation written from the paper (Dreher et
+al., "PageRank Pipeline Benchmark", arXiv 1603.01876, Sec. IV.A-IV.D and the
+Appendix) -- with numpy arrays.  It never touches the GPU library.
+
+Parity pins live in ``tests/test_oracle_*.py``; see the header of ppo.c for
+which pin covers which function.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ppo.c")
+_LIB = os.path.join(_HERE, "libppo.so")
+
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_f64p = ctypes.POINTER(ctypes.c_double)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+
+
+class _Kron(ctypes.Structure):
+    _fields_ = [("scale", ctypes.c_int32), ("edge_factor", ctypes.c_int32),
+                ("a", ctypes.c_double), ("b", ctypes.c_double),
+                ("c", ctypes.c_double), ("d", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
+def build() -> str:
+    """Compile ppo.c into oracle/libppo.so (always rebuilds)."""
+    cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
+           "-Wall", "-Wextra", "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        L.ppo_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+        L.ppo_philox4x32_10.restype = None
+        L.ppo_kron_thresholds.argtypes = [ctypes.POINTER(_Kron), _u32p]
+        L.ppo_permute.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64]
+        L.ppo_permute.restype = ctypes.c_int64
+        L.ppo_generate_range.argtypes = [ctypes.POINTER(_Kron), ctypes.c_int64, ctypes.c_int64,
+                                         ctypes.c_int, _i64p, _i64p]
+        L.ppo_sort.argtypes = [ctypes.c_int32, ctypes.c_int64, _i64p, _i64p, _i64p, _i64p]
+        L.ppo_filter.argtypes = [ctypes.c_int32, ctypes.c_int64, _i64p, _i64p, _i64p, _i64p,
+                                 _i64p, _i32p, _f64p, _i64p, _i32p, _f64p, _i64p]
+        L.ppo_filter_rows.argtypes = [ctypes.c_int32, ctypes.c_int64, _i64p, _i64p, _i64p,
+                                      ctypes.c_int64, _i64p, _i32p, _f64p, ctypes.c_int64,
+                                      _i64p, _i64p, _i64p, _i64p]
+        L.ppo_init_r.argtypes = [ctypes.c_int64, ctypes.c_uint64, ctypes.c_int32, _f64p]
+        L.ppo_pagerank.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, ctypes.c_int32,
+                                   ctypes.c_double, _f64p, _f64p]
+        L.ppo_step_rows.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _f64p,
+                                    _f64p, ctypes.c_double, ctypes.c_double, _f64p]
+        _lib = L
+    return _lib
+
+
+def _p(a, t):
+    if a is None:
+        return None
+    return a.ctypes.data_as(t)
+
+
+def _check(st, what):
+    if st != 0:
+        raise RuntimeError(f"oracle {what} failed with status {st}")
+
+
+# --------------------------------------------------------------------------
+# K0: generator (Sec. IV.A)
+# --------------------------------------------------------------------------
+@dataclass(frozen=True)
+class Kron:
+    scale: int
+    edge_factor: int = 16
+    a: float = 0.57
+    b: float = 0.19
+    c: float = 0.19
+    d: float = 0.05
+    seed: int = 1603
+
+    @property
+    def n(self) -> int:
+        return 1 << self.scale
+
+    @property
+    def m(self) -> int:
+        return self.edge_factor << self.scale
+
+    def _c(self):
+        return _Kron(self.scale, self.edge_factor, self.a, self.b, self.c, self.d,
+                     self.seed & (2**64 - 1))
+
+
+def philox4x32_10(ctr, key):
+    c = np.asarray(ctr, dtype=np.uint32)
+    k = np.asarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().ppo_philox4x32_10(_p(c, _u32p), _p(k, _u32p), _p(out, _u32p))
+    return out
+
+
+def kron_thresholds(p: Kron):
+    thr = np.zeros(3, dtype=np.uint32)
+    _check(lib().ppo_kron_thresholds(ctypes.byref(p._c()), _p(thr, _u32p)), "thresholds")
+    return thr
+
+
+def permute(scale: int, seed: int, x: int) -> int:
+    return int(lib().ppo_permute(scale, seed & (2**64 - 1), x))
+
+
+def generate(p: Kron, e0: int = 0, count: int | None = None, permute: bool = True):
+    if count is None:
+        count = p.m - e0
+    u = np.empty(count, dtype=np.int64)
+    v = np.empty(count, dtype=np.int64)
+    _check(lib().ppo_generate_range(ctypes.byref(p._c()), e0, count, int(permute),
+                                    _p(u, _i64p), _p(v, _i64p)), "generate")
+    return u, v
+
+
+# --------------------------------------------------------------------------
+# K1: sort (Sec. IV.B)
+# --------------------------------------------------------------------------
+def sort(scale: int, u, v):
+    u = np.ascontiguousarray(u, dtype=np.int64)
+    v = np.ascontiguousarray(v, dtype=np.int64)
+    uo = np.empty_like(u)
+    vo = np.empty_like(v)
+    _check(lib().ppo_sort(scale, u.size, _p(u, _i64p), _p(v, _i64p),
+                          _p(uo, _i64p), _p(vo, _i64p)), "sort")
+    return uo, vo
+
+
+# --------------------------------------------------------------------------
+# K2: filter (Sec. IV.C)
+# --------------------------------------------------------------------------
+@dataclass
+class Filtered:
+    n: int
+    nnz: int
+    d_in: np.ndarray
+    d_out: np.ndarray
+    A_rp: np.ndarray
+    A_col: np.ndarray
+    A_val: np.ndarray
+    AT_rp: np.ndarray
+    AT_col: np.ndarray
+    AT_val: np.ndarray
+
+
+def filter(scale: int, u, v) -> Filtered:
+    u = np.ascontiguousarray(u, dtype=np.int64)
+    v = np.ascontiguousarray(v, dtype=np.int64)
+    n = 1 << scale
+    m = u.size
+    d_in = np.empty(n, np.int64)
+    d_out = np.empty(n, np.int64)
+    A_rp = np.empty(n + 1, np.int64)
+    AT_rp = np.empty(n + 1, np.int64)
+    cap = max(m, 1)
+    A_col = np.empty(cap, np.int32)
+    A_val = np.empty(cap, np.float64)
+    AT_col = np.empty(cap, np.int32)
+    AT_val = np.empty(cap, np.float64)
+    nnz = np.zeros(1, np.int64)
+    _check(lib().ppo_filter(scale, m, _p(u, _i64p), _p(v, _i64p), _p(d_in, _i64p),
+                            _p(d_out, _i64p), _p(A_rp, _i64p), _p(A_col, _i32p),
+                            _p(A_val, _f64p), _p(AT_rp, _i64p), _p(AT_col, _i32p),
+                            _p(AT_val, _f64p), _p(nnz, _i64p)), "filter")
+    z = int(nnz[0])
+    return Filtered(n, z, d_in, d_out, A_rp, A_col[:z].copy(), A_val[:z].copy(),
+                    AT_rp, AT_col[:z].copy(), AT_val[:z].copy())
+
+
+def filter_rows(scale: int, u, v, rows, want_nnz: bool = False):
+    """Sampled K2 at any scale: d_in, d_out, mx over all edges plus the
+    listed rows of A^T.  Returns (rp, col, val, d_in, d_out, mx, nnz|None)."""
+    u = np.ascontiguousarray(u, dtype=np.int64)
+    v = np.ascontiguousarray(v, dtype=np.int64)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    n = 1 << scale
+    m = u.size
+    # A row of A^T has at most d_in[v] entries; bound the buffer by m.
+    cap = int(min(m, max(1, 64 * rows.size + 4096)))
+    while True:
+        rp = np.empty(rows.size + 1, np.int64)
+        col = np.empty(cap, np.int32)
+        val = np.empty(cap, np.float64)
+        d_in = np.empty(n, np.int64)
+        d_out = np.empty(n, np.int64)
+        mx = np.zeros(1, np.int64)
+        nnz = np.zeros(1, np.int64)
+        st = lib().ppo_filter_rows(scale, m, _p(u, _i64p), _p(v, _i64p), _p(rows, _i64p),
+                                   rows.size, _p(rp, _i64p), _p(col, _i32p), _p(val, _f64p),
+                                   cap, _p(d_in, _i64p), _p(d_out, _i64p), _p(mx, _i64p),
+                                   _p(nnz, _i64p) if want_nnz else None)
+        if st == -1 and cap < m:
+            cap = m
+            continue
+        _check(st, "filter_rows")
+        k = int(rp[-1])
+        return (rp, col[:k].copy(), val[:k].copy(), d_in, d_out, int(mx[0]),
+                int(nnz[0]) if want_nnz else None)
+
+
+# --------------------------------------------------------------------------
+# K3: PageRank (Sec. IV.D, Appendix)
+# --------------------------------------------------------------------------
+def init_r(n: int, seed: int, rhs: int = 0):
+    r = np.empty(n, np.float64)
+    _check(lib().ppo_init_r(n, seed & (2**64 - 1), rhs, _p(r, _f64p)), "init_r")
+    return r
+
+
+def pagerank(n: int, A_rp, A_col, A_val, r0, iters: int = 20, c: float = 0.85):
+    """Returns (r_iters, sums) with sums[k] = sum(r_k), k = 0..iters."""
+    A_rp = np.ascontiguousarray(A_rp, dtype=np.int64)
+    A_col = np.ascontiguousarray(A_col, dtype=np.int32)
+    A_val = np.ascontiguousarray(A_val, dtype=np.float64)
+    r = np.array(r0, dtype=np.float64, copy=True)
+    sums = np.empty(iters + 1, np.float64)
+    if A_col.size == 0:
+        A_col = np.zeros(1, np.int32)
+        A_val = np.zeros(1, np.float64)
+    _check(lib().ppo_pagerank(n, _p(A_rp, _i64p), _p(A_col, _i32p), _p(A_val, _f64p),
+                              iters, c, _p(r, _f64p), _p(sums, _f64p)), "pagerank")
+    return r, sums
+
+
+def step_rows(n: int, rp, col, val, r, s: float, c: float = 0.85):
+    rp = np.ascontiguousarray(rp, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    nrows = rp.size - 1
+    y = np.empty(max(nrows, 0), np.float64)
+    if col.size == 0:
+        col = np.zeros(1, np.int32)
+        val = np.zeros(1, np.float64)
+    _check(lib().ppo_step_rows(n, nrows, _p(rp, _i64p), _p(col, _i32p), _p(val, _f64p),
+                               _p(r, _f64p), s, c, _p(y, _f64p)), "step_rows")
+    return y
+
+
+def transpose_csr(n: int, rp, col, val):
+    """CSR(A) -> CSR(A^T) by a stable counting sort on the column (numpy;
+    used by tests that feed K3 hand-built matrices)."""
+    rp = np.asarray(rp, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    order = np.argsort(col, kind="stable")
+    trp = np.zeros(n + 1, np.int64)
+    np.add.at(trp, col + 1, 1)
+    trp = np.cumsum(trp)
+    return trp, rows[order].astype(np.int32), np.asarray(val, np.float64)[order]
