@@ -1,0 +1,254 @@
+#!/usr/bin/env python3
+"""PageRank pipeline benchmark on one MI355X; prints one JSON line.
+
+A step is one pass of the whole pipeline over one synthetic Kronecker graph
+held in HBM: K0 generate, K1 sort, K2 filter (into CSR(A^T)), K3 PageRank
+(initial vector + 20 damped iterations).  The headline metric is the
+paper's K3 rate, 20*M / t_K3 edges per second (Sec. IV.D), on the largest
+single-GPU instance (S = 26, M = 2^30 edges, FP32 values and ranks with
+compensated row sums, FP64 sum(r) and teleport).  K1 and K2 rates (M/t,
+Sec. IV.B and IV.C) and the FP64 form on the same graph are reported beside
+it.  The roofline object prices the SpMV kernel's algorithmic HBM bytes
+against its average launch time, timed with HIP events on its stream.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--scale", type=int, default=26)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--iters", type=int, default=20)
+    ap.add_argument("--no-f64-side", action="store_true", help="skip the FP64 side-by-side run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def spmv_bytes(n: int, nnz: int, dtype: str) -> int:
+    """Algorithmic HBM bytes of one pull-form SpMV launch: row pointers
+    4(N+1), columns 4Z, values Z*sizeof(val), x read once N*sizeof(val), y
+    written once N*sizeof(val)."""
+    w = 8 if dtype == "f64" else 4
+    return 4 * (n + 1) + (4 + w) * nnz + 2 * w * n
+
+
+def cpu_baseline(AT, scale: int, m: int, budget_s: float):
+    """The oracle (single thread, FP64) timed on a contiguous block of rows of
+    the same CSR(A^T): one damped iteration over those rows.  Scaled to K3
+    edges/s: the rows hold a fraction f of the nnz, so the rate is
+    f*M / t_rows (one iteration processes M edges in the paper's metric)."""
+    import numpy as np
+    import oracle
+
+    n, z = AT.n, AT.nnz
+    rp = AT.row_ptr.cpu().numpy().astype(np.int64)
+    # Calibrate on a small block, then size the sample to the budget.
+    r = np.full(n, 1.0 / n)
+    target = max(1, min(z, 2_000_000))
+    rows = int(np.searchsorted(rp, target))
+    rows = max(1, min(rows, n))
+    t0 = time.perf_counter()
+    _run_rows(oracle, AT, rp, r, 0, rows)
+    t_cal = time.perf_counter() - t0
+    per_nnz = t_cal / max(1, rp[rows])
+    want = int(min(z, budget_s / max(per_nnz, 1e-12)))
+    rows2 = int(np.searchsorted(rp, want))
+    rows2 = max(rows, min(rows2, n))
+    t0 = time.perf_counter()
+    _run_rows(oracle, AT, rp, r, 0, rows2)
+    t = time.perf_counter() - t0
+    f = float(rp[rows2]) / float(max(z, 1))
+    value = f * m / t
+    return {"value": value, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle ppo_step_rows (FP64, 1 thread) on rows [0, {rows2}) of the S={scale} "
+                       f"CSR(A^T): {int(rp[rows2])} of {z} nnz ({100*f:.1f}%), one iteration, "
+                       f"{t:.1f} s; rate = fraction * M / t"),
+            "host_cpu": platform.processor() or platform.machine()}
+
+
+def _run_rows(oracle, AT, rp, r, r0, r1):
+    import numpy as np
+    a, b = int(rp[r0]), int(rp[r1])
+    col = AT.col[a:b].cpu().numpy()
+    val = AT.val[a:b].cpu().numpy().astype(np.float64)
+    sub = (rp[r0:r1 + 1] - a).astype(np.int64)
+    return oracle.step_rows(AT.n, sub, col, val, r, 1.0, 0.85)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU path is a design, not a build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1603_01876_amd import native as pp
+    from paper_1603_01876_amd import workloads
+
+    torch.cuda.set_device(0)
+    dev = "cuda"
+    S, dt = args.scale, args.dtype
+    spec = workloads.pipeline(S)
+    n, m = spec.n, spec.m
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    log(f"S={S} N={n} M={m} dtype={dt}: allocating")
+
+    u = torch.empty(m, dtype=torch.int64, device=dev)
+    v = torch.empty(m, dtype=torch.int64, device=dev)
+    us = torch.empty(m, dtype=torch.int64, device=dev)
+    vs = torch.empty(m, dtype=torch.int64, device=dev)
+    ws12 = torch.empty(max(pp.workspace_bytes(pp.K1, n, m), pp.workspace_bytes(pp.K2, n, m)),
+                       dtype=torch.uint8, device=dev)
+    AT = pp.CSR(n, 0, torch.empty(n + 1, dtype=torch.int32, device=dev),
+                torch.empty(m, dtype=torch.int32, device=dev),
+                torch.empty(m, dtype=tdt, device=dev))
+    d_in = torch.empty(n, dtype=torch.int32, device=dev)
+    d_out = torch.empty(n, dtype=torch.int32, device=dev)
+    r = torch.empty(n, dtype=tdt, device=dev)
+    sums = torch.empty(args.iters + 1, dtype=torch.float64, device=dev)
+    ws3 = torch.empty(pp.workspace_bytes(pp.K3, n, m, dt), dtype=torch.uint8, device=dev)
+    rseed = workloads.BASE_SEED
+
+    def step(timed):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ev[0].record()
+        pp.generate(spec, u, v)
+        ev[1].record()
+        pp.sort(S, u, v, us, vs, ws=ws12)
+        ev[2].record()
+        pp.filter(S, us, vs, dt, AT=AT, d_in=d_in, d_out=d_out, ws=ws12)
+        ev[3].record()
+        pp.init_r(n, rseed, dt, out=r, ws=ws3)
+        pp.pagerank(AT, r, iters=args.iters, c=workloads.DAMPING, sums=sums, ws=ws3)
+        ev[4].record()
+        return ev
+
+    for i in range(args.warmup):
+        step(False)
+        torch.cuda.synchronize()
+        log(f"warmup step {i} done (nnz={AT.nnz})")
+
+    pp.set_kernel_timing(True)
+    spmv_ms = []
+    evs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        evs.append(step(True))
+        spmv_ms += pp.kernel_times()      # waits for this step's last SpMV
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pp.set_kernel_timing(False)
+    log(f"timed {args.steps} steps in {t1 - t0:.3f} s")
+
+    k = {name: [] for name in ("k0", "k1", "k2", "k3")}
+    for ev in evs:
+        for j, name in enumerate(("k0", "k1", "k2", "k3")):
+            k[name].append(ev[j].elapsed_time(ev[j + 1]) / 1e3)
+    mean = {key: sum(val) / len(val) for key, val in k.items()}
+    z = AT.nnz
+    value = args.iters * m / mean["k3"]
+    spmv_avg_s = sum(spmv_ms) / len(spmv_ms) / 1e3
+    nbytes = spmv_bytes(n, z, dt)
+    achieved = nbytes / spmv_avg_s / 1e9
+    sums_h = sums.cpu().numpy()
+
+    out = {
+        "metric": "K3 PageRank edges/s (20*M/t_K3)",
+        "value": value,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": (t1 - t0) / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dt,
+        "data": "synthetic Kronecker graph (seeded counter-based generator, K0 on the GPU)",
+        "config": {"workload": f"kron-s{S}-{dt}", "scale": S, "vertices": n, "edges": m,
+                   "edge_factor": spec.edge_factor, "initiator": [spec.a, spec.b, spec.c, spec.d],
+                   "nnz_filtered": z, "iterations": args.iters, "damping": workloads.DAMPING,
+                   "parallelism": "single GPU"},
+        "kernels": {
+            "k0_ms": mean["k0"] * 1e3, "k1_ms": mean["k1"] * 1e3, "k2_ms": mean["k2"] * 1e3,
+            "k3_ms": mean["k3"] * 1e3,
+            "k1_edges_per_s": m / mean["k1"], "k2_edges_per_s": m / mean["k2"],
+            "k3_edges_per_s": value,
+            "spmv_avg_ms": spmv_avg_s * 1e3, "spmv_launches": len(spmv_ms),
+        },
+        "roofline": {"bound": "hbm", "kernel": f"k_spmv<{'float' if dt == 'f32' else 'double'}>",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": nbytes},
+        "sum_r": {"first": float(sums_h[0]), "last": float(sums_h[-1])},
+    }
+
+    if not args.no_f64_side and dt == "f32":
+        log("FP64 side-by-side")
+        r32 = r.double().clone()
+        del ws12
+        AT64 = pp.CSR(n, 0, AT.row_ptr.clone(), torch.empty(m, dtype=torch.int32, device=dev),
+                      torch.empty(m, dtype=torch.float64, device=dev))
+        ws2 = torch.empty(pp.workspace_bytes(pp.K2, n, m), dtype=torch.uint8, device=dev)
+        pp.filter(S, us, vs, "f64", AT=AT64, d_in=d_in, d_out=d_out, ws=ws2)
+        del ws2
+        ws64 = torch.empty(pp.workspace_bytes(pp.K3, n, m, "f64"), dtype=torch.uint8, device=dev)
+        r64 = torch.empty(n, dtype=torch.float64, device=dev)
+        sums64 = torch.empty(args.iters + 1, dtype=torch.float64, device=dev)
+        times = []
+        pp.set_kernel_timing(True)
+        spmv64 = []
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            pp.init_r(n, rseed, "f64", out=r64, ws=ws64)
+            pp.pagerank(AT64, r64, iters=args.iters, c=workloads.DAMPING, sums=sums64, ws=ws64)
+            e1.record()
+            spmv64 += pp.kernel_times()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) / 1e3)
+        pp.set_kernel_timing(False)
+        t64 = sum(times) / len(times)
+        s64 = sum(spmv64) / len(spmv64) / 1e3
+        err = float((r32 - r64).abs().sum() / r64.abs().sum())
+        b64 = spmv_bytes(n, AT64.nnz, "f64")
+        out["forms"] = {
+            "f64": {"k3_edges_per_s": args.iters * m / t64, "k3_ms": t64 * 1e3,
+                    "spmv_avg_ms": s64 * 1e3, "spmv_GBps": b64 / s64 / 1e9,
+                    "spmv_frac_of_peak": b64 / s64 / 1e9 / HBM_PEAK_GBS},
+            "f32_speedup_over_f64": t64 / mean["k3"],
+            "f32_rel_l1_vs_f64_gpu": err,
+        }
+        del AT64, ws64
+
+    if not args.no_cpu:
+        log("CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(AT, S, m, args.cpu_seconds)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

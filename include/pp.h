@@ -1,0 +1,159 @@
+/*
+ * pp.h -- C ABI of the MI355X (gfx950) PageRank pipeline library libpp.so.
+ *
+ * Implements the four kernels of the PageRank Pipeline Benchmark (Dreher et
+ * al., arXiv 1603.01876, Sec. IV): K0 Kronecker edge generation (Sec. IV.A),
+ * K1 sort by start vertex (Sec. IV.B), K2 filter into a normalised sparse
+ * matrix (Sec. IV.C) and K3 PageRank iterations (Sec. IV.D and the
+ * Appendix).
+ *
+ * Conventions for every entry point:
+ *  - Array pointers are DEVICE memory owned by the caller, unless marked
+ *    [host].  The library never allocates device memory; scratch comes from
+ *    a caller-provided workspace of at least pp_workspace_bytes() bytes
+ *    (any alignment; the library aligns inside it).
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is
+ *    enqueued asynchronously; outputs are defined once the stream has been
+ *    synchronised.  Exceptions are noted per call (pp_sort, pp_filter).
+ *  - Arguments are checked on the host before anything is enqueued; a
+ *    failed check returns PP_EINVAL / PP_ERANGE / PP_EWORKSPACE and leaves
+ *    every output untouched.  PP_EHIP reports a HIP runtime failure;
+ *    pp_last_error() then returns the HIP message.
+ *  - Vertex labels are 0-based in [0, 2^S).  Edge lists are int64.  Sparse
+ *    matrices use int32 row pointers and column indices, so edge counts
+ *    must stay below 2^31 (PP_ERANGE otherwise).
+ */
+#ifndef PP_H
+#define PP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PP_OK = 0,
+  PP_EINVAL = 1,     /* invalid argument or input that violates a precondition */
+  PP_ERANGE = 2,     /* size beyond the int32 index range or scale > 30 */
+  PP_EWORKSPACE = 3, /* workspace NULL or smaller than pp_workspace_bytes() */
+  PP_EHIP = 4        /* HIP runtime or launch failure */
+} pp_status;
+
+typedef enum {
+  PP_F64 = 0, /* FP64 matrix values and ranks */
+  PP_F32 = 1  /* FP32 values and ranks, compensated FP32 row sums;
+                 sum(r), the teleport scalar and 1/d_out stay FP64 */
+} pp_dtype;
+
+typedef enum { PP_K0 = 0, PP_K1 = 1, PP_K2 = 2, PP_K3 = 3 } pp_kernel;
+
+/* Kronecker generator parameters [host] (Sec. IV.A): N = 2^scale vertices,
+ * M = edge_factor * N edges, initiator quadrant probabilities a,b,c,d
+ * (non-negative, summing to 1), seed of the counter-based random stream. */
+typedef struct {
+  int32_t scale;       /* 1..30 */
+  int32_t edge_factor; /* 1..1024; the paper's k = 16 */
+  double a, b, c, d;
+  uint64_t seed;
+} pp_kron_params;
+
+/* A square sparse matrix in CSR form.  The struct itself is [host]; the
+ * three arrays are device memory.  row_ptr has n+1 entries, col and val
+ * have room for `cap` entries; val holds FP64 or FP32 values per the dtype
+ * argument of the call that uses it.  nnz is the number of stored entries
+ * (set by pp_filter, read by pp_pagerank). */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  int64_t cap;
+  int32_t *row_ptr;
+  int32_t *col;
+  void *val;
+} pp_csr;
+
+/* Text for a status code (static storage). */
+const char *pp_strerror(pp_status st);
+
+/* Text of the most recent failure in this thread ("" if none). */
+const char *pp_last_error(void);
+
+/* Workspace bytes needed by kernel k for n vertices, m edges (K0..K2) or
+ * at most m stored entries (K3), value type dt and nrhs right-hand sides
+ * (K3; 1 otherwise).  Returns 0 when no workspace is needed and
+ * (size_t)-1 for arguments out of range. */
+size_t pp_workspace_bytes(pp_kernel k, int64_t n, int64_t m, pp_dtype dt, int32_t nrhs);
+
+/* K0 (Sec. IV.A): writes the M = edge_factor * 2^scale edges (u[e], v[e]),
+ * e = 0..M-1, of the Kronecker graph: per level, quadrant (u-bit, v-bit)
+ * drawn with probabilities a,b,c,d from Philox4x32-10 keyed by the seed,
+ * then both labels relabelled by a seed-keyed bijection on scale bits.
+ * Self-loops and repeated edges are kept.  u, v: M int64 each.
+ * Needs no workspace.  The result depends only on the parameters. */
+pp_status pp_generate(const pp_kron_params *p, int64_t *u, int64_t *v, void *stream);
+
+/* K1 (Sec. IV.B): stable sort of the m edges (u, v) by u, so that
+ * u_out[i-1] <= u_out[i]; edges with equal u keep their input order.
+ * Requires 0 <= u[i], v[i] < 2^scale (checked on the device: PP_EINVAL).
+ * u_out/v_out must not overlap u/v.  Synchronises `stream` once, after the
+ * first pass, to report the input check. */
+pp_status pp_sort(int32_t scale, int64_t m, const int64_t *u, const int64_t *v,
+                  int64_t *u_out, int64_t *v_out, void *ws, size_t ws_bytes, void *stream);
+
+/* K2 (Sec. IV.C): from the K1 output (edges sorted by u), forms the count
+ * matrix A(u,v) = number of edges u->v, the in-degrees d_in = column sums
+ * of counts, removes every column whose in-degree equals the maximum and
+ * every column whose in-degree is 1 (both tests on the same d_in), takes
+ * d_out = row sums of the surviving counts and divides each surviving
+ * entry by its row's d_out (IEEE FP64 division; PP_F32 stores the quotient
+ * rounded to FP32).  Writes CSR(A^T): AT->row_ptr[v] .. AT->row_ptr[v+1]
+ * lists the sources u (ascending) of the surviving entries in column v of
+ * A, with their values; AT->n must be 2^scale and AT->cap >= m.
+ * d_in / d_out (2^scale int32 each, NULL = not returned).
+ * Input check on the device: labels in range and u non-decreasing, else
+ * PP_EINVAL.  Synchronises `stream` twice (input check, then the entry
+ * count, which it stores in AT->nnz). */
+pp_status pp_filter(int32_t scale, int64_t m, const int64_t *u, const int64_t *v, pp_dtype dt,
+                    pp_csr *AT, int32_t *d_in, int32_t *d_out, void *ws, size_t ws_bytes,
+                    void *stream);
+
+/* K3 initial vector (Sec. IV.D, r = rand(1,N); r = r./norm(r,1)): for each
+ * right-hand side j < nrhs, k_ij = top 24 bits of word 0 of Philox4x32-10
+ * keyed by the seed at counter (i, j, 0, 2); r_ij = k_ij / sum_i k_ij, one
+ * IEEE FP64 division of exact integers (FP32: that quotient rounded); if the
+ * sum is 0, r_ij = 1/n.  r: n x nrhs, row-major, of the dtype.  The integer
+ * sums live in the workspace: any workspace sized for pp_pagerank with the
+ * same n, dtype and nrhs is large enough (pp_workspace_bytes(PP_K3, n, 0,
+ * dt, nrhs) is the minimum). */
+pp_status pp_init_r(int64_t n, int32_t nrhs, uint64_t seed, pp_dtype dt, void *r, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/* K3 (Sec. IV.D and the Appendix): `iters` iterations of
+ *   r_j <- c * sum_i r_i * A(i,j) + ((1-c)/N) * sum(r)
+ * on CSR(A^T) (as written by pp_filter), for nrhs independent right-hand
+ * sides stored row-major in r (n x nrhs, in/out).  nrhs = 1 runs the
+ * sparse matrix-vector form; nrhs in 2..64 runs the sparse matrix-dense
+ * matrix form.  sums (device, (iters+1) x nrhs FP64, may be NULL) receives
+ * sum(r) of each right-hand side before every iteration and after the last
+ * one.  Dangling rows are not adjusted, so sum(r) may decay.  The caller
+ * must supply a valid CSR (row_ptr non-decreasing from 0 to nnz, columns in
+ * [0, n)); pp_filter's output always is. */
+pp_status pp_pagerank(const pp_csr *AT, pp_dtype dt, int32_t nrhs, int32_t iters, double c,
+                      void *r, double *sums, void *ws, size_t ws_bytes, void *stream);
+
+/* Benchmark instrumentation.  While enabled (enable != 0), each
+ * pp_pagerank call records a pair of HIP events on its stream around every
+ * launch of its sparse product kernel (one per iteration); the events are
+ * created once by this call and reused.  pp_kernel_times() waits for the
+ * last recorded pair and copies up to `cap` durations in milliseconds of
+ * the most recent pp_pagerank call into ms [host]; it returns how many were
+ * recorded (0 if none, -1 on a HIP error).  Process-wide state, meant for a
+ * single benchmarking thread. */
+pp_status pp_set_kernel_timing(int enable);
+int32_t pp_kernel_times(float *ms, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

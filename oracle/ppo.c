@@ -20,13 +20,15 @@
  *                special graphs (complete, star, permutation) => A = 0;
  *                invariants (sum of counts, rows summing to one)
  *   init_r       exact integer sum => sum(r0) = 1 within N ulp
- *   pagerank     dense power iteration; closed forms for a permutation
+ *   pagerank     extended-precision (long double) reference iteration;
+ *                dense power iteration; closed forms for a permutation
  *                matrix and for A = 0; the sum(r) recurrence; the Perron
  *                vector of c*A.' + (1-c)/N from numpy.linalg.eig (Sec. IV.D)
  *   step_rows    equals one pagerank iteration on every row
  */
 #include "ppo.h"
 
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -436,6 +438,34 @@ done:
 /* ------------------------------------------------------------------------ */
 /* K3 -- PageRank, Sec. IV.D and the Appendix.                               */
 /* ------------------------------------------------------------------------ */
+
+/* The paper defines K3 in exact arithmetic; its sums (the row-vector times  */
+/* matrix product and sum(r)) fix no rounding order.  Plain left-to-right    */
+/* FP64 accumulation of ~1e6-term sums and of 1e4-entry columns drifts by    */
+/* ~1e-12 over 20 iterations, the size of the tolerance the GPU is held to,  */
+/* so every sum here is compensated (Neumaier's variant of Kahan summation):  */
+/* the running FP64 sum s plus a correction c that collects each addition's  */
+/* exact rounding error.  Terms are still added in ascending index order.    */
+typedef struct {
+  double s, c;
+} csum;
+
+static void csum_add(csum *a, double x) {
+  double t = a->s + x;
+  if (fabs(a->s) >= fabs(x))
+    a->c += (a->s - t) + x;
+  else
+    a->c += (x - t) + a->s;
+  a->s = t;
+}
+
+static double csum_value(const csum *a) { return a->s + a->c; }
+
+static double sum_r(int64_t n, const double *r) {
+  csum a = {0.0, 0.0};
+  for (int64_t i = 0; i < n; ++i) csum_add(&a, r[i]);
+  return csum_value(&a);
+}
 int ppo_init_r(int64_t n, uint64_t seed, int32_t rhs, double *r) {
   if (n < 1 || n > ((int64_t)1 << 30) || rhs < 0 || !r) return PPO_EINVAL;
   /* r = rand(1,N); r = r ./ norm(r,1).  Each draw is a 24-bit integer k_i,
@@ -463,29 +493,24 @@ int ppo_pagerank(int64_t n, const int64_t *A_rp, const int32_t *A_col, const dou
                  int32_t iters, double c, double *r, double *sums) {
   if (n < 1 || iters < 0 || !A_rp || !r) return PPO_EINVAL;
   if (A_rp[n] > 0 && (!A_col || !A_val)) return PPO_EINVAL;
-  double *y = (double *)malloc((size_t)n * sizeof(double));
+  csum *y = (csum *)malloc((size_t)n * sizeof(csum));
   if (!y) return PPO_ENOMEM;
   /* a = ones(1,N) .* (1-c) ./ N */
   double a = (1.0 - c) / (double)n;
   for (int32_t it = 0; it < iters; ++it) {
-    double s = 0.0;
-    for (int64_t i = 0; i < n; ++i) s += r[i];
+    double s = sum_r(n, r);
     if (sums) sums[it] = s;
     /* r = ((c .* r) * A) + (a .* sum(r,2)): the row vector c.*r times A,
      * accumulated over i in ascending order, then the teleport term. */
-    for (int64_t j = 0; j < n; ++j) y[j] = 0.0;
+    for (int64_t j = 0; j < n; ++j) y[j].s = y[j].c = 0.0;
     for (int64_t i = 0; i < n; ++i) {
       double cr = c * r[i];
-      for (int64_t q = A_rp[i]; q < A_rp[i + 1]; ++q) y[A_col[q]] += cr * A_val[q];
+      for (int64_t q = A_rp[i]; q < A_rp[i + 1]; ++q) csum_add(&y[A_col[q]], cr * A_val[q]);
     }
     double t = a * s;
-    for (int64_t j = 0; j < n; ++j) r[j] = y[j] + t;
+    for (int64_t j = 0; j < n; ++j) r[j] = csum_value(&y[j]) + t;
   }
-  if (sums) {
-    double s = 0.0;
-    for (int64_t i = 0; i < n; ++i) s += r[i];
-    sums[iters] = s;
-  }
+  if (sums) sums[iters] = sum_r(n, r);
   free(y);
   return PPO_OK;
 }
@@ -496,12 +521,12 @@ int ppo_step_rows(int64_t n, int64_t nrows, const int64_t *rp, const int32_t *co
   double a = (1.0 - c) / (double)n;
   double t = a * s;
   for (int64_t q = 0; q < nrows; ++q) {
-    double acc = 0.0;
+    csum acc = {0.0, 0.0};
     for (int64_t k = rp[q]; k < rp[q + 1]; ++k) {
       if (col[k] < 0 || col[k] >= n) return PPO_EINVAL;
-      acc += (c * r[col[k]]) * val[k];
+      csum_add(&acc, (c * r[col[k]]) * val[k]);
     }
-    y[q] = acc + t;
+    y[q] = csum_value(&acc) + t;
   }
   return PPO_OK;
 }

@@ -74,13 +74,14 @@ int ppo_init_r(int64_t n, uint64_t seed, int32_t rhs, double *r);
 
 /* K3 (Sec. IV.D, Appendix): iters times r = ((c*r)*A) + ((1-c)/N)*sum(r),
  * on CSR(A).  sums (iters+1 entries, may be NULL) receives sum(r) before
- * each iteration and after the last. */
+ * each iteration and after the last.  Every sum is compensated (Neumaier),
+ * terms in ascending index order. */
 int ppo_pagerank(int64_t n, const int64_t *A_rp, const int32_t *A_col, const double *A_val,
                  int32_t iters, double c, double *r, double *sums);
 
 /* One damped step for a set of output entries, pull form: row q of the
  * given rows-of-A^T (entries rp[q]..rp[q+1], u ascending) yields
- * y[q] = sum_i (c*r_i)*val (i ascending) + ((1-c)/n)*s.  With rp = the
+ * y[q] = sum_i (c*r_i)*val (i ascending, compensated) + ((1-c)/n)*s.  With rp = the
  * full CSR(A^T) row pointer and nrows = n this is a whole iteration. */
 int ppo_step_rows(int64_t n, int64_t nrows, const int64_t *rp, const int32_t *col,
                   const double *val, const double *r, double s, double c, double *y);

@@ -1,0 +1,243 @@
+// k1_radix.hip -- stable LSD radix sort of 64-bit (hi << 32 | lo) keys on the
+// low key_bits bits of hi.  K1 sorts the edge list by u with it (Sec. IV.B);
+// K2 reuses it to order the u-sorted list by v (Sec. IV.C).
+//
+// One pass per digit of at most 8 bits (the S label bits are split evenly
+// over ceil(S/8) passes).  A pass is three launches with no waiting between
+// workgroups: per-tile digit counts, a device-wide exclusive scan of the
+// digit-major count table, and a scatter that ranks each key inside its
+// tile.  A tile is 4096 keys; each of the four waves owns 1024 contiguous
+// keys and walks them in 16 rounds of 64, so every load is a contiguous
+// 512 B wave access and the rank of a key among equal digits follows the
+// input order (stability).  Inside a round the lanes holding the same digit
+// are found with one ballot per digit bit; the lowest such lane advances the
+// wave's LDS counter for that digit by the group's population count.
+//
+// The first pass can read two int64 arrays (packing on the fly) and the
+// last pass can write two int64 arrays (unpacking), so K1 reads and writes
+// the caller's u/v directly and the intermediate passes move 8 B per key.
+#include "pp_common.hpp"
+
+namespace pp {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kPerThread = 16;
+constexpr int kTile = kThreads * kPerThread;     // 4096 keys
+constexpr int kWaves = kThreads / kWave;         // 4
+constexpr int kWaveKeys = kTile / kWaves;        // 1024
+
+__device__ __forceinline__ uint32_t digit_of(uint64_t key, int shift, uint32_t dmask) {
+  return uint32_t(key >> (32 + shift)) & dmask;
+}
+
+// Rank of this lane's key among the earlier keys of the same digit in this
+// wave's chunk; advances the wave's per-digit counters `wh`.
+__device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, int bits, uint32_t *wh) {
+  uint64_t match = __ballot(valid);
+  for (int b = 0; b < bits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t bal = __ballot(bit);
+    match &= bit ? bal : ~bal;
+  }
+  const uint64_t below = match & lanes_below();
+  uint32_t before = 0;
+  if (valid) before = wh[d];
+  if (valid && below == 0) wh[d] = before + uint32_t(__popcll(match));
+  return before + uint32_t(__popcll(below));
+}
+
+template <bool kSep>
+__device__ __forceinline__ uint64_t load_key(const RadixIn &in, int64_t i) {
+  if constexpr (kSep) {
+    return (uint64_t(in.hi[i]) << 32) | (uint64_t(in.lo[i]) & 0xFFFFFFFFull);
+  } else {
+    return in.packed[i];
+  }
+}
+
+template <bool kSep>
+__device__ __forceinline__ void store_key(const RadixOut &out, int64_t pos, uint64_t key) {
+  if constexpr (kSep) {
+    out.hi[pos] = int64_t(key >> 32);
+    out.lo[pos] = int64_t(key & 0xFFFFFFFFull);
+  } else {
+    out.packed[pos] = key;
+  }
+}
+
+// Per-tile digit counts -> counts[d * ntiles + tile].  With kCheck, also
+// validates the raw int64 input (range and, optionally, lo non-decreasing).
+template <bool kSep, bool kCheck>
+__global__ __launch_bounds__(kThreads) void k_radix_count(RadixIn in, int64_t m, int shift,
+                                                          int bits, int64_t ntiles,
+                                                          uint32_t *__restrict__ counts,
+                                                          int64_t check_n, int check_sorted,
+                                                          uint32_t *flag) {
+  __shared__ uint32_t wh[kWaves][256];
+  for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&wh[0][0])[i] = 0u;
+  __syncthreads();
+  const int w = threadIdx.x / kWave;
+  const int64_t base = int64_t(blockIdx.x) * kTile + int64_t(w) * kWaveKeys;
+  const uint32_t dmask = (1u << bits) - 1u;
+  uint32_t bad = 0;
+  for (int r = 0; r < kPerThread; ++r) {
+    const int64_t i = base + r * kWave + lane_id();
+    const bool valid = i < m;
+    uint64_t key = 0;
+    if (valid) {
+      if constexpr (kSep && kCheck) {
+        const int64_t hi = in.hi[i], lo = in.lo[i];
+        if (hi < 0 || hi >= check_n || lo < 0 || lo >= check_n) bad |= 1u;
+        if (check_sorted && i > 0 && in.lo[i - 1] > lo) bad |= 2u;
+        key = (uint64_t(hi) << 32) | (uint64_t(lo) & 0xFFFFFFFFull);
+      } else {
+        key = load_key<kSep>(in, i);
+      }
+    }
+    wave_rank(digit_of(key, shift, dmask), valid, bits, wh[w]);
+  }
+  if constexpr (kCheck) {
+    if (bad) atomicOr(flag, bad);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d <= int(dmask); d += kThreads)
+    counts[int64_t(d) * ntiles + blockIdx.x] = wh[0][d] + wh[1][d] + wh[2][d] + wh[3][d];
+}
+
+template <bool kSrcSep, bool kDstSep>
+__global__ __launch_bounds__(kThreads) void k_radix_scatter(RadixIn in, RadixOut out, int64_t m,
+                                                            int shift, int bits, int64_t ntiles,
+                                                            const uint32_t *__restrict__ offsets) {
+  __shared__ uint32_t wh[kWaves][256];
+  const uint32_t dmask = (1u << bits) - 1u;
+  for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&wh[0][0])[i] = 0u;
+  __syncthreads();
+  const int w = threadIdx.x / kWave;
+  const int64_t base = int64_t(blockIdx.x) * kTile + int64_t(w) * kWaveKeys;
+  uint64_t keys[kPerThread];
+  uint32_t rank[kPerThread];
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) {
+    const int64_t i = base + r * kWave + lane_id();
+    const bool valid = i < m;
+    keys[r] = valid ? load_key<kSrcSep>(in, i) : 0ull;
+    rank[r] = wave_rank(digit_of(keys[r], shift, dmask), valid, bits, wh[w]);
+  }
+  __syncthreads();
+  // wh[w][d] <- global offset of digit d for this tile + keys of digit d in
+  // the waves before w.
+  for (int d = threadIdx.x; d <= int(dmask); d += kThreads) {
+    uint32_t run = offsets[int64_t(d) * ntiles + blockIdx.x];
+#pragma unroll
+    for (int v = 0; v < kWaves; ++v) {
+      const uint32_t c = wh[v][d];
+      wh[v][d] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) {
+    const int64_t i = base + r * kWave + lane_id();
+    if (i < m) {
+      const uint32_t d = digit_of(keys[r], shift, dmask);
+      store_key<kDstSep>(out, int64_t(wh[w][d]) + rank[r], keys[r]);
+    }
+  }
+}
+
+struct Layout {
+  uint64_t *buf[2];
+  uint32_t *counts;
+  uint32_t *scan_ws;
+};
+
+Layout carve(void *ws, int64_t m) {
+  Carve c(ws);
+  Layout L{};
+  const int64_t ntiles = (m + kTile - 1) / kTile;
+  L.buf[0] = c.take<uint64_t>(size_t(m));
+  L.buf[1] = c.take<uint64_t>(size_t(m));
+  L.counts = c.take<uint32_t>(size_t(256 * ntiles));
+  L.scan_ws = c.take<uint32_t>(size_t(scan_ws_elems(256 * ntiles)));
+  return L;
+}
+
+size_t layout_bytes(int64_t m) {
+  Carve c(nullptr);
+  const int64_t ntiles = (m + kTile - 1) / kTile;
+  c.take<uint64_t>(size_t(m));
+  c.take<uint64_t>(size_t(m));
+  c.take<uint32_t>(size_t(256 * ntiles));
+  c.take<uint32_t>(size_t(scan_ws_elems(256 * ntiles)));
+  return c.bytes();
+}
+
+}  // namespace
+
+size_t radix_ws_bytes(int64_t m, int32_t /*key_bits*/) { return layout_bytes(m); }
+
+pp_status radix_sort(RadixIn in, RadixOut out, int64_t m, int32_t key_bits, void *ws,
+                     size_t ws_bytes, int64_t check_n, bool check_sorted_lo, uint32_t *flag,
+                     hipStream_t s, bool sync_after_first_pass) {
+  if (m <= 0) return PP_OK;
+  if (key_bits < 1 || key_bits > 31) return fail(PP_EINVAL, "radix key bits %d", key_bits);
+  if (ws_bytes < layout_bytes(m)) return fail(PP_EWORKSPACE, "radix workspace too small");
+  Layout L = carve(ws, m);
+  const int64_t ntiles = (m + kTile - 1) / kTile;
+  if (ntiles >= (int64_t(1) << 31)) return fail(PP_ERANGE, "too many tiles");
+  const int npass = (key_bits + 7) / 8;
+  const int base_bits = key_bits / npass, extra = key_bits % npass;
+  int shift = 0;
+  const bool check = check_n > 0;
+  for (int p = 0; p < npass; ++p) {
+    const int bits = base_bits + (p < extra ? 1 : 0);
+    const bool first = p == 0, last = p == npass - 1;
+    RadixIn src = first ? in : RadixIn{L.buf[(p - 1) & 1], nullptr, nullptr};
+    RadixOut dst = last ? out : RadixOut{L.buf[p & 1], nullptr, nullptr};
+    const bool src_sep = src.packed == nullptr;
+    const bool dst_sep = dst.packed == nullptr;
+    const dim3 grid = dim3(static_cast<unsigned>(ntiles)), block = dim3(kThreads);
+    if (src_sep) {
+      if (first && check)
+        hipLaunchKernelGGL((k_radix_count<true, true>), grid, block, 0, s, src, m, shift, bits,
+                           ntiles, L.counts, check_n, int(check_sorted_lo), flag);
+      else
+        hipLaunchKernelGGL((k_radix_count<true, false>), grid, block, 0, s, src, m, shift, bits,
+                           ntiles, L.counts, int64_t(0), 0, flag);
+    } else {
+      hipLaunchKernelGGL((k_radix_count<false, false>), grid, block, 0, s, src, m, shift, bits,
+                         ntiles, L.counts, int64_t(0), 0, flag);
+    }
+    PP_LAUNCHED("k_radix_count");
+    if (first && check && sync_after_first_pass) {
+      uint32_t h = 0;
+      PP_HIP(hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, s));
+      PP_HIP(hipStreamSynchronize(s));
+      if (h & 1u) return fail(PP_EINVAL, "input label outside [0, %lld)", (long long)check_n);
+      if (h & 2u) return fail(PP_EINVAL, "input not sorted by start vertex");
+    }
+    // Digit-major table: only the 2^bits rows this pass wrote are scanned.
+    pp_status st = exscan_u32(L.counts, L.counts, (int64_t(1) << bits) * ntiles, L.scan_ws, nullptr, s);
+    if (st != PP_OK) return st;
+    if (src_sep && dst_sep)
+      hipLaunchKernelGGL((k_radix_scatter<true, true>), grid, block, 0, s, src, dst, m, shift,
+                         bits, ntiles, L.counts);
+    else if (src_sep)
+      hipLaunchKernelGGL((k_radix_scatter<true, false>), grid, block, 0, s, src, dst, m, shift,
+                         bits, ntiles, L.counts);
+    else if (dst_sep)
+      hipLaunchKernelGGL((k_radix_scatter<false, true>), grid, block, 0, s, src, dst, m, shift,
+                         bits, ntiles, L.counts);
+    else
+      hipLaunchKernelGGL((k_radix_scatter<false, false>), grid, block, 0, s, src, dst, m, shift,
+                         bits, ntiles, L.counts);
+    PP_LAUNCHED("k_radix_scatter");
+    shift += bits;
+  }
+  return PP_OK;
+}
+
+}  // namespace pp

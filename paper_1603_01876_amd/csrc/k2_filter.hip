@@ -1,0 +1,304 @@
+// k2_filter.hip -- K2, the filter (Sec. IV.C): count matrix, in-degree,
+// supernode and leaf column removal, out-degree, row normalisation, written
+// out as CSR(A^T) for the pull-form PageRank of K3.
+//
+// The K1 output is ordered by u.  A stable radix sort of it by v gives the
+// lexicographic (v, u) order: equal (u,v) pairs are adjacent (their run
+// length is the count A(u,v)), each column v of A is a contiguous run (its
+// length is d_in[v]), and column removal becomes the removal of whole runs.
+// Every reduction is an integer one (counts, max, integer atomics), so the
+// result is bit-identical run to run and independent of scheduling:
+//   1. radix-sort (v<<32|u) by v; the first pass also checks the input
+//   2. vstart[w]  = first position of column w in the sorted list
+//   3. d_in[w]    = vstart[w+1] - vstart[w];  mx = max d_in (atomicMax)
+//   4. keep bitmap: d_in != mx and d_in != 1 (both on the same d_in)
+//   5. d_out[u]   = kept edges per u, on the u-ordered input: per-wave
+//                   segmented popcounts, one integer atomic per run
+//   6. compaction: per-tile counts of kept distinct pairs, scan, emit
+//                   col = u, val = count / d_out[u] (IEEE FP64 division,
+//                   FP32 stores the rounded quotient) and row_ptr.
+#include "pp_common.hpp"
+
+namespace pp {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kPerThread = 16;
+constexpr int kTile = kThreads * kPerThread;  // 4096 sorted entries per tile
+constexpr int kWaves = kThreads / kWave;
+constexpr int kWaveKeys = kTile / kWaves;
+
+__device__ __forceinline__ int32_t vof(uint64_t key) { return int32_t(key >> 32); }
+__device__ __forceinline__ int32_t uof(uint64_t key) { return int32_t(key & 0xFFFFFFFFull); }
+
+__device__ __forceinline__ bool kept(const uint64_t *keepw, int32_t w) {
+  return (keepw[w >> 6] >> (w & 63)) & 1ull;
+}
+
+// vstart[w] = first sorted position with v >= w, for w = 0..n.
+__global__ __launch_bounds__(256) void k_vstart(const uint64_t *__restrict__ P, int64_t m,
+                                                int32_t n, int32_t *__restrict__ vstart) {
+  const int64_t stride = int64_t(gridDim.x) * 256;
+  for (int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x; p < m; p += stride) {
+    const int32_t v = vof(P[p]);
+    const int32_t vp = p > 0 ? vof(P[p - 1]) : -1;
+    for (int32_t w = vp + 1; w <= v; ++w) vstart[w] = int32_t(p);
+    if (p == m - 1)
+      for (int32_t w = v + 1; w <= n; ++w) vstart[w] = int32_t(m);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_din(const int32_t *__restrict__ vstart, int32_t n,
+                                             int32_t *__restrict__ d_in, int32_t *mx) {
+  int32_t best = 0;
+  const int64_t stride = int64_t(gridDim.x) * 256;
+  for (int64_t w = int64_t(blockIdx.x) * 256 + threadIdx.x; w < n; w += stride) {
+    const int32_t d = vstart[w + 1] - vstart[w];
+    d_in[w] = d;
+    best = d > best ? d : best;
+  }
+  best = wave_max(best);
+  if (lane_id() == 0) atomicMax(mx, best);
+}
+
+// One 64-bit word per wave: bit (w mod 64) set iff column w survives.
+__global__ __launch_bounds__(256) void k_keepbits(const int32_t *__restrict__ d_in, int32_t n,
+                                                  const int32_t *mx, uint64_t *__restrict__ keepw) {
+  const int32_t top = *mx;
+  const int64_t stride = int64_t(gridDim.x) * 256;
+  const int64_t nw = (int64_t(n) + 63) / 64 * 64;
+  for (int64_t w = int64_t(blockIdx.x) * 256 + threadIdx.x; w < nw; w += stride) {
+    bool keep = false;
+    if (w < n) {
+      const int32_t d = d_in[w];
+      keep = d != top && d != 1;
+    }
+    const uint64_t bits = __ballot(keep);
+    if (lane_id() == 0) keepw[w >> 6] = bits;
+  }
+}
+
+// d_out[u] += number of kept edges of u, over the u-ordered input.  A wave
+// covers 64 consecutive edges; each run of equal u inside it is summed with
+// one popcount and one atomic add by the run's first lane.
+__global__ __launch_bounds__(256) void k_dout(const int64_t *__restrict__ u,
+                                              const int64_t *__restrict__ v, int64_t m,
+                                              const uint64_t *__restrict__ keepw,
+                                              int32_t *__restrict__ d_out) {
+  const int64_t stride = int64_t(gridDim.x) * 256;
+  const int lane = lane_id();
+  for (int64_t p0 = int64_t(blockIdx.x) * 256 + (threadIdx.x & ~63); p0 < m; p0 += stride) {
+    const int64_t p = p0 + lane;
+    const bool valid = p < m;
+    const int32_t uu = valid ? int32_t(u[p]) : -1;
+    const bool f = valid && kept(keepw, int32_t(v[p]));
+    const int32_t up = __shfl_up(uu, 1, kWave);
+    const bool head = valid && (lane == 0 || up != uu);
+    const uint64_t heads = __ballot(head);
+    const uint64_t flags = __ballot(f);
+    if (head) {
+      const uint64_t after = heads & ~((2ull << lane) - 1ull);   // heads above this lane
+      const uint64_t upto = after ? (after & (~after + 1ull)) - 1ull : ~0ull;
+      const uint64_t seg = upto & ~((1ull << lane) - 1ull);
+      const int cnt = __popcll(flags & seg);
+      if (cnt) atomicAdd(&d_out[uu], cnt);
+    }
+  }
+}
+
+// Per tile: number of kept distinct (v,u) pairs.
+__global__ __launch_bounds__(kThreads) void k_compact_count(const uint64_t *__restrict__ P,
+                                                            int64_t m,
+                                                            const uint64_t *__restrict__ keepw,
+                                                            uint32_t *__restrict__ tile_cnt) {
+  __shared__ uint32_t sh[4];
+  const int w = threadIdx.x / kWave;
+  const int64_t base = int64_t(blockIdx.x) * kTile + int64_t(w) * kWaveKeys;
+  uint32_t c = 0;
+  for (int r = 0; r < kPerThread; ++r) {
+    const int64_t p = base + r * kWave + lane_id();
+    if (p < m) {
+      const uint64_t key = P[p];
+      const bool distinct = p == 0 || P[p - 1] != key;
+      c += (distinct && kept(keepw, vof(key))) ? 1u : 0u;
+    }
+  }
+  const uint32_t tot = block_sum256(c, sh);
+  if (threadIdx.x == 0) tile_cnt[blockIdx.x] = tot;
+}
+
+template <typename V>
+__global__ __launch_bounds__(kThreads) void k_compact_emit(
+    const uint64_t *__restrict__ P, int64_t m, int32_t n, const uint64_t *__restrict__ keepw,
+    const int32_t *__restrict__ d_out, const uint32_t *__restrict__ tile_off,
+    int32_t *__restrict__ row_ptr, int32_t *__restrict__ col, V *__restrict__ val) {
+  __shared__ uint32_t wave_tot[kWaves];
+  const int w = threadIdx.x / kWave;
+  const int lane = lane_id();
+  const int64_t base = int64_t(blockIdx.x) * kTile + int64_t(w) * kWaveKeys;
+  uint64_t keys[kPerThread];
+  uint64_t ball[kPerThread];
+  uint32_t run = 0;
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) {
+    const int64_t p = base + r * kWave + lane;
+    bool f = false;
+    uint64_t key = 0;
+    if (p < m) {
+      key = P[p];
+      const bool distinct = p == 0 || P[p - 1] != key;
+      f = distinct && kept(keepw, vof(key));
+    }
+    keys[r] = key;
+    ball[r] = __ballot(f);
+    run += uint32_t(__popcll(ball[r]));
+  }
+  if (lane == 0) wave_tot[w] = run;
+  __syncthreads();
+  uint32_t before = tile_off[blockIdx.x];
+  for (int v = 0; v < w; ++v) before += wave_tot[v];
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) {
+    const int64_t p = base + r * kWave + lane;
+    if (p < m) {
+      const uint64_t key = keys[r];
+      const bool f = (ball[r] >> lane) & 1ull;
+      const uint32_t excl = before + uint32_t(__popcll(ball[r] & lanes_below()));
+      const int32_t v = vof(key);
+      if (f) {
+        const int32_t u = uof(key);
+        int64_t q = p + 1;
+        while (q < m && P[q] == key) ++q;
+        const double quot = double(q - p) / double(d_out[u]);
+        col[excl] = u;
+        val[excl] = V(quot);
+      }
+      // Row pointers of every column that starts here (empty ones too).
+      const int32_t vp = p > 0 ? vof(P[p - 1]) : -1;
+      for (int32_t j = vp + 1; j <= v; ++j) row_ptr[j] = int32_t(excl);
+      if (p == m - 1) {
+        const int32_t z = int32_t(excl + (f ? 1u : 0u));
+        for (int32_t j = v + 1; j <= n; ++j) row_ptr[j] = z;
+      }
+    }
+    before += uint32_t(__popcll(ball[r]));
+  }
+}
+
+struct Layout {
+  uint64_t *P;
+  void *radix_ws;
+  size_t radix_bytes;
+  int32_t *vstart, *d_in, *d_out;
+  uint64_t *keepw;
+  uint32_t *tile_cnt, *scan_ws;
+  int32_t *mx;
+  int64_t *z;
+  uint32_t *flag;
+};
+
+Layout carve(void *ws, int64_t n, int64_t m) {
+  Carve c(ws);
+  Layout L{};
+  const int64_t ntiles = (m + kTile - 1) / kTile;
+  L.P = c.take<uint64_t>(size_t(m));
+  L.radix_bytes = radix_ws_bytes(m, 31);
+  L.radix_ws = c.take<uint8_t>(L.radix_bytes);
+  L.vstart = c.take<int32_t>(size_t(n + 1));
+  L.d_in = c.take<int32_t>(size_t(n));
+  L.d_out = c.take<int32_t>(size_t(n));
+  L.keepw = c.take<uint64_t>(size_t((n + 63) / 64));
+  L.tile_cnt = c.take<uint32_t>(size_t(ntiles + 1));
+  L.scan_ws = c.take<uint32_t>(size_t(scan_ws_elems(ntiles + 1)));
+  L.mx = c.take<int32_t>(1);
+  L.z = c.take<int64_t>(1);
+  L.flag = c.take<uint32_t>(1);
+  return L;
+}
+
+}  // namespace
+
+size_t filter_ws_bytes(int64_t n, int64_t m) {
+  Carve c(nullptr);
+  const int64_t ntiles = (m + kTile - 1) / kTile;
+  c.take<uint64_t>(size_t(m));
+  c.take<uint8_t>(radix_ws_bytes(m, 31));
+  c.take<int32_t>(size_t(n + 1));
+  c.take<int32_t>(size_t(n));
+  c.take<int32_t>(size_t(n));
+  c.take<uint64_t>(size_t((n + 63) / 64));
+  c.take<uint32_t>(size_t(ntiles + 1));
+  c.take<uint32_t>(size_t(scan_ws_elems(ntiles + 1)));
+  c.take<int32_t>(1);
+  c.take<int64_t>(1);
+  c.take<uint32_t>(1);
+  return c.bytes();
+}
+
+pp_status launch_filter(int32_t scale, int64_t m, const int64_t *u, const int64_t *v,
+                        pp_dtype dt, pp_csr *AT, int32_t *d_in, int32_t *d_out, void *ws,
+                        size_t ws_bytes, hipStream_t s) {
+  const int64_t n = int64_t(1) << scale;
+  if (ws_bytes < filter_ws_bytes(n, m)) return fail(PP_EWORKSPACE, "filter workspace too small");
+  Layout L = carve(ws, n, m);
+  int32_t *din = d_in ? d_in : L.d_in;
+  int32_t *dout = d_out ? d_out : L.d_out;
+  pp_status st;
+
+  if (m == 0) {
+    if ((st = fill_i32(AT->row_ptr, n + 1, 0, s)) != PP_OK) return st;
+    if ((st = fill_i32(din, n, 0, s)) != PP_OK) return st;
+    if ((st = fill_i32(dout, n, 0, s)) != PP_OK) return st;
+    PP_HIP(hipStreamSynchronize(s));
+    AT->nnz = 0;
+    return PP_OK;
+  }
+
+  // 1. sort by v (stable on the u-ordered input), validating the input.
+  if ((st = fill_i32(reinterpret_cast<int32_t *>(L.flag), 1, 0, s)) != PP_OK) return st;
+  st = radix_sort(RadixIn{nullptr, v, u}, RadixOut{L.P, nullptr, nullptr}, m, scale, L.radix_ws,
+                  L.radix_bytes, n, true, L.flag, s, true);
+  if (st != PP_OK) return st;
+
+  // 2-4. column starts, in-degrees, maximum, surviving columns.
+  const int n32 = int32_t(n);
+  hipLaunchKernelGGL(k_vstart, dim3(grid_for(m, 256, 256 * 32)), dim3(256), 0, s, L.P, m, n32,
+                     L.vstart);
+  if ((st = fill_i32(L.mx, 1, 0, s)) != PP_OK) return st;
+  hipLaunchKernelGGL(k_din, dim3(grid_for(n, 256, 256 * 32)), dim3(256), 0, s, L.vstart, n32, din,
+                     L.mx);
+  hipLaunchKernelGGL(k_keepbits, dim3(grid_for((n + 63) / 64 * 64, 256, 256 * 32)), dim3(256), 0,
+                     s, din, n32, L.mx, L.keepw);
+  PP_LAUNCHED("k_vstart/k_din/k_keepbits");
+
+  // 5. out-degrees from the u-ordered input.
+  if ((st = fill_i32(dout, n, 0, s)) != PP_OK) return st;
+  hipLaunchKernelGGL(k_dout, dim3(grid_for(m, 256, 256 * 32)), dim3(256), 0, s, u, v, m, L.keepw,
+                     dout);
+  PP_LAUNCHED("k_dout");
+
+  // 6. compaction into CSR(A^T).
+  const int64_t ntiles = (m + kTile - 1) / kTile;
+  hipLaunchKernelGGL(k_compact_count, dim3(unsigned(ntiles)), dim3(kThreads), 0, s, L.P, m,
+                     L.keepw, L.tile_cnt);
+  PP_LAUNCHED("k_compact_count");
+  if ((st = exscan_u32(L.tile_cnt, L.tile_cnt, ntiles, L.scan_ws, L.z, s)) != PP_OK) return st;
+  if (dt == PP_F64)
+    hipLaunchKernelGGL(k_compact_emit<double>, dim3(unsigned(ntiles)), dim3(kThreads), 0, s, L.P,
+                       m, n32, L.keepw, dout, L.tile_cnt, AT->row_ptr, AT->col,
+                       static_cast<double *>(AT->val));
+  else
+    hipLaunchKernelGGL(k_compact_emit<float>, dim3(unsigned(ntiles)), dim3(kThreads), 0, s, L.P,
+                       m, n32, L.keepw, dout, L.tile_cnt, AT->row_ptr, AT->col,
+                       static_cast<float *>(AT->val));
+  PP_LAUNCHED("k_compact_emit");
+
+  int64_t z = 0;
+  PP_HIP(hipMemcpyAsync(&z, L.z, sizeof(z), hipMemcpyDeviceToHost, s));
+  PP_HIP(hipStreamSynchronize(s));
+  AT->nnz = z;
+  return PP_OK;
+}
+
+}  // namespace pp

@@ -1,0 +1,517 @@
+// k3_pagerank.hip -- K3, PageRank (Sec. IV.D and the Appendix):
+//   r_{k+1,j} = c * sum_i r_{k,i} A(i,j) + ((1-c)/N) * sum(r_k),  k = 0..iters-1,
+// as a pull-form sparse matrix-vector product on CSR(A^T), plus the
+// initial vector r = rand(1,N) ./ norm(r,1).
+//
+// Load balance: after the filter most rows of A^T are empty and the rest
+// follow a power law, so rows are not a unit of work.  The SpMV splits the
+// merged sequence of (row ends, non-zeros) into equal pieces (merge-path
+// decomposition, Merrill & Garland, SC'16): a workgroup of 256 threads owns
+// 256*IPT consecutive items, stages its row ends and its products r[col]*val
+// in LDS with coalesced loads, and each thread consumes IPT items of its
+// own.  Rows cut by a thread boundary are completed inside the workgroup;
+// rows cut by a workgroup boundary leave a carry that a second, small kernel
+// adds in workgroup order.  Nothing is summed with floating-point atomics,
+// so every result is reproducible bit for bit.
+//
+// Precision forms: PP_F64 accumulates in FP64.  PP_F32 keeps values, ranks
+// and products in FP32 and accumulates each row with a compensated (TwoSum)
+// pair; partial pairs are merged with TwoSum too.  In both forms sum(r) is
+// reduced in FP64 in a fixed order and the teleport scalar (1-c)/N * sum(r)
+// is FP64.  The partition, the carries' row ids and the fix-up flags depend
+// only on the matrix, so they are computed once per call.
+#include <vector>
+
+#include "pp_common.hpp"
+
+#pragma clang fp contract(off)
+
+namespace pp {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kIpt = 8;                      // merge items per thread
+constexpr int kItems = kThreads * kIpt;      // items per workgroup
+constexpr int kFinishPer = kThreads * 8;     // spmv workgroups per finish workgroup
+constexpr int64_t kSumChunk = kThreads * 64; // entries of r per workgroup of sum(r_0)
+
+// ------------------------------------------------------------ accumulators
+struct AccD {
+  double s;
+  __device__ __forceinline__ void add(double x) { s += x; }
+  __device__ __forceinline__ double value() const { return s; }
+};
+__device__ __forceinline__ AccD merge(AccD a, AccD b) { return AccD{a.s + b.s}; }
+
+// Compensated FP32 sum: s + e approximates the exact sum; every addition is
+// Knuth's TwoSum, whose rounding error is carried in e.
+struct AccF {
+  float s, e;
+  __device__ __forceinline__ void add(float x) {
+    const float t = s + x;
+    const float z = t - s;
+    const float err = (s - (t - z)) + (x - z);
+    s = t;
+    e += err;
+  }
+  __device__ __forceinline__ float value() const { return s + e; }
+};
+__device__ __forceinline__ AccF merge(AccF a, AccF b) {
+  AccF r = a;
+  r.add(b.s);
+  r.e += b.e;
+  return r;
+}
+
+template <typename V>
+struct Form;
+template <>
+struct Form<double> {
+  using Acc = AccD;
+  __device__ static double finish(AccD a, double c, double t) { return c * a.value() + t; }
+};
+template <>
+struct Form<float> {
+  using Acc = AccF;
+  __device__ static float finish(AccF a, double c, double t) {
+    return float(c * double(a.value()) + t);
+  }
+};
+
+// ------------------------------------------------------------- partition
+// coord[b] = (rows ended, non-zeros consumed) after the first b*kItems items
+// of the merge of the row-end list rp[1..n] with the non-zero indices.
+__global__ __launch_bounds__(256) void k_partition(const int32_t *__restrict__ rp, int32_t n,
+                                                   int32_t nnz, int32_t nb, int2 *coord) {
+  const int64_t total = int64_t(n) + nnz;
+  for (int32_t b = blockIdx.x * 256 + threadIdx.x; b <= nb; b += gridDim.x * 256) {
+    const int64_t diag64 = int64_t(b) * kItems < total ? int64_t(b) * kItems : total;
+    const int32_t diag = int32_t(diag64);
+    int32_t lo = diag - nnz > 0 ? diag - nnz : 0;
+    int32_t hi = diag < n ? diag : n;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (rp[mid + 1] <= diag - mid - 1)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    coord[b] = make_int2(lo, diag - lo);
+  }
+}
+
+// Static per-block facts: the row left open at the block's end (-1 if none)
+// and whether the block completes a row that began in an earlier block.
+__global__ __launch_bounds__(256) void k_block_flags(const int32_t *__restrict__ rp, int32_t n,
+                                                     int32_t nb, const int2 *__restrict__ coord,
+                                                     int32_t *carry_row, uint8_t *closes) {
+  for (int32_t b = blockIdx.x * 256 + threadIdx.x; b < nb; b += gridDim.x * 256) {
+    const int2 c0 = coord[b], c1 = coord[b + 1];
+    carry_row[b] = c1.x < n ? c1.x : -1;
+    closes[b] = (c0.x < n && rp[c0.x] < c0.y && c1.x > c0.x) ? 1 : 0;
+  }
+}
+
+// ------------------------------------------------------------------ SpMV
+template <typename V>
+__global__ __launch_bounds__(kThreads) void k_spmv(
+    const int32_t *__restrict__ rp, const int32_t *__restrict__ col, const V *__restrict__ val,
+    const V *__restrict__ x, V *__restrict__ y, int32_t n, const int2 *__restrict__ coord,
+    double c, const double *__restrict__ tele, double *__restrict__ blk_ysum,
+    typename Form<V>::Acc *__restrict__ blk_carry, typename Form<V>::Acc *__restrict__ blk_head) {
+  using Acc = typename Form<V>::Acc;
+  __shared__ int32_t s_end[kItems];
+  __shared__ V s_prod[kItems];
+  __shared__ Acc s_carry[kThreads];
+  __shared__ int32_t s_row[kThreads];
+  __shared__ double s_red[4];
+
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int2 c0 = coord[b], c1 = coord[b + 1];
+  const int32_t i0 = c0.x, j0 = c0.y;
+  const int32_t na = c1.x - c0.x, nz = c1.y - c0.y;
+
+  // Stage: local row ends and products, coalesced.  Loads are issued for
+  // all of a thread's slots before any is consumed.
+  {
+    int32_t cc[kIpt];
+    V vv[kIpt];
+#pragma unroll
+    for (int r = 0; r < kIpt; ++r) {
+      const int k = r * kThreads + tid;
+      cc[r] = k < nz ? __builtin_nontemporal_load(col + j0 + k) : 0;
+      vv[r] = k < nz ? __builtin_nontemporal_load(val + j0 + k) : V(0);
+    }
+#pragma unroll
+    for (int r = 0; r < kIpt; ++r) {
+      const int k = r * kThreads + tid;
+      if (k < nz) s_prod[k] = x[cc[r]] * vv[r];
+      if (k < na) s_end[k] = rp[i0 + 1 + k] - j0;
+    }
+  }
+  const bool mid_row = i0 < n && rp[i0] < j0;
+  const double tk = *tele;
+  __syncthreads();
+
+  // This thread's items [d, dend) of the workgroup's merge sequence.
+  const int32_t tot = na + nz;
+  int32_t d = tid * kIpt < tot ? tid * kIpt : tot;
+  const int32_t dend = d + kIpt < tot ? d + kIpt : tot;
+  int32_t lo = d - nz > 0 ? d - nz : 0, hi = d < na ? d : na;
+  while (lo < hi) {
+    const int32_t m = (lo + hi) >> 1;
+    if (s_end[m] <= d - m - 1)
+      lo = m + 1;
+    else
+      hi = m;
+  }
+  int32_t ti = lo, tj = d - lo;
+
+  Acc acc{}, first{};
+  int32_t first_row = -1;
+  double ysum = 0.0;
+  for (; d < dend; ++d) {
+    if (ti < na && s_end[ti] <= tj) {
+      if (first_row < 0) {
+        first_row = ti;
+        first = acc;
+      } else {
+        const V yv = Form<V>::finish(acc, c, tk);
+        y[i0 + ti] = yv;
+        ysum += double(yv);
+      }
+      acc = Acc{};
+      ++ti;
+    } else {
+      acc.add(s_prod[tj]);
+      ++tj;
+    }
+  }
+  s_carry[tid] = acc;
+  s_row[tid] = i0 + ti;
+  __syncthreads();
+
+  if (first_row >= 0) {
+    // Complete the first row this thread ends with the partials of the
+    // threads before it that left the same row open, in thread order.
+    const int32_t R = i0 + first_row;
+    int t = tid - 1;
+    while (t >= 0 && s_row[t] == R) --t;
+    Acc sum{};
+    for (int q = t + 1; q < tid; ++q) sum = merge(sum, s_carry[q]);
+    sum = merge(sum, first);
+    if (t < 0 && mid_row && R == i0) {
+      blk_head[b] = sum;  // row began in an earlier workgroup: fixed up later
+    } else {
+      const V yv = Form<V>::finish(sum, c, tk);
+      y[R] = yv;
+      ysum += double(yv);
+    }
+  }
+  if (tid == kThreads - 1) {
+    // Partial of the row left open at the end of this workgroup.
+    const int32_t R = c1.x;
+    Acc sum{};
+    if (R < n) {
+      int t = kThreads - 1;
+      while (t >= 0 && s_row[t] == R) --t;
+      for (int q = t + 1; q < kThreads; ++q) sum = merge(sum, s_carry[q]);
+    }
+    blk_carry[b] = sum;
+  }
+  const double bs = block_sum256(ysum, s_red);
+  if (tid == 0) blk_ysum[b] = bs;
+}
+
+// Completes rows that span workgroups, then reduces sum(y) in a fixed
+// order: per finish-workgroup partials, and the last workgroup to arrive
+// adds those partials, stores sum(y) and the next teleport scalar.
+template <typename V>
+__global__ __launch_bounds__(kThreads) void k_finish(
+    V *__restrict__ y, int32_t nb, const int2 *__restrict__ coord,
+    const uint8_t *__restrict__ closes, const int32_t *__restrict__ carry_row,
+    const typename Form<V>::Acc *__restrict__ blk_carry,
+    const typename Form<V>::Acc *__restrict__ blk_head, const double *__restrict__ blk_ysum,
+    double c, const double *__restrict__ tele_in, double *part, uint32_t *counter, double w,
+    double *sum_out, double *tele_out) {
+  using Acc = typename Form<V>::Acc;
+  __shared__ double sh[4];
+  __shared__ bool is_last;
+  const int g = blockIdx.x, tid = threadIdx.x;
+  const double tk = *tele_in;
+  const int64_t lo = int64_t(g) * kFinishPer;
+  const int64_t hi = lo + kFinishPer < nb ? lo + kFinishPer : nb;
+  double acc = 0.0;
+  for (int64_t b = lo + tid; b < hi; b += kThreads) {
+    double v = blk_ysum[b];
+    if (closes[b]) {
+      const int32_t R = coord[b].x;
+      int64_t q = b - 1;
+      while (q >= 0 && carry_row[q] == R) --q;
+      Acc sum{};
+      for (int64_t k = q + 1; k < b; ++k) sum = merge(sum, blk_carry[k]);
+      sum = merge(sum, blk_head[b]);
+      const V yv = Form<V>::finish(sum, c, tk);
+      y[R] = yv;
+      v += double(yv);
+    }
+    acc += v;
+  }
+  const double tot = block_sum256(acc, sh);
+  if (tid == 0) {
+    part[g] = tot;
+    __threadfence();
+    is_last = atomicAdd(counter, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (is_last) {
+    __threadfence();
+    double a = 0.0;
+    for (int k = tid; k < int(gridDim.x); k += kThreads) a += load_acquire(part + k);
+    const double s = block_sum256(a, sh);
+    if (tid == 0) {
+      if (sum_out) *sum_out = s;
+      *tele_out = w * s;
+      *counter = 0u;
+    }
+  }
+}
+
+// sum(r_0) with the same two-level fixed-order reduction.
+template <typename V>
+__global__ __launch_bounds__(kThreads) void k_sum0(const V *__restrict__ r, int64_t n,
+                                                   int64_t chunk, double *part, uint32_t *counter,
+                                                   double w, double *sum_out, double *tele_out) {
+  __shared__ double sh[4];
+  __shared__ bool is_last;
+  const int g = blockIdx.x, tid = threadIdx.x;
+  const int64_t lo = int64_t(g) * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  double acc = 0.0;
+  for (int64_t i = lo + tid; i < hi; i += kThreads) acc += double(r[i]);
+  const double tot = block_sum256(acc, sh);
+  if (tid == 0) {
+    part[g] = tot;
+    __threadfence();
+    is_last = atomicAdd(counter, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (is_last) {
+    __threadfence();
+    double a = 0.0;
+    for (int k = tid; k < int(gridDim.x); k += kThreads) a += load_acquire(part + k);
+    const double s = block_sum256(a, sh);
+    if (tid == 0) {
+      if (sum_out) *sum_out = s;
+      *tele_out = w * s;
+      *counter = 0u;
+    }
+  }
+}
+
+// ------------------------------------------------------------ initial r
+__global__ __launch_bounds__(256) void k_init_sum(int64_t n, int32_t nrhs, uint32_t k0,
+                                                  uint32_t k1, unsigned long long *ksum) {
+  const int32_t j = blockIdx.y;
+  unsigned long long acc = 0;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    const U4 w = philox10(U4{uint32_t(i), uint32_t(j), 0u, 2u}, k0, k1);
+    acc += w.x >> 8;
+  }
+  acc = wave_sum(acc);
+  if (lane_id() == 0 && acc) atomicAdd(ksum + j, acc);
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_init_write(int64_t n, int32_t nrhs, uint32_t k0,
+                                                    uint32_t k1,
+                                                    const unsigned long long *__restrict__ ksum,
+                                                    V *__restrict__ r) {
+  const int32_t j = blockIdx.y;
+  const unsigned long long K = ksum[j];
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    const U4 w = philox10(U4{uint32_t(i), uint32_t(j), 0u, 2u}, k0, k1);
+    const double q = K ? double(w.x >> 8) / double(K) : 1.0 / double(n);
+    r[i * nrhs + j] = V(q);
+  }
+}
+
+// Optional event pairs around each SpMV launch (benchmark instrumentation).
+struct Timing {
+  bool on = false;
+  int used = 0;
+  std::vector<hipEvent_t> start, stop;
+};
+Timing g_timing;
+constexpr int kMaxTimed = 256;
+
+pp_status timed_begin(hipStream_t s) {
+  if (!g_timing.on || g_timing.used >= kMaxTimed) return PP_OK;
+  PP_HIP(hipEventRecord(g_timing.start[g_timing.used], s));
+  return PP_OK;
+}
+pp_status timed_end(hipStream_t s) {
+  if (!g_timing.on || g_timing.used >= kMaxTimed) return PP_OK;
+  PP_HIP(hipEventRecord(g_timing.stop[g_timing.used], s));
+  ++g_timing.used;
+  return PP_OK;
+}
+
+template <typename V>
+struct Layout {
+  V *y;
+  int2 *coord;
+  uint8_t *closes;
+  int32_t *carry_row;
+  typename Form<V>::Acc *blk_carry, *blk_head;
+  double *blk_ysum, *part, *tele;
+  uint32_t *counter;
+  unsigned long long *ksum;
+};
+
+template <typename V>
+Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs) {
+  using Acc = typename Form<V>::Acc;
+  Carve c(ws);
+  Layout<V> L{};
+  const int64_t nb = (n + nnz_cap + kItems - 1) / kItems + 1;
+  const int64_t G = (nb + kFinishPer - 1) / kFinishPer + 1;
+  const int64_t G0 = (n + kSumChunk - 1) / kSumChunk + 1;
+  L.ksum = c.take<unsigned long long>(64);
+  L.counter = c.take<uint32_t>(4);
+  L.tele = c.take<double>(2 * 64);
+  L.y = c.take<V>(size_t(n) * nrhs);
+  L.coord = c.take<int2>(size_t(nb + 1));
+  L.closes = c.take<uint8_t>(size_t(nb));
+  L.carry_row = c.take<int32_t>(size_t(nb));
+  L.blk_carry = c.take<Acc>(size_t(nb));
+  L.blk_head = c.take<Acc>(size_t(nb));
+  L.blk_ysum = c.take<double>(size_t(nb));
+  L.part = c.take<double>(size_t(G > G0 ? G : G0));
+  return L;
+}
+
+template <typename V>
+size_t ws_bytes_t(int64_t n, int64_t nnz_cap, int32_t nrhs) {
+  Carve c(nullptr);
+  using Acc = typename Form<V>::Acc;
+  const int64_t nb = (n + nnz_cap + kItems - 1) / kItems + 1;
+  const int64_t G = (nb + kFinishPer - 1) / kFinishPer + 1;
+  const int64_t G0 = (n + kSumChunk - 1) / kSumChunk + 1;
+  c.take<unsigned long long>(64);
+  c.take<uint32_t>(4);
+  c.take<double>(2 * 64);
+  c.take<V>(size_t(n) * nrhs);
+  c.take<int2>(size_t(nb + 1));
+  c.take<uint8_t>(size_t(nb));
+  c.take<int32_t>(size_t(nb));
+  c.take<Acc>(size_t(nb));
+  c.take<Acc>(size_t(nb));
+  c.take<double>(size_t(nb));
+  c.take<double>(size_t(G > G0 ? G : G0));
+  return c.bytes();
+}
+
+template <typename V>
+pp_status run_pagerank(const pp_csr &AT, int32_t iters, double c, V *r, double *sums, void *ws,
+                       size_t ws_bytes, hipStream_t s) {
+  const int64_t n = AT.n, nnz = AT.nnz;
+  if (ws_bytes < ws_bytes_t<V>(n, nnz, 1)) return fail(PP_EWORKSPACE, "pagerank workspace too small");
+  Layout<V> L = carve<V>(ws, n, nnz, 1);
+  const int32_t nb = int32_t((n + nnz + kItems - 1) / kItems);
+  const int32_t G = (nb + kFinishPer - 1) / kFinishPer;
+  const double w = (1.0 - c) / double(n);
+  pp_status st;
+  if ((st = fill_i32(reinterpret_cast<int32_t *>(L.counter), 4, 0, s)) != PP_OK) return st;
+
+  hipLaunchKernelGGL(k_partition, dim3(grid_for(int64_t(nb) + 1, 256, 4096)), dim3(256), 0, s,
+                     AT.row_ptr, int32_t(n), int32_t(nnz), nb, L.coord);
+  hipLaunchKernelGGL(k_block_flags, dim3(grid_for(nb, 256, 4096)), dim3(256), 0, s, AT.row_ptr,
+                     int32_t(n), nb, L.coord, L.carry_row, L.closes);
+  PP_LAUNCHED("k_partition/k_block_flags");
+
+  const int G0 = int((n + kSumChunk - 1) / kSumChunk);
+  hipLaunchKernelGGL(k_sum0<V>, dim3(G0), dim3(kThreads), 0, s, r, n, kSumChunk, L.part, L.counter,
+                     w, sums, L.tele);
+  PP_LAUNCHED("k_sum0");
+
+  const V *val = static_cast<const V *>(AT.val);
+  g_timing.used = 0;
+  for (int32_t k = 0; k < iters; ++k) {
+    const V *x = (k & 1) ? L.y : r;
+    V *yv = (k & 1) ? r : L.y;
+    if ((st = timed_begin(s)) != PP_OK) return st;
+    hipLaunchKernelGGL(k_spmv<V>, dim3(nb), dim3(kThreads), 0, s, AT.row_ptr, AT.col, val, x, yv,
+                       int32_t(n), L.coord, c, L.tele + (k & 1), L.blk_ysum, L.blk_carry,
+                       L.blk_head);
+    if ((st = timed_end(s)) != PP_OK) return st;
+    hipLaunchKernelGGL(k_finish<V>, dim3(G), dim3(kThreads), 0, s, yv, nb, L.coord, L.closes,
+                       L.carry_row, L.blk_carry, L.blk_head, L.blk_ysum, c, L.tele + (k & 1),
+                       L.part, L.counter, w, sums ? sums + k + 1 : nullptr,
+                       L.tele + ((k + 1) & 1));
+    PP_LAUNCHED("k_spmv/k_finish");
+  }
+  if (iters & 1) return copy_bytes(r, L.y, size_t(n) * sizeof(V), s);
+  return PP_OK;
+}
+
+}  // namespace
+
+pp_status set_kernel_timing(bool enable) {
+  if (enable && g_timing.start.empty()) {
+    g_timing.start.resize(kMaxTimed);
+    g_timing.stop.resize(kMaxTimed);
+    for (int i = 0; i < kMaxTimed; ++i) {
+      PP_HIP(hipEventCreate(&g_timing.start[i]));
+      PP_HIP(hipEventCreate(&g_timing.stop[i]));
+    }
+  }
+  g_timing.on = enable;
+  g_timing.used = 0;
+  return PP_OK;
+}
+
+int32_t kernel_times(float *ms, int32_t cap) {
+  const int n = g_timing.used < cap ? g_timing.used : cap;
+  if (n <= 0) return 0;
+  if (hipEventSynchronize(g_timing.stop[g_timing.used - 1]) != hipSuccess) return -1;
+  for (int i = 0; i < n; ++i)
+    if (hipEventElapsedTime(ms + i, g_timing.start[i], g_timing.stop[i]) != hipSuccess) return -1;
+  return n;
+}
+
+size_t pagerank_ws_bytes(int64_t n, int64_t nnz_cap, pp_dtype dt, int32_t nrhs) {
+  return dt == PP_F64 ? ws_bytes_t<double>(n, nnz_cap, nrhs) : ws_bytes_t<float>(n, nnz_cap, nrhs);
+}
+
+pp_status launch_init_r(int64_t n, int32_t nrhs, uint64_t seed, pp_dtype dt, void *r, void *ws,
+                        size_t ws_bytes, hipStream_t s) {
+  if (ws_bytes < 64 * sizeof(unsigned long long) + 256)
+    return fail(PP_EWORKSPACE, "init_r workspace too small");
+  Carve cv(ws);
+  unsigned long long *ksum = cv.take<unsigned long long>(64);
+  pp_status st = fill_u64(reinterpret_cast<uint64_t *>(ksum), nrhs, 0ull, s);
+  if (st != PP_OK) return st;
+  const uint32_t k0 = uint32_t(seed), k1 = uint32_t(seed >> 32);
+  const dim3 grid(grid_for(n, 256, 2048), unsigned(nrhs));
+  hipLaunchKernelGGL(k_init_sum, grid, dim3(256), 0, s, n, nrhs, k0, k1, ksum);
+  if (dt == PP_F64)
+    hipLaunchKernelGGL(k_init_write<double>, grid, dim3(256), 0, s, n, nrhs, k0, k1, ksum,
+                       static_cast<double *>(r));
+  else
+    hipLaunchKernelGGL(k_init_write<float>, grid, dim3(256), 0, s, n, nrhs, k0, k1, ksum,
+                       static_cast<float *>(r));
+  PP_LAUNCHED("k_init_sum/k_init_write");
+  return PP_OK;
+}
+
+pp_status launch_pagerank(const pp_csr &AT, pp_dtype dt, int32_t nrhs, int32_t iters, double c,
+                          void *r, double *sums, void *ws, size_t ws_bytes, hipStream_t s) {
+  if (nrhs != 1) return fail(PP_EINVAL, "nrhs %d: only the single-vector form is built", nrhs);
+  if (dt == PP_F64)
+    return run_pagerank<double>(AT, iters, c, static_cast<double *>(r), sums, ws, ws_bytes, s);
+  return run_pagerank<float>(AT, iters, c, static_cast<float *>(r), sums, ws, ws_bytes, s);
+}
+
+}  // namespace pp

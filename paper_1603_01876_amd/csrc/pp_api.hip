@@ -1,0 +1,156 @@
+// pp_api.hip -- the extern "C" entry points of libpp.so (declared in
+// include/pp.h): host-side argument checks, then the launchers of k0..k3.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "pp_common.hpp"
+
+namespace pp {
+
+namespace {
+thread_local char g_last_error[512] = "";
+}
+
+pp_status fail(pp_status st, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+pp_status check_hip(hipError_t e, const char *where) {
+  return fail(PP_EHIP, "%s: %s (%s)", where, hipGetErrorName(e), hipGetErrorString(e));
+}
+
+namespace {
+
+constexpr int64_t kI32Max = (int64_t(1) << 31) - 1;
+
+bool kron_ok(const pp_kron_params *p) {
+  if (!p) return false;
+  if (p->scale < 1 || p->scale > 30) return false;
+  if (p->edge_factor < 1 || p->edge_factor > 1024) return false;
+  if (!(p->a >= 0 && p->b >= 0 && p->c >= 0 && p->d >= 0)) return false;
+  const double s = p->a + p->b + p->c + p->d;
+  return s > 0.999999999 && s < 1.000000001;
+}
+
+hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+}  // namespace
+}  // namespace pp
+
+using namespace pp;
+
+extern "C" {
+
+const char *pp_strerror(pp_status st) {
+  switch (st) {
+    case PP_OK: return "success";
+    case PP_EINVAL: return "invalid argument";
+    case PP_ERANGE: return "size out of range";
+    case PP_EWORKSPACE: return "workspace missing or too small";
+    case PP_EHIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+const char *pp_last_error(void) { return g_last_error; }
+
+size_t pp_workspace_bytes(pp_kernel k, int64_t n, int64_t m, pp_dtype dt, int32_t nrhs) {
+  if (n < 1 || n > (int64_t(1) << 30) || m < 0 || m > kI32Max) return size_t(-1);
+  if (dt != PP_F64 && dt != PP_F32) return size_t(-1);
+  switch (k) {
+    case PP_K0: return 0;
+    case PP_K1: return radix_ws_bytes(m, 31) + 512;
+    case PP_K2: return filter_ws_bytes(n, m);
+    case PP_K3:
+      if (nrhs < 1 || nrhs > 64 || n + m > kI32Max) return size_t(-1);
+      return pagerank_ws_bytes(n, m, dt, nrhs);
+  }
+  return size_t(-1);
+}
+
+pp_status pp_generate(const pp_kron_params *p, int64_t *u, int64_t *v, void *stream) {
+  if (!kron_ok(p)) return fail(PP_EINVAL, "pp_generate: bad generator parameters");
+  if (!u || !v) return fail(PP_EINVAL, "pp_generate: null output");
+  return launch_generate(*p, u, v, as_stream(stream));
+}
+
+pp_status pp_sort(int32_t scale, int64_t m, const int64_t *u, const int64_t *v, int64_t *u_out,
+                  int64_t *v_out, void *ws, size_t ws_bytes, void *stream) {
+  if (scale < 1 || scale > 30) return fail(PP_ERANGE, "pp_sort: scale %d", scale);
+  if (m < 0) return fail(PP_EINVAL, "pp_sort: m < 0");
+  if (m > kI32Max) return fail(PP_ERANGE, "pp_sort: m = %lld >= 2^31", (long long)m);
+  if (m == 0) return PP_OK;
+  if (!u || !v || !u_out || !v_out) return fail(PP_EINVAL, "pp_sort: null array");
+  if (u_out == u || u_out == v || v_out == u || v_out == v)
+    return fail(PP_EINVAL, "pp_sort: output aliases input");
+  const size_t need = radix_ws_bytes(m, 31) + 512;
+  if (!ws || ws_bytes < need) return fail(PP_EWORKSPACE, "pp_sort: workspace needs %zu bytes", need);
+  hipStream_t s = as_stream(stream);
+  // The check flag lives at the start of the workspace, the sort after it.
+  Carve c(ws);
+  uint32_t *flag = c.take<uint32_t>(1);
+  void *rest = reinterpret_cast<void *>(c.base + c.used);
+  const size_t rest_bytes = ws_bytes - c.used;
+  pp_status st = fill_i32(reinterpret_cast<int32_t *>(flag), 1, 0, s);
+  if (st != PP_OK) return st;
+  return radix_sort(RadixIn{nullptr, u, v}, RadixOut{nullptr, u_out, v_out}, m, scale, rest,
+                    rest_bytes, int64_t(1) << scale, false, flag, s, true);
+}
+
+pp_status pp_filter(int32_t scale, int64_t m, const int64_t *u, const int64_t *v, pp_dtype dt,
+                    pp_csr *AT, int32_t *d_in, int32_t *d_out, void *ws, size_t ws_bytes,
+                    void *stream) {
+  if (scale < 1 || scale > 30) return fail(PP_ERANGE, "pp_filter: scale %d", scale);
+  if (m < 0) return fail(PP_EINVAL, "pp_filter: m < 0");
+  if (m > kI32Max) return fail(PP_ERANGE, "pp_filter: m = %lld >= 2^31", (long long)m);
+  if (dt != PP_F64 && dt != PP_F32) return fail(PP_EINVAL, "pp_filter: dtype %d", int(dt));
+  if (!AT || !AT->row_ptr || (m > 0 && (!AT->col || !AT->val || !u || !v)))
+    return fail(PP_EINVAL, "pp_filter: null array");
+  const int64_t n = int64_t(1) << scale;
+  if (AT->n != n) return fail(PP_EINVAL, "pp_filter: AT->n = %lld, expected 2^%d", (long long)AT->n, scale);
+  if (AT->cap < m) return fail(PP_EINVAL, "pp_filter: AT->cap %lld < m %lld", (long long)AT->cap, (long long)m);
+  const size_t need = filter_ws_bytes(n, m);
+  if (!ws || ws_bytes < need) return fail(PP_EWORKSPACE, "pp_filter: workspace needs %zu bytes", need);
+  return launch_filter(scale, m, u, v, dt, AT, d_in, d_out, ws, ws_bytes, as_stream(stream));
+}
+
+pp_status pp_init_r(int64_t n, int32_t nrhs, uint64_t seed, pp_dtype dt, void *r, void *ws,
+                    size_t ws_bytes, void *stream) {
+  if (n < 1 || n > (int64_t(1) << 30)) return fail(PP_ERANGE, "pp_init_r: n = %lld", (long long)n);
+  if (nrhs < 1 || nrhs > 64) return fail(PP_EINVAL, "pp_init_r: nrhs %d", nrhs);
+  if (dt != PP_F64 && dt != PP_F32) return fail(PP_EINVAL, "pp_init_r: dtype %d", int(dt));
+  if (!r) return fail(PP_EINVAL, "pp_init_r: null r");
+  if (!ws) return fail(PP_EWORKSPACE, "pp_init_r: null workspace");
+  return launch_init_r(n, nrhs, seed, dt, r, ws, ws_bytes, as_stream(stream));
+}
+
+pp_status pp_pagerank(const pp_csr *AT, pp_dtype dt, int32_t nrhs, int32_t iters, double c,
+                      void *r, double *sums, void *ws, size_t ws_bytes, void *stream) {
+  if (!AT || !AT->row_ptr || !r) return fail(PP_EINVAL, "pp_pagerank: null argument");
+  if (dt != PP_F64 && dt != PP_F32) return fail(PP_EINVAL, "pp_pagerank: dtype %d", int(dt));
+  if (AT->n < 1 || AT->n > (int64_t(1) << 30)) return fail(PP_ERANGE, "pp_pagerank: n = %lld", (long long)AT->n);
+  if (AT->nnz < 0 || AT->nnz > AT->cap) return fail(PP_EINVAL, "pp_pagerank: nnz %lld, cap %lld", (long long)AT->nnz, (long long)AT->cap);
+  if (AT->n + AT->nnz > kI32Max) return fail(PP_ERANGE, "pp_pagerank: n + nnz >= 2^31");
+  if (AT->nnz > 0 && (!AT->col || !AT->val)) return fail(PP_EINVAL, "pp_pagerank: null col/val");
+  if (nrhs < 1 || nrhs > 64) return fail(PP_EINVAL, "pp_pagerank: nrhs %d", nrhs);
+  if (iters < 0) return fail(PP_EINVAL, "pp_pagerank: iters %d", iters);
+  if (!(c >= 0.0 && c <= 1.0)) return fail(PP_EINVAL, "pp_pagerank: c = %g", c);
+  const size_t need = pagerank_ws_bytes(AT->n, AT->nnz, dt, nrhs);
+  if (!ws || ws_bytes < need) return fail(PP_EWORKSPACE, "pp_pagerank: workspace needs %zu bytes", need);
+  return launch_pagerank(*AT, dt, nrhs, iters, c, r, sums, ws, ws_bytes, as_stream(stream));
+}
+
+pp_status pp_set_kernel_timing(int enable) { return set_kernel_timing(enable != 0); }
+
+int32_t pp_kernel_times(float *ms, int32_t cap) {
+  if (!ms || cap <= 0) return 0;
+  return kernel_times(ms, cap);
+}
+
+}  // extern "C"

@@ -1,0 +1,201 @@
+// pp_common.hpp -- shared device helpers and host-side plumbing of libpp.so
+// (gfx950, wave64).  Internal header: not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/pp.h"
+
+namespace pp {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- errors
+// Records a message for pp_last_error() and returns the status.
+pp_status fail(pp_status st, const char *fmt, ...);
+// Checks the launch / runtime status after enqueueing work.
+pp_status check_hip(hipError_t e, const char *where);
+#define PP_HIP(expr)                                                        \
+  do {                                                                      \
+    hipError_t e_ = (expr);                                                 \
+    if (e_ != hipSuccess) return ::pp::check_hip(e_, #expr);                \
+  } while (0)
+#define PP_LAUNCHED(where)                                                  \
+  do {                                                                      \
+    hipError_t e_ = hipGetLastError();                                      \
+    if (e_ != hipSuccess) return ::pp::check_hip(e_, where);                \
+  } while (0)
+
+// ------------------------------------------------------------ workspace
+// Bump allocator over the caller's workspace.  With base == nullptr it only
+// measures, so pp_workspace_bytes() and the entry points share one layout.
+struct Carve {
+  uintptr_t base;
+  size_t used = 0;
+  explicit Carve(void *p) : base(reinterpret_cast<uintptr_t>(p)) {}
+  template <typename T>
+  T *take(size_t count) {
+    const size_t align = 256;
+    size_t off = (base + used + align - 1) / align * align - base;
+    used = off + count * sizeof(T) + 0;
+    return base ? reinterpret_cast<T *>(base + off) : nullptr;
+  }
+  size_t bytes() const { return used + 256; }
+};
+
+inline int grid_for(int64_t work, int per_block, int cap = 1 << 20) {
+  int64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return static_cast<int>(g);
+}
+
+// ------------------------------------------------------- device helpers
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanes_below() {
+  return (1ull << lane_id()) - 1ull;
+}
+
+// Philox4x32-10 block (Salmon et al., SC'11): ten rounds; each round
+// multiplies counter words 0 and 2 by fixed odd constants, swaps the halves
+// across the state and mixes in a key that advances by a Weyl step.
+struct U4 {
+  uint32_t x, y, z, w;
+};
+__device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t a = 0xD2511F53u * c.x;
+    const uint32_t ah = __umulhi(0xD2511F53u, c.x);
+    const uint32_t b = 0xCD9E8D57u * c.z;
+    const uint32_t bh = __umulhi(0xCD9E8D57u, c.z);
+    c = U4{bh ^ c.y ^ k0, b, ah ^ c.w ^ k1, a};
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Inclusive wave-wide sum (64 lanes) by shuffles.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    T w = __shfl_xor(v, o, kWave);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+// Exclusive scan over a 256-thread block.  Returns the exclusive prefix of
+// `v` in thread order and writes the block total to *total.  `sh` must hold
+// 4 elements of shared memory.  Contains two __syncthreads().
+template <typename T>
+__device__ __forceinline__ T block_exscan256(T v, T *sh, T *total) {
+  const int lane = lane_id();
+  const int w = threadIdx.x / kWave;
+  T x = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    T y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  if (lane == kWave - 1) sh[w] = x;
+  __syncthreads();
+  T before = 0, all = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    T s = sh[i];
+    if (i < w) before += s;
+    all += s;
+  }
+  __syncthreads();
+  *total = all;
+  return before + x - v;
+}
+
+// Deterministic 256-thread block sum (fixed shuffle tree, then fixed
+// order over the four waves).  Result valid in every thread.
+template <typename T>
+__device__ __forceinline__ T block_sum256(T v, T *sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == 0) sh[w] = v;
+  __syncthreads();
+  T r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return r;
+}
+
+// Device-scope loads that bypass non-coherent caches, for values written
+// by other workgroups of the same launch.
+template <typename T>
+__device__ __forceinline__ T load_acquire(const T *p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------ host launchers
+// Each .hip file exposes plain host functions that enqueue its kernels.
+
+// fill / copy helpers (pp_util.hip)
+pp_status fill_i32(int32_t *p, int64_t n, int32_t value, hipStream_t s);
+pp_status fill_u64(uint64_t *p, int64_t n, uint64_t value, hipStream_t s);
+pp_status copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t s);
+
+// Exclusive scan of n uint32 values (in place allowed).  `total` (device,
+// may be null) receives the sum as int64.  Workspace from scan_ws_elems().
+int64_t scan_ws_elems(int64_t n);
+pp_status exscan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *ws,
+                     int64_t *total, hipStream_t s);
+
+// K0 (k0_generate.hip)
+pp_status launch_generate(const pp_kron_params &p, int64_t *u, int64_t *v, hipStream_t s);
+
+// K1 / K2 radix machinery (k1_radix.hip).  Keys are 64-bit words
+// (hi << 32 | lo); a pass orders them stably by bits [32+shift, 32+shift+bits).
+struct RadixIn {
+  const uint64_t *packed;  // or null: key = hi[i] << 32 | lo[i]
+  const int64_t *hi;
+  const int64_t *lo;
+};
+struct RadixOut {
+  uint64_t *packed;        // or null: hi[i] = key >> 32, lo[i] = key & mask
+  int64_t *hi;
+  int64_t *lo;
+};
+size_t radix_ws_bytes(int64_t m, int32_t key_bits);
+// Sorts m keys stably by their hi word's low `key_bits` bits.  If
+// check_n > 0 the first pass flags (into *flag, device) any hi or lo outside
+// [0, check_n) with bit 0 and, if check_sorted_lo, any lo[i] < lo[i-1]
+// with bit 1; the caller decides when to read it.
+pp_status radix_sort(RadixIn in, RadixOut out, int64_t m, int32_t key_bits, void *ws,
+                     size_t ws_bytes, int64_t check_n, bool check_sorted_lo, uint32_t *flag,
+                     hipStream_t s, bool sync_after_first_pass);
+
+// K2 (k2_filter.hip)
+size_t filter_ws_bytes(int64_t n, int64_t m);
+pp_status launch_filter(int32_t scale, int64_t m, const int64_t *u, const int64_t *v,
+                        pp_dtype dt, pp_csr *AT, int32_t *d_in, int32_t *d_out, void *ws,
+                        size_t ws_bytes, hipStream_t s);
+
+// K3 (k3_pagerank.hip)
+size_t pagerank_ws_bytes(int64_t n, int64_t nnz_cap, pp_dtype dt, int32_t nrhs);
+pp_status launch_init_r(int64_t n, int32_t nrhs, uint64_t seed, pp_dtype dt, void *r,
+                        void *ws, size_t ws_bytes, hipStream_t s);
+pp_status launch_pagerank(const pp_csr &AT, pp_dtype dt, int32_t nrhs, int32_t iters, double c,
+                          void *r, double *sums, void *ws, size_t ws_bytes, hipStream_t s);
+pp_status set_kernel_timing(bool enable);
+int32_t kernel_times(float *ms, int32_t cap);
+
+}  // namespace pp

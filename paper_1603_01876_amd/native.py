@@ -1,0 +1,248 @@
+"""Python binding of libpp.so (include/pp.h): argument marshalling only.
+
+Every array is a torch tensor on the GPU; torch provides device memory and
+the current stream, nothing else.  Each function calls exactly one C entry
+point of the same name; all computation happens in the library's HIP
+kernels.  There is no fallback: if libpp.so is missing or fails to load,
+every call raises PPError.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpp.so")
+
+PP_OK, PP_EINVAL, PP_ERANGE, PP_EWORKSPACE, PP_EHIP = range(5)
+F64, F32 = 0, 1
+K0, K1, K2, K3 = range(4)
+
+_TORCH = {F64: torch.float64, F32: torch.float32}
+_NAMES = {"f64": F64, "f32": F32, F64: F64, F32: F32,
+          torch.float64: F64, torch.float32: F32}
+
+
+class PPError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status}: {detail}")
+        self.status = status
+
+
+class _Kron(ctypes.Structure):
+    _fields_ = [("scale", ctypes.c_int32), ("edge_factor", ctypes.c_int32),
+                ("a", ctypes.c_double), ("b", ctypes.c_double),
+                ("c", ctypes.c_double), ("d", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("cap", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("val", ctypes.c_void_p)]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every entry point in include/pp.h.
+_VP, _I32, _I64, _U64, _SZ, _D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                  ctypes.c_uint64, ctypes.c_size_t, ctypes.c_double)
+SIGNATURES = {
+    "pp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "pp_last_error": (ctypes.c_char_p, []),
+    "pp_workspace_bytes": (_SZ, [ctypes.c_int, _I64, _I64, ctypes.c_int, _I32]),
+    "pp_generate": (ctypes.c_int, [ctypes.POINTER(_Kron), _VP, _VP, _VP]),
+    "pp_sort": (ctypes.c_int, [_I32, _I64, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    "pp_filter": (ctypes.c_int, [_I32, _I64, _VP, _VP, ctypes.c_int, ctypes.POINTER(_Csr),
+                                 _VP, _VP, _VP, _SZ, _VP]),
+    "pp_init_r": (ctypes.c_int, [_I64, _I32, _U64, ctypes.c_int, _VP, _VP, _SZ, _VP]),
+    "pp_pagerank": (ctypes.c_int, [ctypes.POINTER(_Csr), ctypes.c_int, _I32, _I32, _D, _VP,
+                                   _VP, _VP, _SZ, _VP]),
+    "pp_set_kernel_timing": (ctypes.c_int, [ctypes.c_int]),
+    "pp_kernel_times": (_I32, [ctypes.POINTER(ctypes.c_float), _I32]),
+}
+
+
+def lib():
+    """Loads libpp.so once.  Raises PPError if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise PPError(-1, "libpp", f"{LIB_PATH} not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st: int, where: str):
+    if st != PP_OK:
+        L = lib()
+        raise PPError(st, where, f"{L.pp_strerror(st).decode()}: {L.pp_last_error().decode()}")
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def dtype_code(dtype) -> int:
+    return _NAMES[dtype]
+
+
+def workspace_bytes(kernel: int, n: int, m: int, dtype="f64", nrhs: int = 1) -> int:
+    b = lib().pp_workspace_bytes(kernel, n, m, dtype_code(dtype), nrhs)
+    if b == ctypes.c_size_t(-1).value:
+        raise PPError(PP_ERANGE, "pp_workspace_bytes", f"kernel {kernel}, n {n}, m {m}")
+    return int(b)
+
+
+def _ws(nbytes: int, ws, device):
+    if ws is not None:
+        if ws.numel() * ws.element_size() < nbytes:
+            raise PPError(PP_EWORKSPACE, "workspace", f"needs {nbytes} bytes")
+        return ws
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+
+# ---------------------------------------------------------------------- K0
+def generate(spec, u=None, v=None, device="cuda"):
+    """K0: returns (u, v) int64 tensors of M = k*2^S edges."""
+    m = spec.edge_factor << spec.scale
+    if u is None:
+        u = torch.empty(m, dtype=torch.int64, device=device)
+    if v is None:
+        v = torch.empty(m, dtype=torch.int64, device=device)
+    p = _Kron(spec.scale, spec.edge_factor, spec.a, spec.b, spec.c, spec.d,
+              spec.seed & (2**64 - 1))
+    _check(lib().pp_generate(ctypes.byref(p), _ptr(u), _ptr(v), _stream()), "pp_generate")
+    return u, v
+
+
+# ---------------------------------------------------------------------- K1
+def sort(scale: int, u, v, u_out=None, v_out=None, ws=None):
+    """K1: stable sort by u.  Returns (u_out, v_out)."""
+    m = u.numel()
+    if u_out is None:
+        u_out = torch.empty_like(u)
+    if v_out is None:
+        v_out = torch.empty_like(v)
+    nbytes = workspace_bytes(K1, 1 << scale, m)
+    ws = _ws(nbytes, ws, u.device)
+    _check(lib().pp_sort(scale, m, _ptr(u), _ptr(v), _ptr(u_out), _ptr(v_out), _ptr(ws),
+                         ws.numel(), _stream()), "pp_sort")
+    return u_out, v_out
+
+
+# ---------------------------------------------------------------------- K2
+@dataclass
+class CSR:
+    """CSR(A^T) on the device: row v lists the sources u of column v of A."""
+    n: int
+    nnz: int
+    row_ptr: torch.Tensor
+    col: torch.Tensor
+    val: torch.Tensor
+
+    @property
+    def dtype(self) -> int:
+        return dtype_code(self.val.dtype)
+
+    def _c(self) -> _Csr:
+        return _Csr(self.n, self.nnz, self.col.numel(), self.row_ptr.data_ptr(),
+                    self.col.data_ptr(), self.val.data_ptr())
+
+    @staticmethod
+    def from_arrays(n, row_ptr, col, val, dtype="f64", device="cuda") -> "CSR":
+        """Uploads a host CSR (numpy or torch) to the device."""
+        rp = torch.as_tensor(row_ptr).to(torch.int32)
+        cl = torch.as_tensor(col).to(torch.int32)
+        vl = torch.as_tensor(val).to(_TORCH[dtype_code(dtype)])
+        nnz = int(rp[-1])
+        cap = max(nnz, 1)
+        col_d = torch.zeros(cap, dtype=torch.int32, device=device)
+        val_d = torch.zeros(cap, dtype=vl.dtype, device=device)
+        col_d[:nnz] = cl[:nnz].to(device)
+        val_d[:nnz] = vl[:nnz].to(device)
+        return CSR(n, nnz, rp.to(device), col_d, val_d)
+
+
+def filter(scale: int, u, v, dtype="f64", AT: CSR | None = None, d_in=None, d_out=None,
+           ws=None, degrees: bool = True):
+    """K2: returns (CSR(A^T), d_in, d_out); degrees are None if not asked for."""
+    n = 1 << scale
+    m = u.numel()
+    dt = dtype_code(dtype)
+    dev = u.device
+    if AT is None:
+        cap = max(m, 1)
+        AT = CSR(n, 0, torch.empty(n + 1, dtype=torch.int32, device=dev),
+                 torch.empty(cap, dtype=torch.int32, device=dev),
+                 torch.empty(cap, dtype=_TORCH[dt], device=dev))
+    if degrees:
+        if d_in is None:
+            d_in = torch.empty(n, dtype=torch.int32, device=dev)
+        if d_out is None:
+            d_out = torch.empty(n, dtype=torch.int32, device=dev)
+    ws = _ws(workspace_bytes(K2, n, m), ws, dev)
+    c = AT._c()
+    _check(lib().pp_filter(scale, m, _ptr(u), _ptr(v), dt, ctypes.byref(c), _ptr(d_in),
+                           _ptr(d_out), _ptr(ws), ws.numel(), _stream()), "pp_filter")
+    AT.nnz = int(c.nnz)
+    return AT, d_in, d_out
+
+
+# ---------------------------------------------------------------------- K3
+def init_r(n: int, seed: int, dtype="f64", nrhs: int = 1, out=None, ws=None, device="cuda"):
+    """K3 initial vector(s): n x nrhs row-major (shape (n,) when nrhs == 1)."""
+    dt = dtype_code(dtype)
+    if out is None:
+        shape = (n,) if nrhs == 1 else (n, nrhs)
+        out = torch.empty(shape, dtype=_TORCH[dt], device=device)
+    ws = _ws(workspace_bytes(K3, n, 0, dt, nrhs), ws, out.device)
+    _check(lib().pp_init_r(n, nrhs, seed & (2**64 - 1), dt, _ptr(out), _ptr(ws), ws.numel(),
+                           _stream()), "pp_init_r")
+    return out
+
+
+def pagerank(AT: CSR, r, iters: int = 20, c: float = 0.85, sums=True, ws=None):
+    """K3: iterates r in place; returns sum(r) per iteration ((iters+1) x nrhs
+    FP64 tensor) or None when sums is False."""
+    dt = dtype_code(r.dtype)
+    if dt != AT.dtype:
+        raise PPError(PP_EINVAL, "pagerank", "r and matrix values differ in dtype")
+    nrhs = 1 if r.dim() == 1 else r.shape[1]
+    if sums is True:
+        sums = torch.empty((iters + 1, nrhs) if nrhs > 1 else (iters + 1,),
+                           dtype=torch.float64, device=r.device)
+    elif sums is False:
+        sums = None
+    ws = _ws(workspace_bytes(K3, AT.n, AT.nnz, dt, nrhs), ws, r.device)
+    cs = AT._c()
+    _check(lib().pp_pagerank(ctypes.byref(cs), dt, nrhs, iters, c, _ptr(r), _ptr(sums),
+                             _ptr(ws), ws.numel(), _stream()), "pp_pagerank")
+    return sums
+
+
+# ------------------------------------------------------------ instrumentation
+def set_kernel_timing(enable: bool) -> None:
+    """Records HIP events around every sparse-product launch of pagerank()."""
+    _check(lib().pp_set_kernel_timing(int(enable)), "pp_set_kernel_timing")
+
+
+def kernel_times(cap: int = 256) -> list[float]:
+    """Durations (ms) of the sparse-product launches of the last pagerank()."""
+    buf = (ctypes.c_float * cap)()
+    n = lib().pp_kernel_times(buf, cap)
+    if n < 0:
+        raise PPError(PP_EHIP, "pp_kernel_times", lib().pp_last_error().decode())
+    return [float(buf[i]) for i in range(n)]

@@ -1,0 +1,146 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library must load, export every entry point include/pp.h declares, and
+reject bad arguments on the host before anything is enqueued.
+"""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from paper_1603_01876_amd import native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w\s\*]*?\b(pp_\w+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_the_pipeline():
+    names = declared_functions()
+    for want in ["pp_generate", "pp_sort", "pp_filter", "pp_init_r", "pp_pagerank",
+                 "pp_workspace_bytes", "pp_strerror", "pp_last_error"]:
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = native.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+        assert name in native.SIGNATURES, f"binding lacks {name}"
+
+
+def test_strerror():
+    L = native.lib()
+    assert L.pp_strerror(0) == b"success"
+    assert L.pp_strerror(3).startswith(b"workspace")
+
+
+def test_workspace_sizes():
+    n, m = 1 << 12, 16 << 12
+    assert native.workspace_bytes(native.K0, n, m) == 0
+    k1 = native.workspace_bytes(native.K1, n, m)
+    assert k1 >= 16 * m                      # two 8-byte key buffers
+    k2 = native.workspace_bytes(native.K2, n, m)
+    assert k2 >= k1
+    k3d = native.workspace_bytes(native.K3, n, m, "f64")
+    k3f = native.workspace_bytes(native.K3, n, m, "f32")
+    assert k3d > k3f > 0
+    with pytest.raises(native.PPError):
+        native.workspace_bytes(native.K1, 0, m)
+    with pytest.raises(native.PPError):
+        native.workspace_bytes(native.K1, n, 1 << 31)
+    with pytest.raises(native.PPError):
+        native.workspace_bytes(native.K3, n, m, "f32", nrhs=65)
+
+
+def _err(fn, *args):
+    st = fn(*args)
+    return st
+
+
+def test_generate_rejects_bad_params():
+    L = native.lib()
+    p = native._Kron(0, 16, 0.57, 0.19, 0.19, 0.05, 1)
+    assert L.pp_generate(ctypes.byref(p), 8, 8, None) == native.PP_EINVAL
+    p = native._Kron(10, 16, 0.5, 0.5, 0.5, 0.5, 1)
+    assert L.pp_generate(ctypes.byref(p), 8, 8, None) == native.PP_EINVAL
+    p = native._Kron(10, 16, 0.57, 0.19, 0.19, 0.05, 1)
+    assert L.pp_generate(ctypes.byref(p), None, 8, None) == native.PP_EINVAL
+    assert b"null" in L.pp_last_error()
+
+
+def test_sort_rejects_bad_args():
+    L = native.lib()
+    assert L.pp_sort(31, 10, 8, 8, 16, 16, 8, 1 << 20, None) == native.PP_ERANGE
+    assert L.pp_sort(10, 1 << 31, 8, 8, 16, 16, 8, 1 << 20, None) == native.PP_ERANGE
+    assert L.pp_sort(10, -1, 8, 8, 16, 16, 8, 1 << 20, None) == native.PP_EINVAL
+    assert L.pp_sort(10, 100, None, 8, 16, 24, 8, 1 << 20, None) == native.PP_EINVAL
+    assert L.pp_sort(10, 100, 8, 16, 8, 24, 64, 1 << 20, None) == native.PP_EINVAL  # alias
+    assert L.pp_sort(10, 100, 8, 16, 24, 32, None, 0, None) == native.PP_EWORKSPACE
+    assert L.pp_sort(10, 100, 8, 16, 24, 32, 64, 100, None) == native.PP_EWORKSPACE
+    assert L.pp_sort(10, 0, None, None, None, None, None, 0, None) == native.PP_OK
+
+
+def test_filter_rejects_bad_args():
+    L = native.lib()
+    c = native._Csr(1 << 10, 0, 1 << 14, 8, 16, 24)
+    assert L.pp_filter(10, 1 << 14, 8, 16, 0, ctypes.byref(c), None, None, None, 0,
+                       None) == native.PP_EWORKSPACE
+    bad_n = native._Csr(1 << 9, 0, 1 << 14, 8, 16, 24)
+    assert L.pp_filter(10, 1 << 14, 8, 16, 0, ctypes.byref(bad_n), None, None, 64, 1 << 30,
+                       None) == native.PP_EINVAL
+    small = native._Csr(1 << 10, 0, 100, 8, 16, 24)
+    assert L.pp_filter(10, 1 << 14, 8, 16, 0, ctypes.byref(small), None, None, 64, 1 << 30,
+                       None) == native.PP_EINVAL
+    assert L.pp_filter(10, 1 << 14, 8, 16, 7, ctypes.byref(c), None, None, 64, 1 << 30,
+                       None) == native.PP_EINVAL
+    assert L.pp_filter(0, 1 << 14, 8, 16, 0, ctypes.byref(c), None, None, 64, 1 << 30,
+                       None) == native.PP_ERANGE
+
+
+def test_pagerank_rejects_bad_args():
+    L = native.lib()
+    c = native._Csr(1000, 10, 100, 8, 16, 24)
+    ok = dict(dt=0, nrhs=1, iters=20, c=0.85)
+    assert L.pp_pagerank(ctypes.byref(c), 0, 0, 20, 0.85, 8, None, 64, 1 << 30,
+                         None) == native.PP_EINVAL
+    assert L.pp_pagerank(ctypes.byref(c), 0, 1, -1, 0.85, 8, None, 64, 1 << 30,
+                         None) == native.PP_EINVAL
+    assert L.pp_pagerank(ctypes.byref(c), 0, 1, 20, 1.5, 8, None, 64, 1 << 30,
+                         None) == native.PP_EINVAL
+    assert L.pp_pagerank(ctypes.byref(c), 0, 1, 20, 0.85, 8, None, 64, 10,
+                         None) == native.PP_EWORKSPACE
+    over = native._Csr(1000, 200, 100, 8, 16, 24)
+    assert L.pp_pagerank(ctypes.byref(over), 0, 1, 20, 0.85, 8, None, 64, 1 << 30,
+                         None) == native.PP_EINVAL
+    big = native._Csr(1 << 30, (1 << 31) - 10, 1 << 31, 8, 16, 24)
+    assert L.pp_pagerank(ctypes.byref(big), 0, 1, 20, 0.85, 8, None, 64, 1 << 30,
+                         None) == native.PP_ERANGE
+    assert ok
+
+
+def test_init_r_rejects_bad_args():
+    L = native.lib()
+    assert L.pp_init_r(0, 1, 1, 0, 8, 64, 1 << 20, None) == native.PP_ERANGE
+    assert L.pp_init_r(100, 0, 1, 0, 8, 64, 1 << 20, None) == native.PP_EINVAL
+    assert L.pp_init_r(100, 1, 1, 0, None, 64, 1 << 20, None) == native.PP_EINVAL
+    assert L.pp_init_r(100, 1, 1, 0, 8, None, 0, None) == native.PP_EWORKSPACE
+
+
+def test_product_path_has_no_cpu_fallback():
+    # The binding imports nothing from the oracle and has no host compute path.
+    for f in glob.glob(os.path.join(ROOT, "paper_1603_01876_amd", "*.py")):
+        src = open(f).read()
+        assert not re.search(r"^\s*(import|from)\s+oracle\b", src, flags=re.M), f
+    src = open(os.path.join(ROOT, "paper_1603_01876_amd", "native.py")).read()
+    assert not re.search(r"^\s*import numpy", src, flags=re.M)

@@ -182,3 +182,27 @@ def test_step_rows_equals_one_iteration(ora):
     r1, sums = ora.pagerank(n, f.A_rp, f.A_col, f.A_val, r0, iters=1, c=C)
     y = ora.step_rows(n, f.AT_rp, f.AT_col, f.AT_val, r0, sums[0], C)
     assert np.array_equal(y, r1)       # same summation order: bit-exact
+
+
+# ------------------------------------------------------- accuracy of the sums
+@pytest.mark.parametrize("scale", [12, 16])
+def test_pagerank_matches_extended_precision(ora, scale):
+    # The iteration computed in x87 extended precision (64-bit significand)
+    # with numpy: the oracle's compensated FP64 sums must agree to ~1e-16,
+    # far inside the 1e-12 FP64 tolerance the GPU is held to.
+    p, f = pipeline_matrix(ora, scale)
+    n = p.n
+    r0 = ora.init_r(n, 7)
+    r, sums = ora.pagerank(n, f.A_rp, f.A_col, f.A_val, r0, iters=20, c=C)
+    rows = np.repeat(np.arange(n), np.diff(f.AT_rp))
+    x = r0.astype(np.longdouble)
+    val = f.AT_val.astype(np.longdouble)
+    cl = np.longdouble(C)
+    a = (np.longdouble(1) - cl) / np.longdouble(n)
+    for _ in range(20):
+        y = np.zeros(n, np.longdouble)
+        np.add.at(y, rows, x[f.AT_col] * val)
+        x = cl * y + a * x.sum()
+    err = float(np.abs(r.astype(np.longdouble) - x).sum() / np.abs(x).sum())
+    assert err <= 1e-15
+    assert abs(float(sums[-1] / x.sum()) - 1.0) <= 1e-15
