@@ -41,7 +41,43 @@ def parse():
     ap.add_argument("--no-f64-side", action="store_true", help="skip the FP64 side-by-side run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy 1 GiB three times (reference for rocprofv3 byte counters)")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    """A plain device copy of known size: rocprofv3's FETCH_SIZE / WRITE_SIZE
+    read for it gives the factor that turns those counters into bytes."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes": 1 << 30, "copies": 3}), flush=True)
+
+
+def measured_traffic(scale: int, dtype: str):
+    """HBM bytes per SpMV launch from the committed rocprofv3 counter summary
+    for this workload, or None when there is none or when the kernel source
+    has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k3_spmv_kron_s{scale}_{dtype}_counters.md")
+    src = os.path.join(ROOT, "paper_1603_01876_amd", "csrc", "k3_pagerank.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.split(":", 1)[0].strip() in (
+                "kernel_source_sha256", "fetch_bytes_per_launch", "write_bytes_per_launch"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha256") != sha:
+        return None
+    return (float(fields["fetch_bytes_per_launch"]) + float(fields["write_bytes_per_launch"])) / 1e9
 
 
 def spmv_bytes(n: int, nnz: int, dtype: str) -> int:
@@ -97,6 +133,9 @@ def _run_rows(oracle, AT, rp, r, r0, r1):
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU path is a design, not a build", file=sys.stderr)
@@ -200,7 +239,8 @@ def main():
         },
         "roofline": {"bound": "hbm", "kernel": f"k_spmv<{'float' if dt == 'f32' else 'double'}>",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(S, dt),
+                     "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "algorithmic_bytes_per_launch": nbytes},
         "sum_r": {"first": float(sums_h[0]), "last": float(sums_h[-1])},
     }

@@ -114,40 +114,70 @@ __global__ __launch_bounds__(256) void k_block_flags(const int32_t *__restrict__
 }
 
 // ------------------------------------------------------------------ SpMV
-template <typename V>
+__device__ __forceinline__ AccD shfl_up_acc(AccD a, int o) { return AccD{__shfl_up(a.s, o, kWave)}; }
+__device__ __forceinline__ AccF shfl_up_acc(AccF a, int o) {
+  return AccF{__shfl_up(a.s, o, kWave), __shfl_up(a.e, o, kWave)};
+}
+
+template <typename V, int IPT>
 __global__ __launch_bounds__(kThreads) void k_spmv(
     const int32_t *__restrict__ rp, const int32_t *__restrict__ col, const V *__restrict__ val,
     const V *__restrict__ x, V *__restrict__ y, int32_t n, const int2 *__restrict__ coord,
     double c, const double *__restrict__ tele, double *__restrict__ blk_ysum,
     typename Form<V>::Acc *__restrict__ blk_carry, typename Form<V>::Acc *__restrict__ blk_head) {
   using Acc = typename Form<V>::Acc;
-  __shared__ int32_t s_end[kItems];
-  __shared__ V s_prod[kItems];
-  __shared__ Acc s_carry[kThreads];
-  __shared__ int32_t s_row[kThreads];
+  constexpr int kD = kThreads * IPT;
+  constexpr int kWaves = kThreads / kWave;
+  __shared__ int32_t s_end[kD];
+  __shared__ V s_prod[kD];
+  __shared__ Acc s_pre[kThreads];
+  __shared__ Acc s_wtail[kWaves];
+  __shared__ int32_t s_wfirst[kWaves], s_wlast[kWaves];
   __shared__ double s_red[4];
 
-  const int b = blockIdx.x, tid = threadIdx.x;
+  const int b = blockIdx.x, tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
   const int2 c0 = coord[b], c1 = coord[b + 1];
   const int32_t i0 = c0.x, j0 = c0.y;
   const int32_t na = c1.x - c0.x, nz = c1.y - c0.y;
 
-  // Stage: local row ends and products, coalesced.  Loads are issued for
-  // all of a thread's slots before any is consumed.
+  // Stage the workgroup's products r[col]*val and local row ends in LDS.
+  // Indices past the end are clamped to the last valid one, so every load
+  // is unconditional: a thread issues all IPT column and value loads, then
+  // all IPT gathers, before it waits on any of them.
   {
-    int32_t cc[kIpt];
-    V vv[kIpt];
+    int32_t cc[IPT], ee[IPT];
+    V vv[IPT], xv[IPT];
+    if (nz > 0) {
 #pragma unroll
-    for (int r = 0; r < kIpt; ++r) {
-      const int k = r * kThreads + tid;
-      cc[r] = k < nz ? __builtin_nontemporal_load(col + j0 + k) : 0;
-      vv[r] = k < nz ? __builtin_nontemporal_load(val + j0 + k) : V(0);
+      for (int r = 0; r < IPT; ++r) {
+        const int k = r * kThreads + tid;
+        const int kk = k < nz ? k : nz - 1;
+        cc[r] = __builtin_nontemporal_load(col + j0 + kk);
+        vv[r] = __builtin_nontemporal_load(val + j0 + kk);
+      }
     }
+    if (na > 0) {
 #pragma unroll
-    for (int r = 0; r < kIpt; ++r) {
-      const int k = r * kThreads + tid;
-      if (k < nz) s_prod[k] = x[cc[r]] * vv[r];
-      if (k < na) s_end[k] = rp[i0 + 1 + k] - j0;
+      for (int r = 0; r < IPT; ++r) {
+        const int k = r * kThreads + tid;
+        ee[r] = rp[i0 + 1 + (k < na ? k : na - 1)];
+      }
+    }
+    if (nz > 0) {
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) xv[r] = x[cc[r]];
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) {
+        const int k = r * kThreads + tid;
+        if (k < nz) s_prod[k] = xv[r] * vv[r];
+      }
+    }
+    if (na > 0) {
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) {
+        const int k = r * kThreads + tid;
+        if (k < na) s_end[k] = ee[r] - j0;
+      }
     }
   }
   const bool mid_row = i0 < n && rp[i0] < j0;
@@ -156,8 +186,8 @@ __global__ __launch_bounds__(kThreads) void k_spmv(
 
   // This thread's items [d, dend) of the workgroup's merge sequence.
   const int32_t tot = na + nz;
-  int32_t d = tid * kIpt < tot ? tid * kIpt : tot;
-  const int32_t dend = d + kIpt < tot ? d + kIpt : tot;
+  int32_t d = tid * IPT < tot ? tid * IPT : tot;
+  const int32_t dend = d + IPT < tot ? d + IPT : tot;
   int32_t lo = d - nz > 0 ? d - nz : 0, hi = d < na ? d : na;
   while (lo < hi) {
     const int32_t m = (lo + hi) >> 1;
@@ -188,38 +218,50 @@ __global__ __launch_bounds__(kThreads) void k_spmv(
       ++tj;
     }
   }
-  s_carry[tid] = acc;
-  s_row[tid] = i0 + ti;
+
+  // Segmented inclusive scan of the threads' open-row partials, keyed by the
+  // open row (non-decreasing in thread order, so equal keys are contiguous):
+  // shuffles inside each wave, then the tails of earlier waves.
+  const int32_t key = i0 + ti;
+  Acc v = acc;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const Acc vu = shfl_up_acc(v, o);
+    const int32_t ku = __shfl_up(key, o, kWave);
+    if (lane >= o && ku == key) v = merge(vu, v);
+  }
+  if (lane == kWave - 1) {
+    s_wtail[w] = v;
+    s_wlast[w] = key;
+  }
+  if (lane == 0) s_wfirst[w] = key;
+  __syncthreads();
+  {
+    Acc before{};
+    for (int q = w - 1; q >= 0; --q) {
+      if (s_wlast[q] != key) break;
+      before = merge(s_wtail[q], before);
+      if (s_wfirst[q] != key) break;
+    }
+    v = merge(before, v);
+  }
+  s_pre[tid] = v;
   __syncthreads();
 
   if (first_row >= 0) {
-    // Complete the first row this thread ends with the partials of the
-    // threads before it that left the same row open, in thread order.
+    // The first row this thread ends is the row thread tid-1 left open, so
+    // its earlier part is that thread's segmented prefix.
     const int32_t R = i0 + first_row;
-    int t = tid - 1;
-    while (t >= 0 && s_row[t] == R) --t;
-    Acc sum{};
-    for (int q = t + 1; q < tid; ++q) sum = merge(sum, s_carry[q]);
-    sum = merge(sum, first);
-    if (t < 0 && mid_row && R == i0) {
-      blk_head[b] = sum;  // row began in an earlier workgroup: fixed up later
+    const Acc sum = tid > 0 ? merge(s_pre[tid - 1], first) : first;
+    if (R == i0 && mid_row) {
+      blk_head[b] = sum;  // row began in an earlier workgroup: completed later
     } else {
       const V yv = Form<V>::finish(sum, c, tk);
       y[R] = yv;
       ysum += double(yv);
     }
   }
-  if (tid == kThreads - 1) {
-    // Partial of the row left open at the end of this workgroup.
-    const int32_t R = c1.x;
-    Acc sum{};
-    if (R < n) {
-      int t = kThreads - 1;
-      while (t >= 0 && s_row[t] == R) --t;
-      for (int q = t + 1; q < kThreads; ++q) sum = merge(sum, s_carry[q]);
-    }
-    blk_carry[b] = sum;
-  }
+  if (tid == kThreads - 1) blk_carry[b] = c1.x < n ? v : Acc{};
   const double bs = block_sum256(ysum, s_red);
   if (tid == 0) blk_ysum[b] = bs;
 }
@@ -442,7 +484,7 @@ pp_status run_pagerank(const pp_csr &AT, int32_t iters, double c, V *r, double *
     const V *x = (k & 1) ? L.y : r;
     V *yv = (k & 1) ? r : L.y;
     if ((st = timed_begin(s)) != PP_OK) return st;
-    hipLaunchKernelGGL(k_spmv<V>, dim3(nb), dim3(kThreads), 0, s, AT.row_ptr, AT.col, val, x, yv,
+    hipLaunchKernelGGL((k_spmv<V, kIpt>), dim3(nb), dim3(kThreads), 0, s, AT.row_ptr, AT.col, val, x, yv,
                        int32_t(n), L.coord, c, L.tele + (k & 1), L.blk_ysum, L.blk_carry,
                        L.blk_head);
     if ((st = timed_end(s)) != PP_OK) return st;
