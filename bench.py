@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--no-f64-side", action="store_true", help="skip the FP64 side-by-side run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-relabel", action="store_true",
+                    help="iterate on K2's labels (no degree-ordered relabelling inside K3)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB three times (reference for rocprofv3 byte counters)")
     return ap.parse_args()
@@ -179,7 +181,8 @@ def main():
         pp.filter(S, us, vs, dt, AT=AT, d_in=d_in, d_out=d_out, ws=ws12)
         ev[3].record()
         pp.init_r(n, rseed, dt, out=r, ws=ws3)
-        pp.pagerank(AT, r, iters=args.iters, c=workloads.DAMPING, sums=sums, ws=ws3)
+        pp.pagerank(AT, r, iters=args.iters, c=workloads.DAMPING, sums=sums, ws=ws3,
+                    weights=None if args.no_relabel else d_out)
         ev[4].record()
         return ev
 
@@ -264,7 +267,8 @@ def main():
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
             pp.init_r(n, rseed, "f64", out=r64, ws=ws64)
-            pp.pagerank(AT64, r64, iters=args.iters, c=workloads.DAMPING, sums=sums64, ws=ws64)
+            pp.pagerank(AT64, r64, iters=args.iters, c=workloads.DAMPING, sums=sums64, ws=ws64,
+                        weights=None if args.no_relabel else d_out)
             e1.record()
             spmv64 += pp.kernel_times()
             torch.cuda.synchronize()

@@ -136,11 +136,19 @@ pp_status pp_init_r(int64_t n, int32_t nrhs, uint64_t seed, pp_dtype dt, void *r
  * sparse matrix-vector form; nrhs in 2..64 runs the sparse matrix-dense
  * matrix form.  sums (device, (iters+1) x nrhs FP64, may be NULL) receives
  * sum(r) of each right-hand side before every iteration and after the last
- * one.  Dangling rows are not adjusted, so sum(r) may decay.  The caller
- * must supply a valid CSR (row_ptr non-decreasing from 0 to nnz, columns in
- * [0, n)); pp_filter's output always is. */
+ * one.  Dangling rows are not adjusted, so sum(r) may decay.
+ * order_weights (device, n int32, may be NULL): per-vertex weights, e.g.
+ * pp_filter's d_out.  When given, the iterations run on a copy of the
+ * matrix (in the workspace) whose vertices are relabelled by decreasing
+ * floor(log2(weight + 1)), ties in label order, so that frequently gathered
+ * ranks share cache lines; r is permuted in and out, so inputs and outputs
+ * keep the original labels.  The weights only affect speed and the order
+ * of floating-point sums.  The caller must supply a valid CSR (row_ptr
+ * non-decreasing from 0 to nnz, columns in [0, n)); pp_filter's output
+ * always is. */
 pp_status pp_pagerank(const pp_csr *AT, pp_dtype dt, int32_t nrhs, int32_t iters, double c,
-                      void *r, double *sums, void *ws, size_t ws_bytes, void *stream);
+                      const int32_t *order_weights, void *r, double *sums, void *ws,
+                      size_t ws_bytes, void *stream);
 
 /* Benchmark instrumentation.  While enabled (enable != 0), each
  * pp_pagerank call records a pair of HIP events on its stream around every

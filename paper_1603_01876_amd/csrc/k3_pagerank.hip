@@ -379,6 +379,101 @@ __global__ __launch_bounds__(256) void k_init_write(int64_t n, int32_t nrhs, uin
   }
 }
 
+// ------------------------------------------------------ vertex relabelling
+// Graph500-style random labels scatter the high-degree sources over all of
+// r, so nearly every gather r[u] misses L2 and moves a 128 B line.  When the
+// caller passes per-vertex weights (pp_filter's d_out: the number of kept
+// edges leaving u, i.e. how often r[u] is gathered), K3 relabels vertices by
+// decreasing floor(log2(weight + 1)) -- a stable bucket order, ties in label
+// order -- and iterates on P A^T P^T.  Hot sources then share cache lines.
+// Rows are permuted with the same map, so x and y stay in one numbering; r
+// is permuted in before the first iteration and out after the last.
+
+// key = bucket << 32 | v, bucket = clz(weight + 1): hotter sorts first.
+__global__ __launch_bounds__(256) void k_order_keys(const int32_t *__restrict__ w, int32_t n,
+                                                    uint64_t *__restrict__ keys) {
+  for (int32_t v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256) {
+    const int32_t wv = w[v] > 0 ? w[v] : 0;
+    const uint32_t b = uint32_t(__clz(int(uint32_t(wv) + 1u)));
+    keys[v] = (uint64_t(b) << 32) | uint32_t(v);
+  }
+}
+
+// order[p] = old label at new position p; newlabel[old] = p; row lengths in
+// the new order (into rp2, scanned afterwards).
+__global__ __launch_bounds__(256) void k_relabel_maps(const uint64_t *__restrict__ keys,
+                                                      const int32_t *__restrict__ rp, int32_t n,
+                                                      int32_t *__restrict__ order,
+                                                      int32_t *__restrict__ newlabel,
+                                                      uint32_t *__restrict__ len2) {
+  for (int32_t p = blockIdx.x * 256 + threadIdx.x; p < n; p += gridDim.x * 256) {
+    const int32_t o = int32_t(keys[p] & 0xFFFFFFFFull);
+    order[p] = o;
+    newlabel[o] = p;
+    len2[p] = uint32_t(rp[o + 1] - rp[o]);
+  }
+}
+
+__global__ void k_set_total(int32_t *rp2, int32_t n, const int64_t *total) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) rp2[n] = int32_t(*total);
+}
+
+// Entries of the relabelled matrix, one thread per entry q of the new
+// layout (balanced by the same merge-path partition the SpMV uses): its row
+// p is found in the workgroup's staged row ends, its source position is the
+// same offset inside old row order[p], its column is newlabel[col].
+template <typename V>
+__global__ __launch_bounds__(kThreads) void k_relabel_copy(
+    const int32_t *__restrict__ rp, const int32_t *__restrict__ col, const V *__restrict__ val,
+    const int32_t *__restrict__ order, const int32_t *__restrict__ newlabel,
+    const int32_t *__restrict__ rp2, int32_t n, const int2 *__restrict__ coord,
+    int32_t *__restrict__ col2, V *__restrict__ val2) {
+  __shared__ int32_t s_end[kItems];
+  __shared__ int32_t s_old[kItems + 1];
+  __shared__ int32_t s_new[kItems + 1];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int2 c0 = coord[b], c1 = coord[b + 1];
+  const int32_t i0 = c0.x, j0 = c0.y, na = c1.x - c0.x, nz = c1.y - c0.y;
+  for (int k = tid; k <= na; k += kThreads) {
+    const int32_t row = i0 + k;
+    if (row < n) {
+      s_new[k] = rp2[row];
+      s_old[k] = rp[order[row]];
+    }
+    if (k < na) s_end[k] = rp2[row + 1];
+  }
+  __syncthreads();
+  for (int32_t q = j0 + tid; q < j0 + nz; q += kThreads) {
+    int32_t lo = 0, hi = na;
+    while (lo < hi) {
+      const int32_t m = (lo + hi) >> 1;
+      if (s_end[m] <= q)
+        lo = m + 1;
+      else
+        hi = m;
+    }
+    const int32_t src = s_old[lo] + (q - s_new[lo]);
+    col2[q] = newlabel[col[src]];
+    val2[q] = val[src];
+  }
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_permute_in(const V *__restrict__ src,
+                                                    const int32_t *__restrict__ order, int32_t n,
+                                                    V *__restrict__ dst) {
+  for (int32_t p = blockIdx.x * 256 + threadIdx.x; p < n; p += gridDim.x * 256)
+    dst[p] = src[order[p]];
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_permute_out(const V *__restrict__ src,
+                                                     const int32_t *__restrict__ order, int32_t n,
+                                                     V *__restrict__ dst) {
+  for (int32_t p = blockIdx.x * 256 + threadIdx.x; p < n; p += gridDim.x * 256)
+    dst[order[p]] = src[p];
+}
+
 // Optional event pairs around each SpMV launch (benchmark instrumentation).
 struct Timing {
   bool on = false;
@@ -410,10 +505,18 @@ struct Layout {
   double *blk_ysum, *part, *tele;
   uint32_t *counter;
   unsigned long long *ksum;
+  // vertex relabelling
+  uint64_t *keys_in, *keys_out;
+  void *radix_ws;
+  size_t radix_bytes;
+  int32_t *order, *newlabel, *rp2, *col2;
+  V *val2, *x2;
+  int64_t *total;
 };
 
+// One layout function serves both measuring (ws == nullptr) and carving.
 template <typename V>
-Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs) {
+Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs, size_t *bytes = nullptr) {
   using Acc = typename Form<V>::Acc;
   Carve c(ws);
   Layout<V> L{};
@@ -423,6 +526,7 @@ Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs) {
   L.ksum = c.take<unsigned long long>(64);
   L.counter = c.take<uint32_t>(4);
   L.tele = c.take<double>(2 * 64);
+  L.total = c.take<int64_t>(1);
   L.y = c.take<V>(size_t(n) * nrhs);
   L.coord = c.take<int2>(size_t(nb + 1));
   L.closes = c.take<uint8_t>(size_t(nb));
@@ -431,68 +535,101 @@ Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs) {
   L.blk_head = c.take<Acc>(size_t(nb));
   L.blk_ysum = c.take<double>(size_t(nb));
   L.part = c.take<double>(size_t(G > G0 ? G : G0));
+  L.keys_in = c.take<uint64_t>(size_t(n));
+  L.keys_out = c.take<uint64_t>(size_t(n));
+  L.radix_bytes = radix_ws_bytes(n, 31) + scan_ws_elems(n) * 4 + 256;
+  L.radix_ws = c.take<uint8_t>(L.radix_bytes);
+  L.order = c.take<int32_t>(size_t(n));
+  L.newlabel = c.take<int32_t>(size_t(n));
+  L.rp2 = c.take<int32_t>(size_t(n + 1));
+  L.col2 = c.take<int32_t>(size_t(nnz_cap > 0 ? nnz_cap : 1));
+  L.val2 = c.take<V>(size_t(nnz_cap > 0 ? nnz_cap : 1));
+  L.x2 = c.take<V>(size_t(n) * nrhs);
+  if (bytes) *bytes = c.bytes();
   return L;
 }
 
 template <typename V>
 size_t ws_bytes_t(int64_t n, int64_t nnz_cap, int32_t nrhs) {
-  Carve c(nullptr);
-  using Acc = typename Form<V>::Acc;
-  const int64_t nb = (n + nnz_cap + kItems - 1) / kItems + 1;
-  const int64_t G = (nb + kFinishPer - 1) / kFinishPer + 1;
-  const int64_t G0 = (n + kSumChunk - 1) / kSumChunk + 1;
-  c.take<unsigned long long>(64);
-  c.take<uint32_t>(4);
-  c.take<double>(2 * 64);
-  c.take<V>(size_t(n) * nrhs);
-  c.take<int2>(size_t(nb + 1));
-  c.take<uint8_t>(size_t(nb));
-  c.take<int32_t>(size_t(nb));
-  c.take<Acc>(size_t(nb));
-  c.take<Acc>(size_t(nb));
-  c.take<double>(size_t(nb));
-  c.take<double>(size_t(G > G0 ? G : G0));
-  return c.bytes();
+  size_t b = 0;
+  carve<V>(nullptr, n, nnz_cap, nrhs, &b);
+  return b;
 }
 
 template <typename V>
-pp_status run_pagerank(const pp_csr &AT, int32_t iters, double c, V *r, double *sums, void *ws,
-                       size_t ws_bytes, hipStream_t s) {
-  const int64_t n = AT.n, nnz = AT.nnz;
+pp_status run_pagerank(const pp_csr &AT0, int32_t iters, double c, const int32_t *weights, V *r,
+                       double *sums, void *ws, size_t ws_bytes, hipStream_t s) {
+  const int64_t n = AT0.n, nnz = AT0.nnz;
   if (ws_bytes < ws_bytes_t<V>(n, nnz, 1)) return fail(PP_EWORKSPACE, "pagerank workspace too small");
   Layout<V> L = carve<V>(ws, n, nnz, 1);
   const int32_t nb = int32_t((n + nnz + kItems - 1) / kItems);
   const int32_t G = (nb + kFinishPer - 1) / kFinishPer;
   const double w = (1.0 - c) / double(n);
+  const int32_t n32 = int32_t(n);
+  const int gN = grid_for(n, 256, 8192);
   pp_status st;
   if ((st = fill_i32(reinterpret_cast<int32_t *>(L.counter), 4, 0, s)) != PP_OK) return st;
 
+  // The matrix the iterations run on, and the vector they start from.
+  const int32_t *rp = AT0.row_ptr, *col = AT0.col;
+  const V *val = static_cast<const V *>(AT0.val);
+  V *x0 = r;
+  if (weights) {
+    hipLaunchKernelGGL(k_order_keys, dim3(gN), dim3(256), 0, s, weights, n32, L.keys_in);
+    PP_LAUNCHED("k_order_keys");
+    st = radix_sort(RadixIn{L.keys_in, nullptr, nullptr}, RadixOut{L.keys_out, nullptr, nullptr},
+                    n, 5, L.radix_ws, L.radix_bytes, 0, false, nullptr, s, false);
+    if (st != PP_OK) return st;
+    hipLaunchKernelGGL(k_relabel_maps, dim3(gN), dim3(256), 0, s, L.keys_out, AT0.row_ptr, n32,
+                       L.order, L.newlabel, reinterpret_cast<uint32_t *>(L.rp2));
+    PP_LAUNCHED("k_relabel_maps");
+    st = exscan_u32(reinterpret_cast<uint32_t *>(L.rp2), reinterpret_cast<uint32_t *>(L.rp2), n,
+                    reinterpret_cast<uint32_t *>(L.keys_in), L.total, s);
+    if (st != PP_OK) return st;
+    hipLaunchKernelGGL(k_set_total, dim3(1), dim3(64), 0, s, L.rp2, n32, L.total);
+    rp = L.rp2;
+    col = L.col2;
+    val = L.val2;
+    x0 = L.x2;
+  }
+
   hipLaunchKernelGGL(k_partition, dim3(grid_for(int64_t(nb) + 1, 256, 4096)), dim3(256), 0, s,
-                     AT.row_ptr, int32_t(n), int32_t(nnz), nb, L.coord);
-  hipLaunchKernelGGL(k_block_flags, dim3(grid_for(nb, 256, 4096)), dim3(256), 0, s, AT.row_ptr,
-                     int32_t(n), nb, L.coord, L.carry_row, L.closes);
+                     rp, n32, int32_t(nnz), nb, L.coord);
+  hipLaunchKernelGGL(k_block_flags, dim3(grid_for(nb, 256, 4096)), dim3(256), 0, s, rp, n32, nb,
+                     L.coord, L.carry_row, L.closes);
   PP_LAUNCHED("k_partition/k_block_flags");
+  if (weights) {
+    hipLaunchKernelGGL(k_relabel_copy<V>, dim3(nb), dim3(kThreads), 0, s, AT0.row_ptr, AT0.col,
+                       static_cast<const V *>(AT0.val), L.order, L.newlabel, L.rp2, n32, L.coord,
+                       L.col2, L.val2);
+    hipLaunchKernelGGL(k_permute_in<V>, dim3(gN), dim3(256), 0, s, r, L.order, n32, L.x2);
+    PP_LAUNCHED("k_relabel_copy/k_permute_in");
+  }
 
   const int G0 = int((n + kSumChunk - 1) / kSumChunk);
-  hipLaunchKernelGGL(k_sum0<V>, dim3(G0), dim3(kThreads), 0, s, r, n, kSumChunk, L.part, L.counter,
-                     w, sums, L.tele);
+  hipLaunchKernelGGL(k_sum0<V>, dim3(G0), dim3(kThreads), 0, s, x0, n, kSumChunk, L.part,
+                     L.counter, w, sums, L.tele);
   PP_LAUNCHED("k_sum0");
 
-  const V *val = static_cast<const V *>(AT.val);
   g_timing.used = 0;
   for (int32_t k = 0; k < iters; ++k) {
-    const V *x = (k & 1) ? L.y : r;
-    V *yv = (k & 1) ? r : L.y;
+    const V *x = (k & 1) ? L.y : x0;
+    V *yv = (k & 1) ? x0 : L.y;
     if ((st = timed_begin(s)) != PP_OK) return st;
-    hipLaunchKernelGGL((k_spmv<V, kIpt>), dim3(nb), dim3(kThreads), 0, s, AT.row_ptr, AT.col, val, x, yv,
-                       int32_t(n), L.coord, c, L.tele + (k & 1), L.blk_ysum, L.blk_carry,
-                       L.blk_head);
+    hipLaunchKernelGGL((k_spmv<V, kIpt>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x, yv,
+                       n32, L.coord, c, L.tele + (k & 1), L.blk_ysum, L.blk_carry, L.blk_head);
     if ((st = timed_end(s)) != PP_OK) return st;
     hipLaunchKernelGGL(k_finish<V>, dim3(G), dim3(kThreads), 0, s, yv, nb, L.coord, L.closes,
                        L.carry_row, L.blk_carry, L.blk_head, L.blk_ysum, c, L.tele + (k & 1),
                        L.part, L.counter, w, sums ? sums + k + 1 : nullptr,
                        L.tele + ((k + 1) & 1));
     PP_LAUNCHED("k_spmv/k_finish");
+  }
+  const V *last = (iters & 1) ? L.y : x0;
+  if (weights) {
+    hipLaunchKernelGGL(k_permute_out<V>, dim3(gN), dim3(256), 0, s, last, L.order, n32, r);
+    PP_LAUNCHED("k_permute_out");
+    return PP_OK;
   }
   if (iters & 1) return copy_bytes(r, L.y, size_t(n) * sizeof(V), s);
   return PP_OK;
@@ -549,11 +686,13 @@ pp_status launch_init_r(int64_t n, int32_t nrhs, uint64_t seed, pp_dtype dt, voi
 }
 
 pp_status launch_pagerank(const pp_csr &AT, pp_dtype dt, int32_t nrhs, int32_t iters, double c,
-                          void *r, double *sums, void *ws, size_t ws_bytes, hipStream_t s) {
+                          const int32_t *weights, void *r, double *sums, void *ws, size_t ws_bytes,
+                          hipStream_t s) {
   if (nrhs != 1) return fail(PP_EINVAL, "nrhs %d: only the single-vector form is built", nrhs);
   if (dt == PP_F64)
-    return run_pagerank<double>(AT, iters, c, static_cast<double *>(r), sums, ws, ws_bytes, s);
-  return run_pagerank<float>(AT, iters, c, static_cast<float *>(r), sums, ws, ws_bytes, s);
+    return run_pagerank<double>(AT, iters, c, weights, static_cast<double *>(r), sums, ws,
+                                ws_bytes, s);
+  return run_pagerank<float>(AT, iters, c, weights, static_cast<float *>(r), sums, ws, ws_bytes, s);
 }
 
 }  // namespace pp

@@ -131,7 +131,8 @@ pp_status pp_init_r(int64_t n, int32_t nrhs, uint64_t seed, pp_dtype dt, void *r
 }
 
 pp_status pp_pagerank(const pp_csr *AT, pp_dtype dt, int32_t nrhs, int32_t iters, double c,
-                      void *r, double *sums, void *ws, size_t ws_bytes, void *stream) {
+                      const int32_t *order_weights, void *r, double *sums, void *ws,
+                      size_t ws_bytes, void *stream) {
   if (!AT || !AT->row_ptr || !r) return fail(PP_EINVAL, "pp_pagerank: null argument");
   if (dt != PP_F64 && dt != PP_F32) return fail(PP_EINVAL, "pp_pagerank: dtype %d", int(dt));
   if (AT->n < 1 || AT->n > (int64_t(1) << 30)) return fail(PP_ERANGE, "pp_pagerank: n = %lld", (long long)AT->n);
@@ -143,7 +144,8 @@ pp_status pp_pagerank(const pp_csr *AT, pp_dtype dt, int32_t nrhs, int32_t iters
   if (!(c >= 0.0 && c <= 1.0)) return fail(PP_EINVAL, "pp_pagerank: c = %g", c);
   const size_t need = pagerank_ws_bytes(AT->n, AT->nnz, dt, nrhs);
   if (!ws || ws_bytes < need) return fail(PP_EWORKSPACE, "pp_pagerank: workspace needs %zu bytes", need);
-  return launch_pagerank(*AT, dt, nrhs, iters, c, r, sums, ws, ws_bytes, as_stream(stream));
+  return launch_pagerank(*AT, dt, nrhs, iters, c, order_weights, r, sums, ws, ws_bytes,
+                         as_stream(stream));
 }
 
 pp_status pp_set_kernel_timing(int enable) { return set_kernel_timing(enable != 0); }

@@ -194,7 +194,8 @@ size_t pagerank_ws_bytes(int64_t n, int64_t nnz_cap, pp_dtype dt, int32_t nrhs);
 pp_status launch_init_r(int64_t n, int32_t nrhs, uint64_t seed, pp_dtype dt, void *r,
                         void *ws, size_t ws_bytes, hipStream_t s);
 pp_status launch_pagerank(const pp_csr &AT, pp_dtype dt, int32_t nrhs, int32_t iters, double c,
-                          void *r, double *sums, void *ws, size_t ws_bytes, hipStream_t s);
+                          const int32_t *weights, void *r, double *sums, void *ws, size_t ws_bytes,
+                          hipStream_t s);
 pp_status set_kernel_timing(bool enable);
 int32_t kernel_times(float *ms, int32_t cap);
 

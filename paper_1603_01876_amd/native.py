@@ -60,7 +60,7 @@ SIGNATURES = {
                                  _VP, _VP, _VP, _SZ, _VP]),
     "pp_init_r": (ctypes.c_int, [_I64, _I32, _U64, ctypes.c_int, _VP, _VP, _SZ, _VP]),
     "pp_pagerank": (ctypes.c_int, [ctypes.POINTER(_Csr), ctypes.c_int, _I32, _I32, _D, _VP,
-                                   _VP, _VP, _SZ, _VP]),
+                                   _VP, _VP, _VP, _SZ, _VP]),
     "pp_set_kernel_timing": (ctypes.c_int, [ctypes.c_int]),
     "pp_kernel_times": (_I32, [ctypes.POINTER(ctypes.c_float), _I32]),
 }
@@ -214,9 +214,10 @@ def init_r(n: int, seed: int, dtype="f64", nrhs: int = 1, out=None, ws=None, dev
     return out
 
 
-def pagerank(AT: CSR, r, iters: int = 20, c: float = 0.85, sums=True, ws=None):
+def pagerank(AT: CSR, r, iters: int = 20, c: float = 0.85, sums=True, ws=None, weights=None):
     """K3: iterates r in place; returns sum(r) per iteration ((iters+1) x nrhs
-    FP64 tensor) or None when sums is False."""
+    FP64 tensor) or None when sums is False.  `weights` (int32 per vertex,
+    e.g. d_out from filter()) turns on the locality relabelling."""
     dt = dtype_code(r.dtype)
     if dt != AT.dtype:
         raise PPError(PP_EINVAL, "pagerank", "r and matrix values differ in dtype")
@@ -228,8 +229,8 @@ def pagerank(AT: CSR, r, iters: int = 20, c: float = 0.85, sums=True, ws=None):
         sums = None
     ws = _ws(workspace_bytes(K3, AT.n, AT.nnz, dt, nrhs), ws, r.device)
     cs = AT._c()
-    _check(lib().pp_pagerank(ctypes.byref(cs), dt, nrhs, iters, c, _ptr(r), _ptr(sums),
-                             _ptr(ws), ws.numel(), _stream()), "pp_pagerank")
+    _check(lib().pp_pagerank(ctypes.byref(cs), dt, nrhs, iters, c, _ptr(weights), _ptr(r),
+                             _ptr(sums), _ptr(ws), ws.numel(), _stream()), "pp_pagerank")
     return sums
 
 

@@ -63,11 +63,6 @@ def test_workspace_sizes():
         native.workspace_bytes(native.K3, n, m, "f32", nrhs=65)
 
 
-def _err(fn, *args):
-    st = fn(*args)
-    return st
-
-
 def test_generate_rejects_bad_params():
     L = native.lib()
     p = native._Kron(0, 16, 0.57, 0.19, 0.19, 0.05, 1)
@@ -111,22 +106,20 @@ def test_filter_rejects_bad_args():
 def test_pagerank_rejects_bad_args():
     L = native.lib()
     c = native._Csr(1000, 10, 100, 8, 16, 24)
-    ok = dict(dt=0, nrhs=1, iters=20, c=0.85)
-    assert L.pp_pagerank(ctypes.byref(c), 0, 0, 20, 0.85, 8, None, 64, 1 << 30,
+    assert L.pp_pagerank(ctypes.byref(c), 0, 0, 20, 0.85, None, 8, None, 64, 1 << 30,
                          None) == native.PP_EINVAL
-    assert L.pp_pagerank(ctypes.byref(c), 0, 1, -1, 0.85, 8, None, 64, 1 << 30,
+    assert L.pp_pagerank(ctypes.byref(c), 0, 1, -1, 0.85, None, 8, None, 64, 1 << 30,
                          None) == native.PP_EINVAL
-    assert L.pp_pagerank(ctypes.byref(c), 0, 1, 20, 1.5, 8, None, 64, 1 << 30,
+    assert L.pp_pagerank(ctypes.byref(c), 0, 1, 20, 1.5, None, 8, None, 64, 1 << 30,
                          None) == native.PP_EINVAL
-    assert L.pp_pagerank(ctypes.byref(c), 0, 1, 20, 0.85, 8, None, 64, 10,
+    assert L.pp_pagerank(ctypes.byref(c), 0, 1, 20, 0.85, None, 8, None, 64, 10,
                          None) == native.PP_EWORKSPACE
     over = native._Csr(1000, 200, 100, 8, 16, 24)
-    assert L.pp_pagerank(ctypes.byref(over), 0, 1, 20, 0.85, 8, None, 64, 1 << 30,
+    assert L.pp_pagerank(ctypes.byref(over), 0, 1, 20, 0.85, None, 8, None, 64, 1 << 30,
                          None) == native.PP_EINVAL
     big = native._Csr(1 << 30, (1 << 31) - 10, 1 << 31, 8, 16, 24)
-    assert L.pp_pagerank(ctypes.byref(big), 0, 1, 20, 0.85, 8, None, 64, 1 << 30,
+    assert L.pp_pagerank(ctypes.byref(big), 0, 1, 20, 0.85, None, 8, None, 64, 1 << 30,
                          None) == native.PP_ERANGE
-    assert ok
 
 
 def test_init_r_rejects_bad_args():

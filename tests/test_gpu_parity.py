@@ -192,13 +192,15 @@ def test_init_r_matches_oracle(n, nrhs):
 
 
 # --------------------------------------------------------------- K3 iterate
-def run_k3(n, A_rp, A_col, A_val, dtype, iters=20, seed=7):
+def run_k3(n, A_rp, A_col, A_val, dtype, iters=20, seed=7, weights=None):
     """GPU K3 on CSR(A^T) built from the oracle's CSR(A); returns the GPU
-    ranks, GPU sums and the oracle's ranks and sums."""
+    ranks, GPU sums and the oracle's ranks and sums.  `weights` (host
+    array) turns on the vertex relabelling inside K3."""
     trp, tcol, tval = oracle.transpose_csr(n, A_rp, A_col, A_val)
     AT = pp.CSR.from_arrays(n, trp, tcol, tval, dtype)
     r = pp.init_r(n, seed, dtype)
-    sums = pp.pagerank(AT, r, iters=iters, c=C)
+    w = None if weights is None else dev(weights, torch.int32)
+    sums = pp.pagerank(AT, r, iters=iters, c=C, weights=w)
     want, wsums = oracle.pagerank(n, A_rp, A_col, A_val, oracle.init_r(n, seed), iters, C)
     return host(r), host(sums), want, wsums
 
@@ -211,6 +213,24 @@ def test_pagerank_on_kronecker_matrix(scale, dtype):
     ous, ovs = oracle.sort(scale, ou, ov)
     f = oracle.filter(scale, ous, ovs)
     got, sums, want, wsums = run_k3(f.n, f.A_rp, f.A_col, f.A_val, dtype)
+    assert rel_l1(got, want) <= TOL[dtype]
+    assert np.abs(sums / wsums - 1).max() <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("scale,kind", [(16, "d_out"), (16, "random"), (10, "negative"),
+                                        (20, "d_out"), (1, "d_out")])
+def test_pagerank_relabelled(scale, kind, dtype):
+    # Relabelling by weights only changes speed and summation order.
+    s = spec(scale)
+    ou, ov = oracle.generate(okron(s))
+    ous, ovs = oracle.sort(scale, ou, ov)
+    f = oracle.filter(scale, ous, ovs)
+    rng = np.random.default_rng(scale)
+    w = {"d_out": f.d_out,
+         "random": rng.integers(0, 1 << 20, f.n),
+         "negative": rng.integers(-5, 5, f.n)}[kind]
+    got, sums, want, wsums = run_k3(f.n, f.A_rp, f.A_col, f.A_val, dtype, weights=w)
     assert rel_l1(got, want) <= TOL[dtype]
     assert np.abs(sums / wsums - 1).max() <= TOL[dtype]
 
@@ -260,6 +280,10 @@ def test_pagerank_structured_matrices(case, dtype):
         n = 12345
         rp, col, val = random_matrix(n, rng, long_rows=[(0, 2048), (1, 2049), (2, 2047)])
     got, sums, want, wsums = run_k3(n, rp, col, val, dtype)
+    assert rel_l1(got, want) <= TOL[dtype]
+    assert np.abs(sums / wsums - 1).max() <= TOL[dtype]
+    w = np.bincount(col, minlength=n)          # gather counts as weights
+    got, sums, want, wsums = run_k3(n, rp, col, val, dtype, weights=w)
     assert rel_l1(got, want) <= TOL[dtype]
     assert np.abs(sums / wsums - 1).max() <= TOL[dtype]
 
@@ -324,7 +348,7 @@ def test_pipeline_end_to_end(scale, dtype):
     us, vs = pp.sort(scale, u, v)
     AT, d_in, d_out = pp.filter(scale, us, vs, dtype)
     r = pp.init_r(AT.n, 11, dtype)
-    sums = pp.pagerank(AT, r)
+    sums = pp.pagerank(AT, r, weights=d_out)
 
     ou, ov = oracle.generate(okron(s))
     ous, ovs = oracle.sort(scale, ou, ov)
