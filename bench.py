@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--no-f64-side", action="store_true", help="skip the FP64 side-by-side run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-RHS form (S=22, 32 right-hand sides)")
+    ap.add_argument("--batched-scale", type=int, default=22)
+    ap.add_argument("--nrhs", type=int, default=32)
     ap.add_argument("--no-relabel", action="store_true",
                     help="iterate on K2's labels (no degree-ordered relabelling inside K3)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -80,6 +84,63 @@ def measured_traffic(scale: int, dtype: str):
     if fields.get("kernel_source_sha256") != sha:
         return None
     return (float(fields["fetch_bytes_per_launch"]) + float(fields["write_bytes_per_launch"])) / 1e9
+
+
+def batched_form(args, pp, workloads, torch):
+    """K3 with nrhs independent vectors on one S=22 matrix (one SpMM per
+    iteration) beside nrhs-times the single-vector FP32 run."""
+    S, k, dev = args.batched_scale, args.nrhs, "cuda"
+    spec = workloads.pipeline(S)
+    n, m = spec.n, spec.m
+    u, v = pp.generate(spec)
+    us, vs = pp.sort(S, u, v)
+    del u, v
+    AT, _, d_out = pp.filter(S, us, vs, "f32")
+    del us, vs
+    w = None if args.no_relabel else d_out
+    ws = torch.empty(pp.workspace_bytes(pp.K3, n, AT.nnz, "f32", k), dtype=torch.uint8, device=dev)
+    rk = torch.empty((n, k), dtype=torch.float32, device=dev)
+    r1 = torch.empty(n, dtype=torch.float32, device=dev)
+
+    def timed(fn, reps=3):
+        ts, kt = [], []
+        pp.set_kernel_timing(True)
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            kt += pp.kernel_times()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        pp.set_kernel_timing(False)
+        return sum(ts) / len(ts), sum(kt) / len(kt) / 1e3
+
+    def run_k():
+        pp.init_r(n, workloads.BASE_SEED, "f32", k, out=rk, ws=ws)
+        pp.pagerank(AT, rk, iters=args.iters, c=workloads.DAMPING, sums=False, ws=ws, weights=w)
+
+    def run_1():
+        pp.init_r(n, workloads.BASE_SEED, "f32", 1, out=r1, ws=ws)
+        pp.pagerank(AT, r1, iters=args.iters, c=workloads.DAMPING, sums=False, ws=ws, weights=w)
+
+    run_k()
+    run_1()
+    tk, kk = timed(run_k)
+    t1, k1 = timed(run_1)
+    err = float((rk[:, 0].double() - r1.double()).abs().sum() / r1.double().abs().sum())
+    nbytes = 4 * (n + 1) + 8 * AT.nnz + 8 * n * k
+    out = {"workload": f"kron-s{S}-f32-rhs{k}", "nrhs": k, "nnz_filtered": AT.nnz,
+           "k3_ms": tk * 1e3, "rhs_edges_per_s": args.iters * m * k / tk,
+           "single_rhs_k3_ms": t1 * 1e3, "single_rhs_edges_per_s": args.iters * m / t1,
+           "per_rhs_speedup_over_single": t1 * k / tk,
+           "spmm_avg_ms": kk * 1e3, "spmm_GBps": nbytes / kk / 1e9,
+           "spmm_frac_of_peak": nbytes / kk / 1e9 / HBM_PEAK_GBS,
+           "spmm_algorithmic_bytes_per_launch": nbytes,
+           "rel_l1_rhs0_vs_single_f32": err}
+    del AT, ws, rk, r1, d_out
+    torch.cuda.empty_cache()
+    return out
 
 
 def spmv_bytes(n: int, nnz: int, dtype: str) -> int:
@@ -286,6 +347,11 @@ def main():
             "f32_rel_l1_vs_f64_gpu": err,
         }
         del AT64, ws64
+
+    if not args.no_batched:
+        log("batched right-hand sides")
+        torch.cuda.empty_cache()
+        out.setdefault("forms", {})["batched_rhs"] = batched_form(args, pp, workloads, torch)
 
     if not args.no_cpu:
         log("CPU oracle baseline")

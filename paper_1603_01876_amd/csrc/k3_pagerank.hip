@@ -266,6 +266,227 @@ __global__ __launch_bounds__(kThreads) void k_spmv(
   if (tid == 0) blk_ysum[b] = bs;
 }
 
+// ------------------------------------------------------------------ SpMM
+// Y = c * A^T X + t_j per column j, X and Y n x k row-major, k = nrhs in
+// 2..64 independent PageRank vectors on one matrix.  The workgroup stages
+// the same merge-path item range as the SpMV (columns, values, row ends),
+// but each item is processed by a group of G = nextpow2(k) lanes, lane l
+// owning right-hand side l: a non-zero gathers the k consecutive values of
+// row col of X (one 128 B line at k = 32), so the gather moves only useful
+// bytes.  Each group walks its items in order and keeps U gathers in
+// flight.  Carries between groups and workgroups, the per-column FP64
+// sum(y) and the per-column teleport scalar work as in the SpMV.
+template <typename V, int G>
+__global__ __launch_bounds__(kThreads) void k_spmm(
+    const int32_t *__restrict__ rp, const int32_t *__restrict__ col, const V *__restrict__ val,
+    const V *__restrict__ x, V *__restrict__ y, int32_t n, int32_t k,
+    const int2 *__restrict__ coord, double c, const double *__restrict__ tele,
+    double *__restrict__ blk_ysum, typename Form<V>::Acc *__restrict__ blk_carry,
+    typename Form<V>::Acc *__restrict__ blk_head) {
+  using Acc = typename Form<V>::Acc;
+  constexpr int NG = kThreads / G;  // lane groups per workgroup
+  constexpr int P = kItems / NG;    // merge items per group
+  constexpr int U = 8;              // gathers in flight per lane
+  __shared__ int32_t s_end[kItems];
+  __shared__ int32_t s_col[kItems];
+  __shared__ V s_val[kItems];
+  __shared__ Acc s_carry[kThreads];
+  __shared__ int32_t s_key[NG];
+  __shared__ double s_ysum[kThreads];
+
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int g = tid / G, l = tid % G;
+  const bool active = l < k;
+  const int2 c0 = coord[b], c1 = coord[b + 1];
+  const int32_t i0 = c0.x, j0 = c0.y;
+  const int32_t na = c1.x - c0.x, nz = c1.y - c0.y;
+  for (int q = tid; q < nz; q += kThreads) {
+    s_col[q] = __builtin_nontemporal_load(col + j0 + q);
+    s_val[q] = __builtin_nontemporal_load(val + j0 + q);
+  }
+  for (int q = tid; q < na; q += kThreads) s_end[q] = rp[i0 + 1 + q] - j0;
+  const bool mid_row = i0 < n && rp[i0] < j0;
+  const double tk = active ? tele[l] : 0.0;
+  __syncthreads();
+
+  const int32_t tot = na + nz;
+  int32_t d = g * P < tot ? g * P : tot;
+  const int32_t dend = d + P < tot ? d + P : tot;
+  int32_t lo = d - nz > 0 ? d - nz : 0, hi = d < na ? d : na;
+  while (lo < hi) {
+    const int32_t m = (lo + hi) >> 1;
+    if (s_end[m] <= d - m - 1)
+      lo = m + 1;
+    else
+      hi = m;
+  }
+  int32_t ti = lo, tj = d - lo;
+
+  Acc acc{}, first{};
+  int32_t first_row = -1;
+  double ysum = 0.0;
+  while (d < dend) {
+    V buf[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t q = tj + u < nz ? tj + u : nz - 1;
+      buf[u] = (active && q >= 0) ? x[int64_t(s_col[q]) * k + l] : V(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      while (d < dend && ti < na && s_end[ti] <= tj) {
+        if (first_row < 0) {
+          first_row = ti;
+          first = acc;
+        } else if (active) {
+          const V yv = Form<V>::finish(acc, c, tk);
+          y[int64_t(i0 + ti) * k + l] = yv;
+          ysum += double(yv);
+        }
+        acc = Acc{};
+        ++ti;
+        ++d;
+      }
+      if (d < dend) {
+        acc.add(buf[u] * s_val[tj]);
+        ++tj;
+        ++d;
+      }
+    }
+  }
+  s_carry[tid] = acc;
+  if (l == 0) s_key[g] = i0 + ti;
+  __syncthreads();
+
+  if (first_row >= 0 && active) {
+    const int32_t R = i0 + first_row;
+    int gg = g - 1;
+    while (gg >= 0 && s_key[gg] == R) --gg;
+    Acc sum{};
+    for (int q = gg + 1; q < g; ++q) sum = merge(sum, s_carry[q * G + l]);
+    sum = merge(sum, first);
+    if (R == i0 && mid_row) {
+      blk_head[int64_t(b) * k + l] = sum;
+    } else {
+      const V yv = Form<V>::finish(sum, c, tk);
+      y[int64_t(R) * k + l] = yv;
+      ysum += double(yv);
+    }
+  }
+  if (g == NG - 1 && active) {
+    Acc sum{};
+    if (c1.x < n) {
+      int gg = NG - 1;
+      while (gg >= 0 && s_key[gg] == c1.x) --gg;
+      for (int q = gg + 1; q < NG; ++q) sum = merge(sum, s_carry[q * G + l]);
+    }
+    blk_carry[int64_t(b) * k + l] = sum;
+  }
+  s_ysum[tid] = ysum;
+  __syncthreads();
+  if (tid < k) {
+    double t = 0.0;
+    for (int q = 0; q < NG; ++q) t += s_ysum[q * G + tid];
+    blk_ysum[int64_t(b) * k + tid] = t;
+  }
+}
+
+// Per-column completion of rows spanning workgroups and per-column sum(y).
+template <typename V>
+__global__ __launch_bounds__(kThreads) void k_finish_mm(
+    V *__restrict__ y, int32_t nb, int32_t k, int32_t G, const int2 *__restrict__ coord,
+    const uint8_t *__restrict__ closes, const int32_t *__restrict__ carry_row,
+    const typename Form<V>::Acc *__restrict__ blk_carry,
+    const typename Form<V>::Acc *__restrict__ blk_head, const double *__restrict__ blk_ysum,
+    double c, const double *__restrict__ tele_in, double *part, uint32_t *counter, double w,
+    double *sum_out, double *tele_out) {
+  using Acc = typename Form<V>::Acc;
+  __shared__ double sh[kThreads];
+  __shared__ bool is_last;
+  const int g = blockIdx.x, tid = threadIdx.x;
+  const int slots = kThreads / G, slot = tid / G, j = tid % G;
+  const int64_t lo = int64_t(g) * kFinishPer;
+  const int64_t hi = lo + kFinishPer < nb ? lo + kFinishPer : nb;
+  double acc = 0.0;
+  if (j < k) {
+    const double tk = tele_in[j];
+    for (int64_t b = lo + slot; b < hi; b += slots) {
+      double v = blk_ysum[b * k + j];
+      if (closes[b]) {
+        const int32_t R = coord[b].x;
+        int64_t q = b - 1;
+        while (q >= 0 && carry_row[q] == R) --q;
+        Acc sum{};
+        for (int64_t t = q + 1; t < b; ++t) sum = merge(sum, blk_carry[t * k + j]);
+        sum = merge(sum, blk_head[b * k + j]);
+        const V yv = Form<V>::finish(sum, c, tk);
+        y[int64_t(R) * k + j] = yv;
+        v += double(yv);
+      }
+      acc += v;
+    }
+  }
+  sh[tid] = acc;
+  __syncthreads();
+  if (tid < k) {
+    double t = 0.0;
+    for (int q = 0; q < slots; ++q) t += sh[q * G + tid];
+    part[int64_t(g) * k + tid] = t;
+    __threadfence();
+  }
+  __syncthreads();
+  if (tid == 0) is_last = atomicAdd(counter, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (is_last) {
+    __threadfence();
+    if (tid < k) {
+      double t = 0.0;
+      for (int q = 0; q < int(gridDim.x); ++q) t += load_acquire(part + int64_t(q) * k + tid);
+      if (sum_out) sum_out[tid] = t;
+      tele_out[tid] = w * t;
+    }
+    if (tid == 0) *counter = 0u;
+  }
+}
+
+// Per-column sum of the n x k starting block.
+template <typename V>
+__global__ __launch_bounds__(kThreads) void k_sum0_mm(const V *__restrict__ r, int64_t n, int32_t k,
+                                                      int32_t G, int64_t chunk, double *part,
+                                                      uint32_t *counter, double w, double *sum_out,
+                                                      double *tele_out) {
+  __shared__ double sh[kThreads];
+  __shared__ bool is_last;
+  const int g = blockIdx.x, tid = threadIdx.x;
+  const int slots = kThreads / G, slot = tid / G, j = tid % G;
+  const int64_t lo = int64_t(g) * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  double acc = 0.0;
+  if (j < k)
+    for (int64_t i = lo + slot; i < hi; i += slots) acc += double(r[i * k + j]);
+  sh[tid] = acc;
+  __syncthreads();
+  if (tid < k) {
+    double t = 0.0;
+    for (int q = 0; q < slots; ++q) t += sh[q * G + tid];
+    part[int64_t(g) * k + tid] = t;
+    __threadfence();
+  }
+  __syncthreads();
+  if (tid == 0) is_last = atomicAdd(counter, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (is_last) {
+    __threadfence();
+    if (tid < k) {
+      double t = 0.0;
+      for (int q = 0; q < int(gridDim.x); ++q) t += load_acquire(part + int64_t(q) * k + tid);
+      if (sum_out) sum_out[tid] = t;
+      tele_out[tid] = w * t;
+    }
+    if (tid == 0) *counter = 0u;
+  }
+}
+
 // Completes rows that span workgroups, then reduces sum(y) in a fixed
 // order: per finish-workgroup partials, and the last workgroup to arrive
 // adds those partials, stores sum(y) and the next teleport scalar.
@@ -458,20 +679,28 @@ __global__ __launch_bounds__(kThreads) void k_relabel_copy(
   }
 }
 
+// Rows of width k: dst row p <- src row order[p] (in), dst row order[p] <-
+// src row p (out).
 template <typename V>
 __global__ __launch_bounds__(256) void k_permute_in(const V *__restrict__ src,
                                                     const int32_t *__restrict__ order, int32_t n,
-                                                    V *__restrict__ dst) {
-  for (int32_t p = blockIdx.x * 256 + threadIdx.x; p < n; p += gridDim.x * 256)
-    dst[p] = src[order[p]];
+                                                    int32_t k, V *__restrict__ dst) {
+  const int64_t total = int64_t(n) * k;
+  for (int64_t e = blockIdx.x * int64_t(256) + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
+    const int64_t p = e / k, j = e - p * k;
+    dst[e] = src[int64_t(order[p]) * k + j];
+  }
 }
 
 template <typename V>
 __global__ __launch_bounds__(256) void k_permute_out(const V *__restrict__ src,
                                                      const int32_t *__restrict__ order, int32_t n,
-                                                     V *__restrict__ dst) {
-  for (int32_t p = blockIdx.x * 256 + threadIdx.x; p < n; p += gridDim.x * 256)
-    dst[order[p]] = src[p];
+                                                     int32_t k, V *__restrict__ dst) {
+  const int64_t total = int64_t(n) * k;
+  for (int64_t e = blockIdx.x * int64_t(256) + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
+    const int64_t p = e / k, j = e - p * k;
+    dst[int64_t(order[p]) * k + j] = src[e];
+  }
 }
 
 // Optional event pairs around each SpMV launch (benchmark instrumentation).
@@ -531,10 +760,10 @@ Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs, size_t *byte
   L.coord = c.take<int2>(size_t(nb + 1));
   L.closes = c.take<uint8_t>(size_t(nb));
   L.carry_row = c.take<int32_t>(size_t(nb));
-  L.blk_carry = c.take<Acc>(size_t(nb));
-  L.blk_head = c.take<Acc>(size_t(nb));
-  L.blk_ysum = c.take<double>(size_t(nb));
-  L.part = c.take<double>(size_t(G > G0 ? G : G0));
+  L.blk_carry = c.take<Acc>(size_t(nb) * nrhs);
+  L.blk_head = c.take<Acc>(size_t(nb) * nrhs);
+  L.blk_ysum = c.take<double>(size_t(nb) * nrhs);
+  L.part = c.take<double>(size_t(G > G0 ? G : G0) * nrhs);
   L.keys_in = c.take<uint64_t>(size_t(n));
   L.keys_out = c.take<uint64_t>(size_t(n));
   L.radix_bytes = radix_ws_bytes(n, 31) + scan_ws_elems(n) * 4 + 256;
@@ -556,21 +785,50 @@ size_t ws_bytes_t(int64_t n, int64_t nnz_cap, int32_t nrhs) {
   return b;
 }
 
+template <typename V, int G>
+void launch_spmm_g(int32_t nb, hipStream_t s, const int32_t *rp, const int32_t *col, const V *val,
+                   const V *x, V *y, int32_t n, int32_t k, const int2 *coord, double c,
+                   const double *tele, double *blk_ysum, typename Form<V>::Acc *blk_carry,
+                   typename Form<V>::Acc *blk_head) {
+  hipLaunchKernelGGL((k_spmm<V, G>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x, y, n, k,
+                     coord, c, tele, blk_ysum, blk_carry, blk_head);
+}
+
 template <typename V>
-pp_status run_pagerank(const pp_csr &AT0, int32_t iters, double c, const int32_t *weights, V *r,
-                       double *sums, void *ws, size_t ws_bytes, hipStream_t s) {
+void launch_spmm(int G, int32_t nb, hipStream_t s, const int32_t *rp, const int32_t *col,
+                 const V *val, const V *x, V *y, int32_t n, int32_t k, const int2 *coord, double c,
+                 const double *tele, double *blk_ysum, typename Form<V>::Acc *blk_carry,
+                 typename Form<V>::Acc *blk_head) {
+  switch (G) {
+    case 2: launch_spmm_g<V, 2>(nb, s, rp, col, val, x, y, n, k, coord, c, tele, blk_ysum, blk_carry, blk_head); break;
+    case 4: launch_spmm_g<V, 4>(nb, s, rp, col, val, x, y, n, k, coord, c, tele, blk_ysum, blk_carry, blk_head); break;
+    case 8: launch_spmm_g<V, 8>(nb, s, rp, col, val, x, y, n, k, coord, c, tele, blk_ysum, blk_carry, blk_head); break;
+    case 16: launch_spmm_g<V, 16>(nb, s, rp, col, val, x, y, n, k, coord, c, tele, blk_ysum, blk_carry, blk_head); break;
+    case 32: launch_spmm_g<V, 32>(nb, s, rp, col, val, x, y, n, k, coord, c, tele, blk_ysum, blk_carry, blk_head); break;
+    default: launch_spmm_g<V, 64>(nb, s, rp, col, val, x, y, n, k, coord, c, tele, blk_ysum, blk_carry, blk_head); break;
+  }
+}
+
+template <typename V>
+pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
+                       const int32_t *weights, V *r, double *sums, void *ws, size_t ws_bytes,
+                       hipStream_t s) {
   const int64_t n = AT0.n, nnz = AT0.nnz;
-  if (ws_bytes < ws_bytes_t<V>(n, nnz, 1)) return fail(PP_EWORKSPACE, "pagerank workspace too small");
-  Layout<V> L = carve<V>(ws, n, nnz, 1);
+  if (ws_bytes < ws_bytes_t<V>(n, nnz, nrhs))
+    return fail(PP_EWORKSPACE, "pagerank workspace too small");
+  Layout<V> L = carve<V>(ws, n, nnz, nrhs);
   const int32_t nb = int32_t((n + nnz + kItems - 1) / kItems);
   const int32_t G = (nb + kFinishPer - 1) / kFinishPer;
   const double w = (1.0 - c) / double(n);
-  const int32_t n32 = int32_t(n);
+  const int32_t n32 = int32_t(n), k = nrhs;
+  int lanes = 2;
+  while (lanes < k) lanes <<= 1;
   const int gN = grid_for(n, 256, 8192);
+  const int gNK = grid_for(n * k, 256, 8192);
   pp_status st;
   if ((st = fill_i32(reinterpret_cast<int32_t *>(L.counter), 4, 0, s)) != PP_OK) return st;
 
-  // The matrix the iterations run on, and the vector they start from.
+  // The matrix the iterations run on, and the vectors they start from.
   const int32_t *rp = AT0.row_ptr, *col = AT0.col;
   const V *val = static_cast<const V *>(AT0.val);
   V *x0 = r;
@@ -602,36 +860,51 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t iters, double c, const int32_t
     hipLaunchKernelGGL(k_relabel_copy<V>, dim3(nb), dim3(kThreads), 0, s, AT0.row_ptr, AT0.col,
                        static_cast<const V *>(AT0.val), L.order, L.newlabel, L.rp2, n32, L.coord,
                        L.col2, L.val2);
-    hipLaunchKernelGGL(k_permute_in<V>, dim3(gN), dim3(256), 0, s, r, L.order, n32, L.x2);
+    hipLaunchKernelGGL(k_permute_in<V>, dim3(gNK), dim3(256), 0, s, r, L.order, n32, k, L.x2);
     PP_LAUNCHED("k_relabel_copy/k_permute_in");
   }
 
   const int G0 = int((n + kSumChunk - 1) / kSumChunk);
-  hipLaunchKernelGGL(k_sum0<V>, dim3(G0), dim3(kThreads), 0, s, x0, n, kSumChunk, L.part,
-                     L.counter, w, sums, L.tele);
+  if (k == 1)
+    hipLaunchKernelGGL(k_sum0<V>, dim3(G0), dim3(kThreads), 0, s, x0, n, kSumChunk, L.part,
+                       L.counter, w, sums, L.tele);
+  else
+    hipLaunchKernelGGL(k_sum0_mm<V>, dim3(G0), dim3(kThreads), 0, s, x0, n, k, lanes, kSumChunk,
+                       L.part, L.counter, w, sums, L.tele);
   PP_LAUNCHED("k_sum0");
 
   g_timing.used = 0;
-  for (int32_t k = 0; k < iters; ++k) {
-    const V *x = (k & 1) ? L.y : x0;
-    V *yv = (k & 1) ? x0 : L.y;
+  for (int32_t it = 0; it < iters; ++it) {
+    const V *x = (it & 1) ? L.y : x0;
+    V *yv = (it & 1) ? x0 : L.y;
+    const double *t_in = L.tele + 64 * (it & 1);
+    double *t_out = L.tele + 64 * ((it + 1) & 1);
+    double *s_out = sums ? sums + int64_t(it + 1) * k : nullptr;
     if ((st = timed_begin(s)) != PP_OK) return st;
-    hipLaunchKernelGGL((k_spmv<V, kIpt>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x, yv,
-                       n32, L.coord, c, L.tele + (k & 1), L.blk_ysum, L.blk_carry, L.blk_head);
+    if (k == 1)
+      hipLaunchKernelGGL((k_spmv<V, kIpt>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x, yv,
+                         n32, L.coord, c, t_in, L.blk_ysum, L.blk_carry, L.blk_head);
+    else
+      launch_spmm<V>(lanes, nb, s, rp, col, val, x, yv, n32, k, L.coord, c, t_in, L.blk_ysum,
+                     L.blk_carry, L.blk_head);
     if ((st = timed_end(s)) != PP_OK) return st;
-    hipLaunchKernelGGL(k_finish<V>, dim3(G), dim3(kThreads), 0, s, yv, nb, L.coord, L.closes,
-                       L.carry_row, L.blk_carry, L.blk_head, L.blk_ysum, c, L.tele + (k & 1),
-                       L.part, L.counter, w, sums ? sums + k + 1 : nullptr,
-                       L.tele + ((k + 1) & 1));
+    if (k == 1)
+      hipLaunchKernelGGL(k_finish<V>, dim3(G), dim3(kThreads), 0, s, yv, nb, L.coord, L.closes,
+                         L.carry_row, L.blk_carry, L.blk_head, L.blk_ysum, c, t_in, L.part,
+                         L.counter, w, s_out, t_out);
+    else
+      hipLaunchKernelGGL(k_finish_mm<V>, dim3(G), dim3(kThreads), 0, s, yv, nb, k, lanes, L.coord,
+                         L.closes, L.carry_row, L.blk_carry, L.blk_head, L.blk_ysum, c, t_in,
+                         L.part, L.counter, w, s_out, t_out);
     PP_LAUNCHED("k_spmv/k_finish");
   }
   const V *last = (iters & 1) ? L.y : x0;
   if (weights) {
-    hipLaunchKernelGGL(k_permute_out<V>, dim3(gN), dim3(256), 0, s, last, L.order, n32, r);
+    hipLaunchKernelGGL(k_permute_out<V>, dim3(gNK), dim3(256), 0, s, last, L.order, n32, k, r);
     PP_LAUNCHED("k_permute_out");
     return PP_OK;
   }
-  if (iters & 1) return copy_bytes(r, L.y, size_t(n) * sizeof(V), s);
+  if (iters & 1) return copy_bytes(r, L.y, size_t(n) * k * sizeof(V), s);
   return PP_OK;
 }
 
@@ -688,11 +961,11 @@ pp_status launch_init_r(int64_t n, int32_t nrhs, uint64_t seed, pp_dtype dt, voi
 pp_status launch_pagerank(const pp_csr &AT, pp_dtype dt, int32_t nrhs, int32_t iters, double c,
                           const int32_t *weights, void *r, double *sums, void *ws, size_t ws_bytes,
                           hipStream_t s) {
-  if (nrhs != 1) return fail(PP_EINVAL, "nrhs %d: only the single-vector form is built", nrhs);
   if (dt == PP_F64)
-    return run_pagerank<double>(AT, iters, c, weights, static_cast<double *>(r), sums, ws,
+    return run_pagerank<double>(AT, nrhs, iters, c, weights, static_cast<double *>(r), sums, ws,
                                 ws_bytes, s);
-  return run_pagerank<float>(AT, iters, c, weights, static_cast<float *>(r), sums, ws, ws_bytes, s);
+  return run_pagerank<float>(AT, nrhs, iters, c, weights, static_cast<float *>(r), sums, ws,
+                             ws_bytes, s);
 }
 
 }  // namespace pp

@@ -361,3 +361,45 @@ def test_pipeline_end_to_end(scale, dtype):
     assert np.array_equal(host(d_in), f.d_in) and np.array_equal(host(d_out), f.d_out)
     assert rel_l1(host(r), want) <= TOL[dtype]
     assert np.abs(host(sums) / wsums - 1).max() <= TOL[dtype]
+
+
+# ------------------------------------------------------- K3 batched (SpMM)
+def run_k3_multi(n, A_rp, A_col, A_val, dtype, nrhs, iters=20, seed=9, weights=None):
+    trp, tcol, tval = oracle.transpose_csr(n, A_rp, A_col, A_val)
+    AT = pp.CSR.from_arrays(n, trp, tcol, tval, dtype)
+    r = pp.init_r(n, seed, dtype, nrhs)
+    w = None if weights is None else dev(weights, torch.int32)
+    sums = host(pp.pagerank(AT, r, iters=iters, c=C, weights=w))
+    got = host(r).reshape(n, nrhs)
+    sums = sums.reshape(iters + 1, nrhs)
+    for j in range(nrhs):
+        want, wsums = oracle.pagerank(n, A_rp, A_col, A_val, oracle.init_r(n, seed, j), iters, C)
+        assert rel_l1(got[:, j], want) <= TOL[dtype], j
+        assert np.abs(sums[:, j] / wsums - 1).max() <= TOL[dtype], j
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("nrhs", [2, 3, 8, 32, 64])
+def test_spmm_matches_independent_runs(nrhs, dtype):
+    scale = 12
+    ou, ov = oracle.generate(okron(spec(scale)))
+    ous, ovs = oracle.sort(scale, ou, ov)
+    f = oracle.filter(scale, ous, ovs)
+    run_k3_multi(f.n, f.A_rp, f.A_col, f.A_val, dtype, nrhs)
+
+
+@pytest.mark.parametrize("nrhs", [5, 32])
+def test_spmm_relabelled_and_long_rows(nrhs):
+    rng = np.random.default_rng(nrhs)
+    n = 30000
+    rp, col, val = random_matrix(n, rng, long_rows=[(3, 20000), (n - 2, 9000)])
+    run_k3_multi(n, rp, col, val, "f32", nrhs, weights=np.bincount(col, minlength=n))
+    run_k3_multi(n, rp, col, val, "f64", nrhs, iters=7)
+
+
+def test_spmm_kronecker_s16_relabelled():
+    scale = 16
+    ou, ov = oracle.generate(okron(spec(scale)))
+    ous, ovs = oracle.sort(scale, ou, ov)
+    f = oracle.filter(scale, ous, ovs)
+    run_k3_multi(f.n, f.A_rp, f.A_col, f.A_val, "f32", 32, weights=f.d_out)
