@@ -45,6 +45,9 @@ def parse():
                     help="skip the batched-RHS form (S=22, 32 right-hand sides)")
     ap.add_argument("--batched-scale", type=int, default=22)
     ap.add_argument("--nrhs", type=int, default=32)
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="skip the many-small-graphs form (512 graphs, S uniform on 8..14)")
+    ap.add_argument("--ngraphs", type=int, default=512)
     ap.add_argument("--no-relabel", action="store_true",
                     help="iterate on K2's labels (no degree-ordered relabelling inside K3)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -141,6 +144,57 @@ def batched_form(args, pp, workloads, torch):
     del AT, ws, rk, r1, d_out
     torch.cuda.empty_cache()
     return out
+
+
+def graphs_form(args, pp, workloads, torch):
+    """K3 for many independent small graphs: one persistent launch recorded
+    into a hipGraph and replayed, beside one pp_pagerank call per graph."""
+    specs = workloads.batch(args.ngraphs, 8, 14, workloads.BASE_SEED)
+    items, edges, nnz = [], 0, 0
+    for i, sp in enumerate(specs):
+        u, v = pp.generate(sp)
+        us, vs = pp.sort(sp.scale, u, v)
+        AT, _, _ = pp.filter(sp.scale, us, vs, "f32", degrees=False)
+        r = torch.empty(AT.n, dtype=torch.float32, device="cuda")
+        items.append((AT, r, None, 7000 + i))
+        edges += sp.m
+        nnz += AT.nnz
+    gb = pp.GraphBatch(items, "f32")
+    stream = torch.cuda.Stream()
+    ts = []
+    with torch.cuda.stream(stream):
+        pp.pagerank_graphs(gb, iters=args.iters, c=workloads.DAMPING, use_graph=True)
+        stream.synchronize()
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            pp.pagerank_graphs(gb, iters=args.iters, c=workloads.DAMPING, use_graph=True)
+            e1.record()
+            stream.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        r_persist = [r.clone() for _, r, _, _ in gb.items]
+        # The same work as one pp_init_r + pp_pagerank call per graph.
+        ws = torch.empty(pp.workspace_bytes(pp.K3, 1 << 14, 1 << 19, "f32"), dtype=torch.uint8,
+                         device="cuda")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for AT, r, _, seed in gb.items:
+            pp.init_r(AT.n, seed, "f32", out=r, ws=ws)
+            pp.pagerank(AT, r, iters=args.iters, c=workloads.DAMPING, sums=False, ws=ws)
+        e1.record()
+        stream.synchronize()
+        t_calls = e0.elapsed_time(e1) / 1e3
+        err = max(float((a.double() - r.double()).abs().sum() / r.double().abs().sum())
+                  for a, (_, r, _, _) in zip(r_persist, gb.items))
+    t = min(ts)
+    return {"workload": f"kron-batch{args.ngraphs}-s8to14-f32", "graphs": args.ngraphs,
+            "edges_total": edges, "nnz_total": nnz, "k3_ms": t * 1e3,
+            "k3_ms_mean": sum(ts) / len(ts) * 1e3,
+            "edges_per_s": args.iters * edges / t,
+            "per_graph_calls_ms": t_calls * 1e3,
+            "speedup_over_per_graph_calls": t_calls / t,
+            "max_rel_l1_vs_per_graph_calls": err,
+            "launch": "one persistent kernel, replayed from a hipGraph"}
 
 
 def spmv_bytes(n: int, nnz: int, dtype: str) -> int:
@@ -352,6 +406,10 @@ def main():
         log("batched right-hand sides")
         torch.cuda.empty_cache()
         out.setdefault("forms", {})["batched_rhs"] = batched_form(args, pp, workloads, torch)
+
+    if not args.no_graphs:
+        log("many small graphs")
+        out.setdefault("forms", {})["graphs"] = graphs_form(args, pp, workloads, torch)
 
     if not args.no_cpu:
         log("CPU oracle baseline")

@@ -47,7 +47,13 @@ typedef enum {
                  sum(r), the teleport scalar and 1/d_out stay FP64 */
 } pp_dtype;
 
-typedef enum { PP_K0 = 0, PP_K1 = 1, PP_K2 = 2, PP_K3 = 3 } pp_kernel;
+typedef enum {
+  PP_K0 = 0,
+  PP_K1 = 1,
+  PP_K2 = 2,
+  PP_K3 = 3,
+  PP_K3_GRAPHS = 4 /* pp_pagerank_graphs; the m argument is the number of graphs */
+} pp_kernel;
 
 /* Kronecker generator parameters [host] (Sec. IV.A): N = 2^scale vertices,
  * M = edge_factor * N edges, initiator quadrant probabilities a,b,c,d
@@ -72,6 +78,23 @@ typedef struct {
   int32_t *col;
   void *val;
 } pp_csr;
+
+/* One graph of a pp_pagerank_graphs batch (the descriptor table itself is
+ * device memory, and so are the arrays it points to):
+ * CSR(A^T) with n rows and nnz entries (as written by pp_filter, values of
+ * the batch's dtype), the output vector r (n entries), optional sums
+ * (iters+1 FP64 entries, NULL = not returned) and the seed of the graph's
+ * initial vector. */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int32_t *row_ptr;
+  const int32_t *col;
+  const void *val;
+  void *r;
+  double *sums;
+  uint64_t seed;
+} pp_graph;
 
 /* Text for a status code (static storage). */
 const char *pp_strerror(pp_status st);
@@ -149,6 +172,28 @@ pp_status pp_init_r(int64_t n, int32_t nrhs, uint64_t seed, pp_dtype dt, void *r
 pp_status pp_pagerank(const pp_csr *AT, pp_dtype dt, int32_t nrhs, int32_t iters, double c,
                       const int32_t *order_weights, void *r, double *sums, void *ws,
                       size_t ws_bytes, void *stream);
+
+/* K3 (Sec. IV.D) for a batch of independent small graphs in one persistent
+ * launch: for every graph, r_0 as pp_init_r (right-hand side 0, the graph's
+ * seed) followed by `iters` iterations as pp_pagerank, with r and the
+ * iterate held in on-chip memory.  graphs is a DEVICE array of ngraphs
+ * descriptors owned by the caller; workgroups take graphs in array order,
+ * so listing the largest first balances the launch.  max_n bounds the
+ * vertex count of every graph and must not exceed pp_graphs_max_n(dt)
+ * (PP_ERANGE).  A graph with n > max_n or malformed fields is skipped and
+ * its r left untouched.  use_graph != 0 records the launch into a hipGraph
+ * on first use and replays it on later calls with the same arguments
+ * (stream must not be NULL then; the replay reads the descriptor table
+ * and the workspace as they are at that time); use_graph == 0 launches
+ * directly.  Workspace: pp_workspace_bytes(PP_K3_GRAPHS, 1, ngraphs, dt, 1);
+ * calls sharing a workspace must not overlap. */
+pp_status pp_pagerank_graphs(int32_t ngraphs, const pp_graph *graphs, int64_t max_n, pp_dtype dt,
+                             int32_t iters, double c, int32_t use_graph, void *ws, size_t ws_bytes,
+                             void *stream);
+
+/* Largest n a pp_pagerank_graphs graph may have with value type dt (the
+ * on-chip memory of one workgroup holds two n-vectors). */
+int64_t pp_graphs_max_n(pp_dtype dt);
 
 /* Benchmark instrumentation.  While enabled (enable != 0), each
  * pp_pagerank call records a pair of HIP events on its stream around every

@@ -1,0 +1,340 @@
+// k3_graphs.hip -- K3 (Sec. IV.D) for many independent small graphs in one
+// persistent launch, captured once into a hipGraph and replayed.
+//
+// Each 1024-thread workgroup takes whole graphs from an atomic queue
+// (descriptors uploaded largest first) and runs the full K3 of a graph on
+// its own: the initial vector r = rand ./ norm(r,1) (same counter-based
+// draws and exact integer sum as pp_init_r), then `iters` damped
+// iterations.  r and y live in LDS, so every gather r[u] is an LDS read and
+// only the graph's CSR streams from L2/HBM.  Rows are split between threads
+// by a merge-path partition of the graph's (row ends, non-zeros), computed
+// once per graph; rows cut between threads are completed with a segmented
+// scan over the workgroup.  sum(r) is an FP64 block reduction in a fixed
+// order.  Workgroups never wait on each other: a workgroup exits when the
+// queue is empty.
+#include <vector>
+
+#include "pp_common.hpp"
+
+#pragma clang fp contract(off)
+
+namespace pp {
+
+namespace {
+
+constexpr int kT = 1024;           // threads per workgroup
+constexpr int kW = kT / kWave;     // waves per workgroup
+
+struct AccD {
+  double s;
+  __device__ __forceinline__ void add(double x) { s += x; }
+  __device__ __forceinline__ double value() const { return s; }
+};
+__device__ __forceinline__ AccD merge(AccD a, AccD b) { return AccD{a.s + b.s}; }
+__device__ __forceinline__ AccD shfl_up_acc(AccD a, int o) { return AccD{__shfl_up(a.s, o, kWave)}; }
+
+struct AccF {
+  float s, e;
+  __device__ __forceinline__ void add(float x) {
+    const float t = s + x;
+    const float z = t - s;
+    const float err = (s - (t - z)) + (x - z);
+    s = t;
+    e += err;
+  }
+  __device__ __forceinline__ float value() const { return s + e; }
+};
+__device__ __forceinline__ AccF merge(AccF a, AccF b) {
+  AccF r = a;
+  r.add(b.s);
+  r.e += b.e;
+  return r;
+}
+__device__ __forceinline__ AccF shfl_up_acc(AccF a, int o) {
+  return AccF{__shfl_up(a.s, o, kWave), __shfl_up(a.e, o, kWave)};
+}
+
+template <typename V>
+struct GForm;
+template <>
+struct GForm<double> {
+  using Acc = AccD;
+  __device__ static double finish(AccD a, double c, double t) { return c * a.value() + t; }
+};
+template <>
+struct GForm<float> {
+  using Acc = AccF;
+  __device__ static float finish(AccF a, double c, double t) {
+    return float(c * double(a.value()) + t);
+  }
+};
+
+// Fixed-order sum over the 1024 threads (shuffle tree, then 16 wave sums in
+// index order); valid in every thread.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T *sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == 0) sh[w] = v;
+  __syncthreads();
+  T r = 0;
+  for (int i = 0; i < kW; ++i) r += sh[i];
+  __syncthreads();
+  return r;
+}
+
+template <typename V>
+__global__ __launch_bounds__(kT) void k_graphs(const pp_graph *__restrict__ graphs, int32_t ngraphs,
+                                               int32_t iters, double c, uint32_t *queue,
+                                               int32_t lds_n) {
+  // queue[0]: next graph; queue[1]: graphs skipped by the bounds check.
+  using Acc = typename GForm<V>::Acc;
+  extern __shared__ __align__(16) uint8_t smem[];
+  V *xa = reinterpret_cast<V *>(smem);
+  V *ya = xa + lds_n;
+  __shared__ int32_t s_g;
+  __shared__ double s_dred[kW];
+  __shared__ unsigned long long s_ured[kW];
+  __shared__ Acc s_pre[kT];
+  __shared__ Acc s_tail[kW];
+  __shared__ int32_t s_first[kW], s_last[kW];
+
+  const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
+  for (;;) {
+    if (tid == 0) s_g = int32_t(atomicAdd(queue, 1u));
+    __syncthreads();
+    const int32_t g = s_g;
+    __syncthreads();
+    if (g >= ngraphs) break;
+    const pp_graph G = graphs[g];
+    // Graphs that do not fit the workgroup's LDS vectors (or are malformed)
+    // are left untouched and counted.
+    if (G.n < 1 || G.n > lds_n || G.nnz < 0 || G.n + G.nnz > 0x7FFFFFFF || !G.row_ptr || !G.r ||
+        (G.nnz > 0 && (!G.col || !G.val))) {
+      if (tid == 0) atomicAdd(queue + 1, 1u);
+      continue;
+    }
+    const int32_t n = int32_t(G.n), nnz = int32_t(G.nnz);
+    const int32_t *__restrict__ rp = G.row_ptr;
+    const int32_t *__restrict__ col = G.col;
+    const V *__restrict__ val = static_cast<const V *>(G.val);
+    V *x = xa, *y = ya;
+
+    // Initial vector: 24-bit draws, exact integer sum, one division each.
+    const uint32_t k0 = uint32_t(G.seed), k1 = uint32_t(G.seed >> 32);
+    unsigned long long part = 0;
+    for (int32_t i = tid; i < n; i += kT)
+      part += philox10(U4{uint32_t(i), 0u, 0u, 2u}, k0, k1).x >> 8;
+    const unsigned long long K = block_sum(part, s_ured);
+    for (int32_t i = tid; i < n; i += kT) {
+      const uint32_t ki = philox10(U4{uint32_t(i), 0u, 0u, 2u}, k0, k1).x >> 8;
+      x[i] = V(K ? double(ki) / double(K) : 1.0 / double(n));
+    }
+    __syncthreads();
+    double ps = 0.0;
+    for (int32_t i = tid; i < n; i += kT) ps += double(x[i]);
+    double s = block_sum(ps, s_dred);
+    if (tid == 0 && G.sums) G.sums[0] = s;
+    const double w = (1.0 - c) / double(n);
+
+    // This thread's merge-path items, fixed for all iterations.
+    const int32_t tot = n + nnz;
+    const int32_t per = (tot + kT - 1) / kT;
+    const int32_t d0 = tid * per < tot ? tid * per : tot;
+    const int32_t d1 = d0 + per < tot ? d0 + per : tot;
+    int32_t lo = d0 - nnz > 0 ? d0 - nnz : 0, hi = d0 < n ? d0 : n;
+    while (lo < hi) {
+      const int32_t m = (lo + hi) >> 1;
+      if (rp[m + 1] <= d0 - m - 1)
+        lo = m + 1;
+      else
+        hi = m;
+    }
+    const int32_t ti0 = lo, tj0 = d0 - lo;
+
+    for (int32_t it = 0; it < iters; ++it) {
+      const double tk = w * s;
+      int32_t ti = ti0, tj = tj0;
+      int32_t next_end = ti < n ? rp[ti + 1] : 0;
+      Acc acc{}, first{};
+      int32_t first_row = -1;
+      double ysum = 0.0;
+      for (int32_t d = d0; d < d1; ++d) {
+        if (ti < n && next_end <= tj) {
+          if (first_row < 0) {
+            first_row = ti;
+            first = acc;
+          } else {
+            const V yv = GForm<V>::finish(acc, c, tk);
+            y[ti] = yv;
+            ysum += double(yv);
+          }
+          acc = Acc{};
+          ++ti;
+          next_end = ti < n ? rp[ti + 1] : 0;
+        } else {
+          acc.add(x[col[tj]] * val[tj]);
+          ++tj;
+        }
+      }
+      // Segmented scan of open-row partials (key = open row), as in the
+      // large-graph SpMV, over 16 waves.
+      const int32_t key = ti;
+      Acc v = acc;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const Acc vu = shfl_up_acc(v, o);
+        const int32_t ku = __shfl_up(key, o, kWave);
+        if (lane >= o && ku == key) v = merge(vu, v);
+      }
+      if (lane == kWave - 1) {
+        s_tail[wv] = v;
+        s_last[wv] = key;
+      }
+      if (lane == 0) s_first[wv] = key;
+      __syncthreads();
+      {
+        Acc before{};
+        for (int q = wv - 1; q >= 0; --q) {
+          if (s_last[q] != key) break;
+          before = merge(s_tail[q], before);
+          if (s_first[q] != key) break;
+        }
+        v = merge(before, v);
+      }
+      s_pre[tid] = v;
+      __syncthreads();
+      if (first_row >= 0) {
+        const Acc sum = tid > 0 ? merge(s_pre[tid - 1], first) : first;
+        const V yv = GForm<V>::finish(sum, c, tk);
+        y[first_row] = yv;
+        ysum += double(yv);
+      }
+      s = block_sum(ysum, s_dred);   // contains __syncthreads: y complete
+      if (tid == 0 && G.sums) G.sums[it + 1] = s;
+      V *t = x;
+      x = y;
+      y = t;
+    }
+    V *r = static_cast<V *>(G.r);
+    for (int32_t i = tid; i < n; i += kT) r[i] = x[i];
+    __syncthreads();
+  }
+}
+
+__global__ void k_zero_queue(uint32_t *q) {
+  if (threadIdx.x < 2) q[threadIdx.x] = 0u;
+}
+
+// Cached hipGraph per launch configuration.  The graph holds two kernel
+// nodes (queue reset, persistent kernel) whose arguments are device
+// pointers owned by the caller, so a replay reads whatever the descriptor
+// table and the workspace hold at that time.
+struct GraphEntry {
+  const void *graphs, *ws;
+  hipStream_t stream;
+  int32_t ngraphs, iters, lds_n, grid;
+  pp_dtype dt;
+  double c;
+  hipGraphExec_t exec;
+};
+std::vector<GraphEntry> g_cache;
+
+int lds_limit() {
+  static int limit = -1;
+  if (limit < 0) {
+    int dev = 0, v = 65536;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+      limit = v;
+    else
+      limit = 65536;
+  }
+  return limit;
+}
+
+int cu_count() {
+  static int cus = -1;
+  if (cus < 0) {
+    int dev = 0, v = 256;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+      cus = v;
+    else
+      cus = 256;
+  }
+  return cus;
+}
+
+constexpr size_t kStaticLds = 24 * 1024;  // reductions, scan tails, s_pre
+
+}  // namespace
+
+size_t graphs_ws_bytes(int32_t /*ngraphs*/) {
+  Carve c(nullptr);
+  c.take<uint32_t>(4);
+  return c.bytes();
+}
+
+int64_t graphs_max_n(pp_dtype dt) {
+  const size_t vb = dt == PP_F64 ? 8 : 4;
+  const int64_t room = int64_t(lds_limit()) - int64_t(kStaticLds);
+  return room > 0 ? room / int64_t(2 * vb) / 64 * 64 : 0;
+}
+
+pp_status launch_graphs(int32_t ngraphs, const pp_graph *graphs, int64_t max_n, pp_dtype dt,
+                        int32_t iters, double c, int32_t use_graph, void *ws, size_t ws_bytes,
+                        hipStream_t s) {
+  if (ws_bytes < graphs_ws_bytes(ngraphs)) return fail(PP_EWORKSPACE, "graphs workspace too small");
+  Carve cv(ws);
+  uint32_t *queue = cv.take<uint32_t>(4);
+  const int32_t lds_n = int32_t((max_n + 63) / 64 * 64);
+  const size_t dyn = size_t(2) * lds_n * (dt == PP_F64 ? 8 : 4);
+  const int grid = ngraphs < cu_count() ? ngraphs : cu_count();
+  if (dt == PP_F64)
+    PP_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_graphs<double>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, int(dyn)));
+  else
+    PP_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_graphs<float>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, int(dyn)));
+
+  auto enqueue = [&](hipStream_t st) -> pp_status {
+    hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(64), 0, st, queue);
+    if (dt == PP_F64)
+      hipLaunchKernelGGL(k_graphs<double>, dim3(grid), dim3(kT), dyn, st, graphs, ngraphs, iters,
+                         c, queue, lds_n);
+    else
+      hipLaunchKernelGGL(k_graphs<float>, dim3(grid), dim3(kT), dyn, st, graphs, ngraphs, iters,
+                         c, queue, lds_n);
+    PP_LAUNCHED("k_graphs");
+    return PP_OK;
+  };
+  if (!use_graph) return enqueue(s);
+
+  for (GraphEntry &e : g_cache) {
+    if (e.graphs == graphs && e.ws == ws && e.stream == s && e.ngraphs == ngraphs &&
+        e.iters == iters && e.lds_n == lds_n && e.grid == grid && e.dt == dt && e.c == c) {
+      PP_HIP(hipGraphLaunch(e.exec, s));
+      return PP_OK;
+    }
+  }
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  PP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  pp_status st = enqueue(s);
+  hipError_t e_end = hipStreamEndCapture(s, &graph);
+  if (st != PP_OK) return st;
+  if (e_end != hipSuccess) return check_hip(e_end, "hipStreamEndCapture");
+  hipError_t e_inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e_inst != hipSuccess) return check_hip(e_inst, "hipGraphInstantiate");
+  if (g_cache.size() >= 8) {
+    hipGraphExecDestroy(g_cache.front().exec);
+    g_cache.erase(g_cache.begin());
+  }
+  g_cache.push_back(GraphEntry{graphs, ws, s, ngraphs, iters, lds_n, grid, dt, c, exec});
+  PP_HIP(hipGraphLaunch(exec, s));
+  return PP_OK;
+}
+
+}  // namespace pp

@@ -70,6 +70,9 @@ size_t pp_workspace_bytes(pp_kernel k, int64_t n, int64_t m, pp_dtype dt, int32_
     case PP_K3:
       if (nrhs < 1 || nrhs > 64 || n + m > kI32Max) return size_t(-1);
       return pagerank_ws_bytes(n, m, dt, nrhs);
+    case PP_K3_GRAPHS:
+      if (m < 1 || m > (int64_t(1) << 24)) return size_t(-1);
+      return graphs_ws_bytes(int32_t(m));
   }
   return size_t(-1);
 }
@@ -146,6 +149,29 @@ pp_status pp_pagerank(const pp_csr *AT, pp_dtype dt, int32_t nrhs, int32_t iters
   if (!ws || ws_bytes < need) return fail(PP_EWORKSPACE, "pp_pagerank: workspace needs %zu bytes", need);
   return launch_pagerank(*AT, dt, nrhs, iters, c, order_weights, r, sums, ws, ws_bytes,
                          as_stream(stream));
+}
+
+int64_t pp_graphs_max_n(pp_dtype dt) {
+  if (dt != PP_F64 && dt != PP_F32) return 0;
+  return graphs_max_n(dt);
+}
+
+pp_status pp_pagerank_graphs(int32_t ngraphs, const pp_graph *graphs, int64_t max_n, pp_dtype dt,
+                             int32_t iters, double c, int32_t use_graph, void *ws, size_t ws_bytes,
+                             void *stream) {
+  if (ngraphs < 1 || ngraphs > (1 << 24)) return fail(PP_EINVAL, "pp_pagerank_graphs: ngraphs %d", ngraphs);
+  if (!graphs) return fail(PP_EINVAL, "pp_pagerank_graphs: null graphs");
+  if (dt != PP_F64 && dt != PP_F32) return fail(PP_EINVAL, "pp_pagerank_graphs: dtype %d", int(dt));
+  if (iters < 0) return fail(PP_EINVAL, "pp_pagerank_graphs: iters %d", iters);
+  if (!(c >= 0.0 && c <= 1.0)) return fail(PP_EINVAL, "pp_pagerank_graphs: c = %g", c);
+  if (max_n < 1 || max_n > graphs_max_n(dt))
+    return fail(PP_ERANGE, "pp_pagerank_graphs: max_n %lld outside [1, %lld]", (long long)max_n,
+                (long long)graphs_max_n(dt));
+  if (use_graph && !stream) return fail(PP_EINVAL, "pp_pagerank_graphs: graph capture needs a stream");
+  const size_t need = graphs_ws_bytes(ngraphs);
+  if (!ws || ws_bytes < need) return fail(PP_EWORKSPACE, "pp_pagerank_graphs: workspace needs %zu bytes", need);
+  return launch_graphs(ngraphs, graphs, max_n, dt, iters, c, use_graph, ws, ws_bytes,
+                       as_stream(stream));
 }
 
 pp_status pp_set_kernel_timing(int enable) { return set_kernel_timing(enable != 0); }

@@ -196,6 +196,13 @@ pp_status launch_init_r(int64_t n, int32_t nrhs, uint64_t seed, pp_dtype dt, voi
 pp_status launch_pagerank(const pp_csr &AT, pp_dtype dt, int32_t nrhs, int32_t iters, double c,
                           const int32_t *weights, void *r, double *sums, void *ws, size_t ws_bytes,
                           hipStream_t s);
+// K3 batch of small graphs (k3_graphs.hip)
+size_t graphs_ws_bytes(int32_t ngraphs);
+int64_t graphs_max_n(pp_dtype dt);
+pp_status launch_graphs(int32_t ngraphs, const pp_graph *graphs, int64_t max_n, pp_dtype dt,
+                        int32_t iters, double c, int32_t use_graph, void *ws, size_t ws_bytes,
+                        hipStream_t s);
+
 pp_status set_kernel_timing(bool enable);
 int32_t kernel_times(float *ms, int32_t cap);
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libpp.so")
 
 PP_OK, PP_EINVAL, PP_ERANGE, PP_EWORKSPACE, PP_EHIP = range(5)
 F64, F32 = 0, 1
-K0, K1, K2, K3 = range(4)
+K0, K1, K2, K3, K3_GRAPHS = range(5)
 
 _TORCH = {F64: torch.float64, F32: torch.float32}
 _NAMES = {"f64": F64, "f32": F32, F64: F64, F32: F32,
@@ -45,6 +45,12 @@ class _Csr(ctypes.Structure):
                 ("val", ctypes.c_void_p)]
 
 
+class _Graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("val", ctypes.c_void_p), ("r", ctypes.c_void_p),
+                ("sums", ctypes.c_void_p), ("seed", ctypes.c_uint64)]
+
+
 _lib = None
 
 # (name, restype, argtypes) of every entry point in include/pp.h.
@@ -61,6 +67,9 @@ SIGNATURES = {
     "pp_init_r": (ctypes.c_int, [_I64, _I32, _U64, ctypes.c_int, _VP, _VP, _SZ, _VP]),
     "pp_pagerank": (ctypes.c_int, [ctypes.POINTER(_Csr), ctypes.c_int, _I32, _I32, _D, _VP,
                                    _VP, _VP, _VP, _SZ, _VP]),
+    "pp_pagerank_graphs": (ctypes.c_int, [_I32, _VP, _I64, ctypes.c_int, _I32, _D, _I32, _VP,
+                                          _SZ, _VP]),
+    "pp_graphs_max_n": (_I64, [ctypes.c_int]),
     "pp_set_kernel_timing": (ctypes.c_int, [ctypes.c_int]),
     "pp_kernel_times": (_I32, [ctypes.POINTER(ctypes.c_float), _I32]),
 }
@@ -232,6 +241,47 @@ def pagerank(AT: CSR, r, iters: int = 20, c: float = 0.85, sums=True, ws=None, w
     _check(lib().pp_pagerank(ctypes.byref(cs), dt, nrhs, iters, c, _ptr(weights), _ptr(r),
                              _ptr(sums), _ptr(ws), ws.numel(), _stream()), "pp_pagerank")
     return sums
+
+
+def graphs_max_n(dtype="f32") -> int:
+    """Largest vertex count pagerank_graphs() accepts for this dtype."""
+    return int(lib().pp_graphs_max_n(dtype_code(dtype)))
+
+
+class GraphBatch:
+    """A batch for pagerank_graphs(): (CSR, r, sums_or_None, seed) per graph
+    and their device descriptor table, largest graphs first."""
+
+    def __init__(self, items, dtype="f32"):
+        self.dtype = dtype_code(dtype)
+        self.items = sorted(items, key=lambda it: -(it[0].n + it[0].nnz))
+        arr = (_Graph * len(self.items))()
+        for i, (AT, r, sums, seed) in enumerate(self.items):
+            if AT.dtype != self.dtype or dtype_code(r.dtype) != self.dtype:
+                raise PPError(PP_EINVAL, "GraphBatch", "dtype mismatch")
+            arr[i] = _Graph(AT.n, AT.nnz, AT.row_ptr.data_ptr(), AT.col.data_ptr(),
+                            AT.val.data_ptr(), r.data_ptr(), _ptr(sums) or 0,
+                            seed & (2**64 - 1))
+        raw = bytes(arr)
+        dev = self.items[0][1].device
+        self.table = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev)
+        self.max_n = max(AT.n for AT, *_ in self.items)
+        self.ws = torch.empty(workspace_bytes(K3_GRAPHS, 1, len(self.items), self.dtype),
+                              dtype=torch.uint8, device=dev)
+
+    def __len__(self):
+        return len(self.items)
+
+
+def pagerank_graphs(batch: GraphBatch, iters: int = 20, c: float = 0.85, use_graph=True,
+                    max_n: int | None = None):
+    """K3 for every graph of the batch in one persistent launch (r and sums
+    filled in place).  With use_graph the launch is recorded once into a
+    hipGraph and replayed on later calls; it needs a non-default stream."""
+    mx = batch.max_n if max_n is None else max_n
+    _check(lib().pp_pagerank_graphs(len(batch), batch.table.data_ptr(), mx, batch.dtype, iters,
+                                    c, int(bool(use_graph)), batch.ws.data_ptr(),
+                                    batch.ws.numel(), _stream()), "pp_pagerank_graphs")
 
 
 # ------------------------------------------------------------ instrumentation
