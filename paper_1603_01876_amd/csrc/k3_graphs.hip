@@ -159,22 +159,40 @@ __global__ __launch_bounds__(kT) void k_graphs(const pp_graph *__restrict__ grap
       Acc acc{}, first{};
       int32_t first_row = -1;
       double ysum = 0.0;
-      for (int32_t d = d0; d < d1; ++d) {
-        if (ti < n && next_end <= tj) {
-          if (first_row < 0) {
-            first_row = ti;
-            first = acc;
-          } else {
-            const V yv = GForm<V>::finish(acc, c, tk);
-            y[ti] = yv;
-            ysum += double(yv);
+      // Walk the items with a window of U column/value loads in flight
+      // (a thread's non-zeros are contiguous); row ends between them
+      // are handled as they come.
+      constexpr int U = 8;
+      for (int32_t d = d0; d < d1;) {
+        int32_t cw[U];
+        V vw[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int32_t q = tj + u < nnz ? tj + u : nnz - 1;
+          cw[u] = q >= 0 ? col[q] : 0;
+          vw[u] = q >= 0 ? val[q] : V(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          while (d < d1 && ti < n && next_end <= tj) {
+            if (first_row < 0) {
+              first_row = ti;
+              first = acc;
+            } else {
+              const V yv = GForm<V>::finish(acc, c, tk);
+              y[ti] = yv;
+              ysum += double(yv);
+            }
+            acc = Acc{};
+            ++ti;
+            next_end = ti < n ? rp[ti + 1] : 0;
+            ++d;
           }
-          acc = Acc{};
-          ++ti;
-          next_end = ti < n ? rp[ti + 1] : 0;
-        } else {
-          acc.add(x[col[tj]] * val[tj]);
-          ++tj;
+          if (d < d1) {
+            acc.add(x[cw[u]] * vw[u]);
+            ++tj;
+            ++d;
+          }
         }
       }
       // Segmented scan of open-row partials (key = open row), as in the
