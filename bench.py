@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--no-graphs", action="store_true",
                     help="skip the many-small-graphs form (512 graphs, S uniform on 8..14)")
     ap.add_argument("--ngraphs", type=int, default=512)
+    ap.add_argument("--no-tune", action="store_true", help="keep the default K3 launch config")
     ap.add_argument("--no-relabel", action="store_true",
                     help="iterate on K2's labels (no degree-ordered relabelling inside K3)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -102,6 +103,10 @@ def batched_form(args, pp, workloads, torch):
     del us, vs
     w = None if args.no_relabel else d_out
     ws = torch.empty(pp.workspace_bytes(pp.K3, n, AT.nnz, "f32", k), dtype=torch.uint8, device=dev)
+    tuned = None
+    if not args.no_tune:
+        from paper_1603_01876_amd import autotune
+        tuned = autotune.tune(AT, "f32", k, w, ws=ws, force=True)
     rk = torch.empty((n, k), dtype=torch.float32, device=dev)
     r1 = torch.empty(n, dtype=torch.float32, device=dev)
 
@@ -128,9 +133,14 @@ def batched_form(args, pp, workloads, torch):
         pp.pagerank(AT, r1, iters=args.iters, c=workloads.DAMPING, sums=False, ws=ws, weights=w)
 
     run_k()
-    run_1()
     tk, kk = timed(run_k)
+    saved = pp.get_k3_config()
+    if not args.no_tune:
+        from paper_1603_01876_amd import autotune
+        autotune.tune(AT, "f32", 1, w, ws=ws, force=True)
+    run_1()
     t1, k1 = timed(run_1)
+    pp.set_k3_config(*saved)
     err = float((rk[:, 0].double() - r1.double()).abs().sum() / r1.double().abs().sum())
     nbytes = 4 * (n + 1) + 8 * AT.nnz + 8 * n * k
     out = {"workload": f"kron-s{S}-f32-rhs{k}", "nrhs": k, "nnz_filtered": AT.nnz,
@@ -140,7 +150,8 @@ def batched_form(args, pp, workloads, torch):
            "spmm_avg_ms": kk * 1e3, "spmm_GBps": nbytes / kk / 1e9,
            "spmm_frac_of_peak": nbytes / kk / 1e9 / HBM_PEAK_GBS,
            "spmm_algorithmic_bytes_per_launch": nbytes,
-           "rel_l1_rhs0_vs_single_f32": err}
+           "rel_l1_rhs0_vs_single_f32": err,
+           "spmm_config": None if tuned is None else tuned}
     del AT, ws, rk, r1, d_out
     torch.cuda.empty_cache()
     return out
@@ -305,6 +316,11 @@ def main():
         step(False)
         torch.cuda.synchronize()
         log(f"warmup step {i} done (nnz={AT.nnz})")
+        if i == 0 and not args.no_tune:
+            from paper_1603_01876_amd import autotune
+            tuned = autotune.tune(AT, dt, 1, None if args.no_relabel else d_out, ws=ws3,
+                                  force=True)
+            log(f"autotuned K3 config {tuned['config']} from {tuned['ms']}")
 
     pp.set_kernel_timing(True)
     spmv_ms = []
@@ -361,6 +377,9 @@ def main():
                      "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "algorithmic_bytes_per_launch": nbytes},
         "sum_r": {"first": float(sums_h[0]), "last": float(sums_h[-1])},
+        "k3_config": {"items_per_thread": pp.get_k3_config()[0],
+                      "relabel": not args.no_relabel,
+                      "tuned": None if args.no_tune or args.warmup < 1 else tuned["ms"]},
     }
 
     if not args.no_f64_side and dt == "f32":

@@ -195,6 +195,22 @@ pp_status pp_pagerank_graphs(int32_t ngraphs, const pp_graph *graphs, int64_t ma
  * on-chip memory of one workgroup holds two n-vectors). */
 int64_t pp_graphs_max_n(pp_dtype dt);
 
+/* Launch configuration of pp_pagerank (process-wide; the autotuner in the
+ * Python package measures the candidates on a given matrix and sets the
+ * fastest).  items_per_thread in {4, 8, 16}: merge-path items per thread of
+ * the sparse matrix-vector kernel (a workgroup tile is 256 times that);
+ * rhs_lanes: lanes per right-hand-side group of the sparse matrix-dense
+ * matrix kernel, 0 = the next power of two >= nrhs, else a power of two in
+ * [nrhs, 64].  Results do not depend on the configuration beyond the order
+ * of floating-point sums.  pp_set_k3_config(NULL) restores the defaults
+ * (8, 0). */
+typedef struct {
+  int32_t items_per_thread;
+  int32_t rhs_lanes;
+} pp_k3_config;
+pp_status pp_set_k3_config(const pp_k3_config *cfg);
+pp_status pp_get_k3_config(pp_k3_config *cfg);
+
 /* Benchmark instrumentation.  While enabled (enable != 0), each
  * pp_pagerank call records a pair of HIP events on its stream around every
  * launch of its sparse product kernel (one per iteration); the events are

@@ -31,8 +31,18 @@ namespace pp {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kIpt = 8;                      // merge items per thread
-constexpr int kItems = kThreads * kIpt;      // items per workgroup
+constexpr int kItems = kThreads * 8;         // SpMM items per workgroup
+constexpr int kItemsMin = kThreads * 4;      // smallest SpMV tile (sizes the workspace)
+constexpr int kItemsMax = kThreads * 16;     // largest SpMV tile (sizes relabel LDS)
+
+// Launch configuration chosen by the caller (or the autotuner): merge items
+// per thread of the SpMV (tile = 256 * ipt items) and lane-group width of
+// the SpMM.
+struct K3Config {
+  int ipt = 8;
+  int rhs_lanes = 0;  // 0: next power of two >= nrhs
+};
+K3Config g_cfg;
 constexpr int kFinishPer = kThreads * 8;     // spmv workgroups per finish workgroup
 constexpr int64_t kSumChunk = kThreads * 64; // entries of r per workgroup of sum(r_0)
 
@@ -80,13 +90,14 @@ struct Form<float> {
 };
 
 // ------------------------------------------------------------- partition
-// coord[b] = (rows ended, non-zeros consumed) after the first b*kItems items
-// of the merge of the row-end list rp[1..n] with the non-zero indices.
+// coord[b] = (rows ended, non-zeros consumed) after the first b*D items of
+// the merge of the row-end list rp[1..n] with the non-zero indices.
 __global__ __launch_bounds__(256) void k_partition(const int32_t *__restrict__ rp, int32_t n,
-                                                   int32_t nnz, int32_t nb, int2 *coord) {
+                                                   int32_t nnz, int32_t nb, int32_t D,
+                                                   int2 *coord) {
   const int64_t total = int64_t(n) + nnz;
   for (int32_t b = blockIdx.x * 256 + threadIdx.x; b <= nb; b += gridDim.x * 256) {
-    const int64_t diag64 = int64_t(b) * kItems < total ? int64_t(b) * kItems : total;
+    const int64_t diag64 = int64_t(b) * D < total ? int64_t(b) * D : total;
     const int32_t diag = int32_t(diag64);
     int32_t lo = diag - nnz > 0 ? diag - nnz : 0;
     int32_t hi = diag < n ? diag : n;
@@ -649,9 +660,9 @@ __global__ __launch_bounds__(kThreads) void k_relabel_copy(
     const int32_t *__restrict__ order, const int32_t *__restrict__ newlabel,
     const int32_t *__restrict__ rp2, int32_t n, const int2 *__restrict__ coord,
     int32_t *__restrict__ col2, V *__restrict__ val2) {
-  __shared__ int32_t s_end[kItems];
-  __shared__ int32_t s_old[kItems + 1];
-  __shared__ int32_t s_new[kItems + 1];
+  __shared__ int32_t s_end[kItemsMax];
+  __shared__ int32_t s_old[kItemsMax + 1];
+  __shared__ int32_t s_new[kItemsMax + 1];
   const int b = blockIdx.x, tid = threadIdx.x;
   const int2 c0 = coord[b], c1 = coord[b + 1];
   const int32_t i0 = c0.x, j0 = c0.y, na = c1.x - c0.x, nz = c1.y - c0.y;
@@ -749,7 +760,7 @@ Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs, size_t *byte
   using Acc = typename Form<V>::Acc;
   Carve c(ws);
   Layout<V> L{};
-  const int64_t nb = (n + nnz_cap + kItems - 1) / kItems + 1;
+  const int64_t nb = (n + nnz_cap + kItemsMin - 1) / kItemsMin + 1;
   const int64_t G = (nb + kFinishPer - 1) / kFinishPer + 1;
   const int64_t G0 = (n + kSumChunk - 1) / kSumChunk + 1;
   L.ksum = c.take<unsigned long long>(64);
@@ -817,12 +828,17 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
   if (ws_bytes < ws_bytes_t<V>(n, nnz, nrhs))
     return fail(PP_EWORKSPACE, "pagerank workspace too small");
   Layout<V> L = carve<V>(ws, n, nnz, nrhs);
-  const int32_t nb = int32_t((n + nnz + kItems - 1) / kItems);
+  const int ipt = (g_cfg.ipt == 4 || g_cfg.ipt == 16) ? g_cfg.ipt : 8;
+  const int32_t D = nrhs == 1 ? kThreads * ipt : kItems;
+  const int32_t nb = int32_t((n + nnz + D - 1) / D);
   const int32_t G = (nb + kFinishPer - 1) / kFinishPer;
   const double w = (1.0 - c) / double(n);
   const int32_t n32 = int32_t(n), k = nrhs;
   int lanes = 2;
   while (lanes < k) lanes <<= 1;
+  if (k > 1 && g_cfg.rhs_lanes >= lanes && g_cfg.rhs_lanes <= 64 &&
+      (g_cfg.rhs_lanes & (g_cfg.rhs_lanes - 1)) == 0)
+    lanes = g_cfg.rhs_lanes;
   const int gN = grid_for(n, 256, 8192);
   const int gNK = grid_for(n * k, 256, 8192);
   pp_status st;
@@ -852,7 +868,7 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
   }
 
   hipLaunchKernelGGL(k_partition, dim3(grid_for(int64_t(nb) + 1, 256, 4096)), dim3(256), 0, s,
-                     rp, n32, int32_t(nnz), nb, L.coord);
+                     rp, n32, int32_t(nnz), nb, D, L.coord);
   hipLaunchKernelGGL(k_block_flags, dim3(grid_for(nb, 256, 4096)), dim3(256), 0, s, rp, n32, nb,
                      L.coord, L.carry_row, L.closes);
   PP_LAUNCHED("k_partition/k_block_flags");
@@ -881,8 +897,14 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
     double *t_out = L.tele + 64 * ((it + 1) & 1);
     double *s_out = sums ? sums + int64_t(it + 1) * k : nullptr;
     if ((st = timed_begin(s)) != PP_OK) return st;
-    if (k == 1)
-      hipLaunchKernelGGL((k_spmv<V, kIpt>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x, yv,
+    if (k == 1 && ipt == 4)
+      hipLaunchKernelGGL((k_spmv<V, 4>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x, yv,
+                         n32, L.coord, c, t_in, L.blk_ysum, L.blk_carry, L.blk_head);
+    else if (k == 1 && ipt == 16)
+      hipLaunchKernelGGL((k_spmv<V, 16>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x, yv,
+                         n32, L.coord, c, t_in, L.blk_ysum, L.blk_carry, L.blk_head);
+    else if (k == 1)
+      hipLaunchKernelGGL((k_spmv<V, 8>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x, yv,
                          n32, L.coord, c, t_in, L.blk_ysum, L.blk_carry, L.blk_head);
     else
       launch_spmm<V>(lanes, nb, s, rp, col, val, x, yv, n32, k, L.coord, c, t_in, L.blk_ysum,
@@ -931,6 +953,20 @@ int32_t kernel_times(float *ms, int32_t cap) {
   for (int i = 0; i < n; ++i)
     if (hipEventElapsedTime(ms + i, g_timing.start[i], g_timing.stop[i]) != hipSuccess) return -1;
   return n;
+}
+
+pp_status set_k3_config(int32_t ipt, int32_t rhs_lanes) {
+  if (ipt != 4 && ipt != 8 && ipt != 16) return fail(PP_EINVAL, "items per thread %d", ipt);
+  if (rhs_lanes != 0 && (rhs_lanes < 2 || rhs_lanes > 64 || (rhs_lanes & (rhs_lanes - 1))))
+    return fail(PP_EINVAL, "rhs lanes %d", rhs_lanes);
+  g_cfg.ipt = ipt;
+  g_cfg.rhs_lanes = rhs_lanes;
+  return PP_OK;
+}
+
+void get_k3_config(int32_t *ipt, int32_t *rhs_lanes) {
+  *ipt = g_cfg.ipt;
+  *rhs_lanes = g_cfg.rhs_lanes;
 }
 
 size_t pagerank_ws_bytes(int64_t n, int64_t nnz_cap, pp_dtype dt, int32_t nrhs) {

@@ -174,6 +174,17 @@ pp_status pp_pagerank_graphs(int32_t ngraphs, const pp_graph *graphs, int64_t ma
                        as_stream(stream));
 }
 
+pp_status pp_set_k3_config(const pp_k3_config *cfg) {
+  if (!cfg) return set_k3_config(8, 0);
+  return set_k3_config(cfg->items_per_thread, cfg->rhs_lanes);
+}
+
+pp_status pp_get_k3_config(pp_k3_config *cfg) {
+  if (!cfg) return fail(PP_EINVAL, "pp_get_k3_config: null");
+  get_k3_config(&cfg->items_per_thread, &cfg->rhs_lanes);
+  return PP_OK;
+}
+
 pp_status pp_set_kernel_timing(int enable) { return set_kernel_timing(enable != 0); }
 
 int32_t pp_kernel_times(float *ms, int32_t cap) {

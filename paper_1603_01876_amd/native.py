@@ -45,6 +45,10 @@ class _Csr(ctypes.Structure):
                 ("val", ctypes.c_void_p)]
 
 
+class _K3Config(ctypes.Structure):
+    _fields_ = [("items_per_thread", ctypes.c_int32), ("rhs_lanes", ctypes.c_int32)]
+
+
 class _Graph(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
                 ("col", ctypes.c_void_p), ("val", ctypes.c_void_p), ("r", ctypes.c_void_p),
@@ -70,6 +74,8 @@ SIGNATURES = {
     "pp_pagerank_graphs": (ctypes.c_int, [_I32, _VP, _I64, ctypes.c_int, _I32, _D, _I32, _VP,
                                           _SZ, _VP]),
     "pp_graphs_max_n": (_I64, [ctypes.c_int]),
+    "pp_set_k3_config": (ctypes.c_int, [ctypes.c_void_p]),
+    "pp_get_k3_config": (ctypes.c_int, [ctypes.c_void_p]),
     "pp_set_kernel_timing": (ctypes.c_int, [ctypes.c_int]),
     "pp_kernel_times": (_I32, [ctypes.POINTER(ctypes.c_float), _I32]),
 }
@@ -282,6 +288,18 @@ def pagerank_graphs(batch: GraphBatch, iters: int = 20, c: float = 0.85, use_gra
     _check(lib().pp_pagerank_graphs(len(batch), batch.table.data_ptr(), mx, batch.dtype, iters,
                                     c, int(bool(use_graph)), batch.ws.data_ptr(),
                                     batch.ws.numel(), _stream()), "pp_pagerank_graphs")
+
+
+def set_k3_config(items_per_thread: int = 8, rhs_lanes: int = 0) -> None:
+    """Launch configuration of pagerank() (see pp_set_k3_config)."""
+    cfg = _K3Config(items_per_thread, rhs_lanes)
+    _check(lib().pp_set_k3_config(ctypes.addressof(cfg)), "pp_set_k3_config")
+
+
+def get_k3_config() -> tuple[int, int]:
+    cfg = _K3Config()
+    _check(lib().pp_get_k3_config(ctypes.addressof(cfg)), "pp_get_k3_config")
+    return int(cfg.items_per_thread), int(cfg.rhs_lanes)
 
 
 # ------------------------------------------------------------ instrumentation

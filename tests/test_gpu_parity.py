@@ -403,3 +403,43 @@ def test_spmm_kronecker_s16_relabelled():
     ous, ovs = oracle.sort(scale, ou, ov)
     f = oracle.filter(scale, ous, ovs)
     run_k3_multi(f.n, f.A_rp, f.A_col, f.A_val, "f32", 32, weights=f.d_out)
+
+
+# ------------------------------------------------------------ launch configs
+@pytest.mark.parametrize("ipt", [4, 8, 16])
+def test_spmv_configs_agree(ipt):
+    scale = 14
+    ou, ov = oracle.generate(okron(spec(scale)))
+    ous, ovs = oracle.sort(scale, ou, ov)
+    f = oracle.filter(scale, ous, ovs)
+    pp.set_k3_config(ipt, 0)
+    try:
+        got, sums, want, wsums = run_k3(f.n, f.A_rp, f.A_col, f.A_val, "f64", weights=f.d_out)
+        assert rel_l1(got, want) <= 1e-12
+        got, sums, want, wsums = run_k3(f.n, f.A_rp, f.A_col, f.A_val, "f32")
+        assert rel_l1(got, want) <= 1e-5
+    finally:
+        pp.set_k3_config(8, 0)
+
+
+def test_spmm_lane_width_and_autotuner(tmp_path):
+    from paper_1603_01876_amd import autotune
+    rng = np.random.default_rng(3)
+    n = 20000
+    rp, col, val = random_matrix(n, rng, long_rows=[(1, 9000)])
+    pp.set_k3_config(8, 64)
+    try:
+        run_k3_multi(n, rp, col, val, "f32", 12)
+    finally:
+        pp.set_k3_config(8, 0)
+    trp, tcol, tval = oracle.transpose_csr(n, rp, col, val)
+    AT = pp.CSR.from_arrays(n, trp, tcol, tval, "f32")
+    cache = str(tmp_path / "tune.json")
+    for k in (1, 12):
+        entry = autotune.tune(AT, "f32", k, cache=cache)
+        assert tuple(entry["config"]) in autotune.candidates(k)
+        assert set(entry["ms"]) == {f"{a},{b}" for a, b in autotune.candidates(k)}
+        assert pp.get_k3_config() == tuple(entry["config"])
+        again = autotune.tune(AT, "f32", k, cache=cache)       # served from the cache
+        assert again == entry
+    pp.set_k3_config(8, 0)
