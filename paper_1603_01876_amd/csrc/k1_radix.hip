@@ -106,16 +106,26 @@ __global__ __launch_bounds__(kThreads) void k_radix_count(RadixIn in, int64_t m,
     counts[int64_t(d) * ntiles + blockIdx.x] = wh[0][d] + wh[1][d] + wh[2][d] + wh[3][d];
 }
 
+// Scatter: every key's position is (digit's global offset for this tile) +
+// (keys of that digit in earlier waves) + (its rank in its wave).  The tile
+// is first written to LDS in digit order, then read back in that order and
+// stored, so consecutive lanes store consecutive addresses of one digit's
+// run instead of 64 different buckets per instruction.
 template <bool kSrcSep, bool kDstSep>
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(RadixIn in, RadixOut out, int64_t m,
                                                             int shift, int bits, int64_t ntiles,
                                                             const uint32_t *__restrict__ offsets) {
   __shared__ uint32_t wh[kWaves][256];
+  __shared__ uint32_t s_tile_off[256];   // first slot of each digit in the tile
+  __shared__ uint32_t s_glob[256];       // global position of that slot
+  __shared__ uint32_t s_scan[4];
+  __shared__ uint64_t s_keys[kTile];
   const uint32_t dmask = (1u << bits) - 1u;
   for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&wh[0][0])[i] = 0u;
   __syncthreads();
   const int w = threadIdx.x / kWave;
-  const int64_t base = int64_t(blockIdx.x) * kTile + int64_t(w) * kWaveKeys;
+  const int64_t tile0 = int64_t(blockIdx.x) * kTile;
+  const int64_t base = tile0 + int64_t(w) * kWaveKeys;
   uint64_t keys[kPerThread];
   uint32_t rank[kPerThread];
 #pragma unroll
@@ -126,24 +136,42 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(RadixIn in, RadixOut
     rank[r] = wave_rank(digit_of(keys[r], shift, dmask), valid, bits, wh[w]);
   }
   __syncthreads();
-  // wh[w][d] <- global offset of digit d for this tile + keys of digit d in
-  // the waves before w.
-  for (int d = threadIdx.x; d <= int(dmask); d += kThreads) {
-    uint32_t run = offsets[int64_t(d) * ntiles + blockIdx.x];
+  // Per digit: prefix over waves (in place), tile total, then an exclusive
+  // scan over digits gives each digit's first slot in the tile.
+  const int d = threadIdx.x;   // 256 threads, one digit each
+  uint32_t total = 0;
+  if (d <= int(dmask)) {
 #pragma unroll
     for (int v = 0; v < kWaves; ++v) {
       const uint32_t c = wh[v][d];
-      wh[v][d] = run;
-      run += c;
+      wh[v][d] = total;
+      total += c;
     }
+  }
+  uint32_t all;
+  const uint32_t first = block_exscan256(total, s_scan, &all);
+  if (d <= int(dmask)) {
+    s_tile_off[d] = first;
+    s_glob[d] = offsets[int64_t(d) * ntiles + blockIdx.x];
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kPerThread; ++r) {
     const int64_t i = base + r * kWave + lane_id();
     if (i < m) {
-      const uint32_t d = digit_of(keys[r], shift, dmask);
-      store_key<kDstSep>(out, int64_t(wh[w][d]) + rank[r], keys[r]);
+      const uint32_t dg = digit_of(keys[r], shift, dmask);
+      s_keys[s_tile_off[dg] + wh[w][dg] + rank[r]] = keys[r];
+    }
+  }
+  __syncthreads();
+  const int64_t valid_in_tile = m - tile0 < kTile ? m - tile0 : kTile;
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) {
+    const int slot = r * kThreads + threadIdx.x;
+    if (slot < valid_in_tile) {
+      const uint64_t key = s_keys[slot];
+      const uint32_t dg = digit_of(key, shift, dmask);
+      store_key<kDstSep>(out, int64_t(s_glob[dg]) + (slot - s_tile_off[dg]), key);
     }
   }
 }

@@ -43,7 +43,7 @@ struct K3Config {
   int rhs_lanes = 0;  // 0: next power of two >= nrhs
 };
 K3Config g_cfg;
-constexpr int kFinishPer = kThreads * 8;     // spmv workgroups per finish workgroup
+constexpr int kFinishPer = kThreads;         // spmv workgroups per finish workgroup
 constexpr int64_t kSumChunk = kThreads * 64; // entries of r per workgroup of sum(r_0)
 
 // ------------------------------------------------------------ accumulators
