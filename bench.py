@@ -49,6 +49,9 @@ def parse():
                     help="skip the many-small-graphs form (512 graphs, S uniform on 8..14)")
     ap.add_argument("--ngraphs", type=int, default=512)
     ap.add_argument("--no-tune", action="store_true", help="keep the default K3 launch config")
+    ap.add_argument("--k3-config", default=None,
+                    help="K3 launch config 'items_per_thread,rhs_lanes,slab_log2' applied before "
+                         "any run (with --no-tune it is the one timed)")
     ap.add_argument("--no-relabel", action="store_true",
                     help="iterate on K2's labels (no degree-ordered relabelling inside K3)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -90,6 +93,14 @@ def measured_traffic(scale: int, dtype: str):
     return (float(fields["fetch_bytes_per_launch"]) + float(fields["write_bytes_per_launch"])) / 1e9
 
 
+def spmv_label(cfg, dt):
+    v = "float" if dt == "f32" else "double"
+    if cfg[2] > 0:
+        return (f"segmented SpMV iteration, slabs of 2^{cfg[2]} columns: k_spmv<{v},{cfg[0]},raw> "
+                f"+ k_fix_raw<{v}> + k_seg_combine<{v}>")
+    return f"k_spmv<{v},{cfg[0]}>"
+
+
 def batched_form(args, pp, workloads, torch):
     """K3 with nrhs independent vectors on one S=22 matrix (one SpMM per
     iteration) beside nrhs-times the single-vector FP32 run."""
@@ -102,11 +113,15 @@ def batched_form(args, pp, workloads, torch):
     AT, _, d_out = pp.filter(S, us, vs, "f32")
     del us, vs
     w = None if args.no_relabel else d_out
-    ws = torch.empty(pp.workspace_bytes(pp.K3, n, AT.nnz, "f32", k), dtype=torch.uint8, device=dev)
+    ws = torch.empty(max(pp.workspace_bytes(pp.K3, n, AT.nnz, "f32", k),
+                         pp.workspace_bytes(pp.K3, n, AT.nnz, "f32", 1)),
+                     dtype=torch.uint8, device=dev)
     tuned = None
     if not args.no_tune:
         from paper_1603_01876_amd import autotune
-        tuned = autotune.tune(AT, "f32", k, w, ws=ws, force=True)
+        tuned = autotune.tune(AT, "f32", k, w, ws=ws, iters=args.iters, force=True)
+        if not tuned["relabel"]:
+            w = None
     rk = torch.empty((n, k), dtype=torch.float32, device=dev)
     r1 = torch.empty(n, dtype=torch.float32, device=dev)
 
@@ -128,16 +143,19 @@ def batched_form(args, pp, workloads, torch):
         pp.init_r(n, workloads.BASE_SEED, "f32", k, out=rk, ws=ws)
         pp.pagerank(AT, rk, iters=args.iters, c=workloads.DAMPING, sums=False, ws=ws, weights=w)
 
-    def run_1():
-        pp.init_r(n, workloads.BASE_SEED, "f32", 1, out=r1, ws=ws)
-        pp.pagerank(AT, r1, iters=args.iters, c=workloads.DAMPING, sums=False, ws=ws, weights=w)
-
     run_k()
     tk, kk = timed(run_k)
     saved = pp.get_k3_config()
+    w1 = w
     if not args.no_tune:
         from paper_1603_01876_amd import autotune
-        autotune.tune(AT, "f32", 1, w, ws=ws, force=True)
+        t1cfg = autotune.tune(AT, "f32", 1, w, ws=ws, iters=args.iters, force=True)
+        w1 = w if t1cfg["relabel"] else None
+
+    def run_1():
+        pp.init_r(n, workloads.BASE_SEED, "f32", 1, out=r1, ws=ws)
+        pp.pagerank(AT, r1, iters=args.iters, c=workloads.DAMPING, sums=False, ws=ws, weights=w1)
+
     run_1()
     t1, k1 = timed(run_1)
     pp.set_k3_config(*saved)
@@ -275,6 +293,8 @@ def main():
 
     torch.cuda.set_device(0)
     dev = "cuda"
+    if args.k3_config:
+        pp.set_k3_config(*[int(x) for x in args.k3_config.split(",")])
     S, dt = args.scale, args.dtype
     spec = workloads.pipeline(S)
     n, m = spec.n, spec.m
@@ -296,6 +316,7 @@ def main():
     sums = torch.empty(args.iters + 1, dtype=torch.float64, device=dev)
     ws3 = torch.empty(pp.workspace_bytes(pp.K3, n, m, dt), dtype=torch.uint8, device=dev)
     rseed = workloads.BASE_SEED
+    state = {"relabel": not args.no_relabel}
 
     def step(timed):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
@@ -308,7 +329,7 @@ def main():
         ev[3].record()
         pp.init_r(n, rseed, dt, out=r, ws=ws3)
         pp.pagerank(AT, r, iters=args.iters, c=workloads.DAMPING, sums=sums, ws=ws3,
-                    weights=None if args.no_relabel else d_out)
+                    weights=d_out if state["relabel"] else None)
         ev[4].record()
         return ev
 
@@ -319,8 +340,10 @@ def main():
         if i == 0 and not args.no_tune:
             from paper_1603_01876_amd import autotune
             tuned = autotune.tune(AT, dt, 1, None if args.no_relabel else d_out, ws=ws3,
-                                  force=True)
-            log(f"autotuned K3 config {tuned['config']} from {tuned['ms']}")
+                                  iters=args.iters, force=True)
+            state["relabel"] = tuned["relabel"]
+            log(f"autotuned K3 config {tuned['config']} relabel={tuned['relabel']} "
+                f"from {tuned['ms']}")
 
     pp.set_kernel_timing(True)
     spmv_ms = []
@@ -371,14 +394,15 @@ def main():
             "k3_edges_per_s": value,
             "spmv_avg_ms": spmv_avg_s * 1e3, "spmv_launches": len(spmv_ms),
         },
-        "roofline": {"bound": "hbm", "kernel": f"k_spmv<{'float' if dt == 'f32' else 'double'}>",
+        "roofline": {"bound": "hbm", "kernel": spmv_label(pp.get_k3_config(), dt),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(S, dt),
                      "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "algorithmic_bytes_per_launch": nbytes},
         "sum_r": {"first": float(sums_h[0]), "last": float(sums_h[-1])},
         "k3_config": {"items_per_thread": pp.get_k3_config()[0],
-                      "relabel": not args.no_relabel,
+                      "slab_log2": pp.get_k3_config()[2],
+                      "relabel": state["relabel"],
                       "tuned": None if args.no_tune or args.warmup < 1 else tuned["ms"]},
     }
 
@@ -394,6 +418,15 @@ def main():
         ws64 = torch.empty(pp.workspace_bytes(pp.K3, n, m, "f64"), dtype=torch.uint8, device=dev)
         r64 = torch.empty(n, dtype=torch.float64, device=dev)
         sums64 = torch.empty(args.iters + 1, dtype=torch.float64, device=dev)
+        saved = pp.get_k3_config()
+        w64 = None if args.no_relabel else d_out
+        tuned64 = None
+        if not args.no_tune:
+            from paper_1603_01876_amd import autotune
+            tuned64 = autotune.tune(AT64, "f64", 1, w64, ws=ws64, iters=args.iters, force=True)
+            if not tuned64["relabel"]:
+                w64 = None
+        cfg64 = pp.get_k3_config()
         times = []
         pp.set_kernel_timing(True)
         spmv64 = []
@@ -402,12 +435,13 @@ def main():
             e0.record()
             pp.init_r(n, rseed, "f64", out=r64, ws=ws64)
             pp.pagerank(AT64, r64, iters=args.iters, c=workloads.DAMPING, sums=sums64, ws=ws64,
-                        weights=None if args.no_relabel else d_out)
+                        weights=w64)
             e1.record()
             spmv64 += pp.kernel_times()
             torch.cuda.synchronize()
             times.append(e0.elapsed_time(e1) / 1e3)
         pp.set_kernel_timing(False)
+        pp.set_k3_config(*saved)
         t64 = sum(times) / len(times)
         s64 = sum(spmv64) / len(spmv64) / 1e3
         err = float((r32 - r64).abs().sum() / r64.abs().sum())
@@ -415,7 +449,9 @@ def main():
         out["forms"] = {
             "f64": {"k3_edges_per_s": args.iters * m / t64, "k3_ms": t64 * 1e3,
                     "spmv_avg_ms": s64 * 1e3, "spmv_GBps": b64 / s64 / 1e9,
-                    "spmv_frac_of_peak": b64 / s64 / 1e9 / HBM_PEAK_GBS},
+                    "spmv_frac_of_peak": b64 / s64 / 1e9 / HBM_PEAK_GBS,
+                    "kernel": spmv_label(cfg64, "f64"), "relabel": w64 is not None,
+                    "tuned": None if tuned64 is None else tuned64["ms"]},
             "f32_speedup_over_f64": t64 / mean["k3"],
             "f32_rel_l1_vs_f64_gpu": err,
         }

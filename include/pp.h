@@ -201,12 +201,19 @@ int64_t pp_graphs_max_n(pp_dtype dt);
  * the sparse matrix-vector kernel (a workgroup tile is 256 times that);
  * rhs_lanes: lanes per right-hand-side group of the sparse matrix-dense
  * matrix kernel, 0 = the next power of two >= nrhs, else a power of two in
- * [nrhs, 64].  Results do not depend on the configuration beyond the order
- * of floating-point sums.  pp_set_k3_config(NULL) restores the defaults
- * (8, 0). */
+ * [nrhs, 64].  slab_log2 in [0, 30]: 0 iterates over the whole matrix in
+ * one pass; k > 0 (nrhs == 1 only) cuts the columns into slabs of 2^k
+ * vertices (widened until there are at most 256) and stores the matrix
+ * slab by slab, so each pass gathers from an L2-sized range of r
+ * (column segmenting, Zhang et al., IEEE BigData 2017).  The segmented
+ * layout is built inside each pp_pagerank call, which then synchronizes
+ * its stream once to read the number of (slab, row) pairs.  Results do not
+ * depend on the configuration beyond the order of floating-point sums.
+ * pp_set_k3_config(NULL) restores the defaults (8, 0, 0). */
 typedef struct {
   int32_t items_per_thread;
   int32_t rhs_lanes;
+  int32_t slab_log2;
 } pp_k3_config;
 pp_status pp_set_k3_config(const pp_k3_config *cfg);
 pp_status pp_get_k3_config(pp_k3_config *cfg);

@@ -1,13 +1,20 @@
 """Autotuner for the K3 launch configuration.
 
-For a given matrix, value type and number of right-hand sides it measures
-every candidate configuration of pagerank() -- SpMV items per thread
-(4, 8, 16: the merge-path tile is 256 times that) or SpMM lane-group width
-(the next power of two >= nrhs, or 64) -- with the library's HIP-event timing
-of the sparse kernel, keeps the fastest and caches it in a JSON file keyed by
-device architecture, size bucket, dtype, nrhs and whether vertices are
-relabelled.  All candidates compute the same result up to the order of
-floating-point sums.
+For a given matrix, value type, number of right-hand sides and iteration
+count it runs pagerank() once per candidate configuration and keeps the one
+whose whole call is fastest: per-call set-up (vertex relabelling, the
+column-segmented layout) is paid once per call, so it is measured together
+with the iterations it serves.  Candidates are
+
+* nrhs == 1: SpMV items per thread (8, 16; the merge-path tile is 256 times
+  that) x column slab width (none, or 2^18, 2^19, 2^20 vertices) x, when the
+  caller passes weights, vertex relabelling on or off;
+* nrhs > 1: SpMM lane-group width (the next power of two >= nrhs, or 64).
+
+The choice is applied with set_k3_config() and cached in a JSON file keyed
+by device architecture, size bucket, dtype, nrhs, iteration count and
+whether weights were offered.  All candidates compute the same result up to
+the order of floating-point sums.
 """
 from __future__ import annotations
 
@@ -20,23 +27,31 @@ import torch
 from . import native as pp
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pp_mi355x", "k3_tuning.json")
+SLABS = (0, 18, 19, 20)
 
 
-def candidates(nrhs: int) -> list[tuple[int, int]]:
+def candidates(nrhs: int, relabel_options=(False,)) -> list[tuple[int, int, int, bool]]:
+    """(items_per_thread, rhs_lanes, slab_log2, relabel) tuples."""
     if nrhs == 1:
-        return [(4, 0), (8, 0), (16, 0)]
+        return [(ipt, 0, slab, rl) for rl in relabel_options for slab in SLABS
+                for ipt in (8, 16)]
     lanes = 2
     while lanes < nrhs:
         lanes *= 2
-    return [(8, lanes)] + ([(8, 64)] if lanes < 64 else [])
+    return [(8, lanes, 0, rl) for rl in relabel_options] + \
+        ([(8, 64, 0, rl) for rl in relabel_options] if lanes < 64 else [])
 
 
-def key(AT, dtype, nrhs: int, relabel: bool) -> str:
+def name(cand) -> str:
+    return ",".join(str(int(x)) for x in cand)
+
+
+def key(AT, dtype, nrhs: int, relabel: bool, iters: int) -> str:
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] \
         if torch.cuda.is_available() else "cpu"
     nb = int(math.log2(max(AT.n, 1)))
     zb = int(math.log2(max(AT.nnz, 1)))
-    return f"{arch}|n2^{nb}|nnz2^{zb}|{dtype}|k{nrhs}|relabel{int(relabel)}"
+    return f"{arch}|n2^{nb}|nnz2^{zb}|{dtype}|k{nrhs}|it{iters}|weights{int(relabel)}"
 
 
 def _load(path):
@@ -47,16 +62,17 @@ def _load(path):
         return {}
 
 
-def tune(AT, dtype="f32", nrhs: int = 1, weights=None, iters: int = 4, cache: str | None = None,
-         force: bool = False, ws=None) -> dict:
+def tune(AT, dtype="f32", nrhs: int = 1, weights=None, iters: int = 20, cache: str | None = None,
+         force: bool = False, ws=None, repeats: int = 2) -> dict:
     """Measures the candidates on this matrix, applies the fastest with
-    set_k3_config() and returns {"config": [ipt, lanes], "ms": {...}}."""
+    set_k3_config() and returns {"config": [ipt, lanes, slab_log2],
+    "relabel": bool, "ms": {candidate: ms per call}}.  The caller passes
+    `weights` to pagerank() only when "relabel" is true."""
     cache = cache or DEFAULT_CACHE
-    k = key(AT, dtype, nrhs, weights is not None)
+    k = key(AT, dtype, nrhs, weights is not None, iters)
     table = _load(cache)
     if not force and k in table:
-        best = table[k]["config"]
-        pp.set_k3_config(*best)
+        pp.set_k3_config(*table[k]["config"])
         return table[k]
     n = AT.n
     shape = (n,) if nrhs == 1 else (n, nrhs)
@@ -65,23 +81,29 @@ def tune(AT, dtype="f32", nrhs: int = 1, weights=None, iters: int = 4, cache: st
     if ws is None:
         ws = torch.empty(pp.workspace_bytes(pp.K3, n, AT.nnz, dtype, nrhs), dtype=torch.uint8,
                          device="cuda")
+    opts = (False, True) if weights is not None else (False,)
     times = {}
-    pp.set_kernel_timing(True)
-    try:
-        for ipt, lanes in candidates(nrhs):
-            pp.set_k3_config(ipt, lanes)
+    for cand in candidates(nrhs, opts):
+        ipt, lanes, slab, rl = cand
+        pp.set_k3_config(ipt, lanes, slab)
+        w = weights if rl else None
+        best = float("inf")
+        for rep in range(repeats + 1):
             pp.init_r(n, 1, dtype, nrhs, out=r, ws=ws)
-            pp.pagerank(AT, r, iters=1, sums=False, ws=ws, weights=weights)   # warm-up
-            pp.kernel_times()
-            pp.pagerank(AT, r, iters=iters, sums=False, ws=ws, weights=weights)
-            t = sorted(pp.kernel_times())
-            times[f"{ipt},{lanes}"] = t[len(t) // 2]
-    finally:
-        pp.set_kernel_timing(False)
-    best = min(times, key=times.get)
-    cfg = [int(x) for x in best.split(",")]
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record()
+            pp.pagerank(AT, r, iters=iters, sums=False, ws=ws, weights=w)
+            t1.record()
+            t1.synchronize()
+            if rep > 0:                       # the first call warms up
+                best = min(best, t0.elapsed_time(t1))
+        times[name(cand)] = best
+    win = min(times, key=times.get)
+    cand = [int(x) for x in win.split(",")]
+    cfg, relabel = cand[:3], bool(cand[3])
     pp.set_k3_config(*cfg)
-    entry = {"config": cfg, "ms": times}
+    entry = {"config": cfg, "relabel": relabel, "ms": times}
     table[k] = entry
     try:
         os.makedirs(os.path.dirname(cache), exist_ok=True)

@@ -32,22 +32,6 @@ __device__ __forceinline__ uint32_t digit_of(uint64_t key, int shift, uint32_t d
   return uint32_t(key >> (32 + shift)) & dmask;
 }
 
-// Rank of this lane's key among the earlier keys of the same digit in this
-// wave's chunk; advances the wave's per-digit counters `wh`.
-__device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, int bits, uint32_t *wh) {
-  uint64_t match = __ballot(valid);
-  for (int b = 0; b < bits; ++b) {
-    const bool bit = (d >> b) & 1u;
-    const uint64_t bal = __ballot(bit);
-    match &= bit ? bal : ~bal;
-  }
-  const uint64_t below = match & lanes_below();
-  uint32_t before = 0;
-  if (valid) before = wh[d];
-  if (valid && below == 0) wh[d] = before + uint32_t(__popcll(match));
-  return before + uint32_t(__popcll(below));
-}
-
 template <bool kSep>
 __device__ __forceinline__ uint64_t load_key(const RadixIn &in, int64_t i) {
   if constexpr (kSep) {
@@ -96,7 +80,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_count(RadixIn in, int64_t m,
         key = load_key<kSep>(in, i);
       }
     }
-    wave_rank(digit_of(key, shift, dmask), valid, bits, wh[w]);
+    wave_digit_rank(digit_of(key, shift, dmask), valid, bits, wh[w]);
   }
   if constexpr (kCheck) {
     if (bad) atomicOr(flag, bad);
@@ -133,7 +117,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(RadixIn in, RadixOut
     const int64_t i = base + r * kWave + lane_id();
     const bool valid = i < m;
     keys[r] = valid ? load_key<kSrcSep>(in, i) : 0ull;
-    rank[r] = wave_rank(digit_of(keys[r], shift, dmask), valid, bits, wh[w]);
+    rank[r] = wave_digit_rank(digit_of(keys[r], shift, dmask), valid, bits, wh[w]);
   }
   __syncthreads();
   // Per digit: prefix over waves (in place), tile total, then an exclusive
@@ -206,6 +190,41 @@ size_t layout_bytes(int64_t m) {
 }  // namespace
 
 size_t radix_ws_bytes(int64_t m, int32_t /*key_bits*/) { return layout_bytes(m); }
+
+size_t radix_pingpong_counts(int64_t m) { return size_t(256) * size_t((m + kTile - 1) / kTile); }
+
+pp_status radix_sort_pingpong(uint64_t *a, uint64_t *b, int64_t m, int32_t key_bits,
+                              uint32_t *counts, uint32_t *scan_ws, hipStream_t s) {
+  if (m <= 0) return PP_OK;
+  if (key_bits < 1 || key_bits > 31) return fail(PP_EINVAL, "radix key bits %d", key_bits);
+  if (key_bits < 2) key_bits = 2;   // two passes of one bit: the keys end up in a again
+  const int64_t ntiles = (m + kTile - 1) / kTile;
+  if (ntiles >= (int64_t(1) << 31)) return fail(PP_ERANGE, "too many tiles");
+  int npass = (key_bits + 7) / 8;
+  npass += npass & 1;
+  const int base_bits = key_bits / npass, extra = key_bits % npass;
+  int shift = 0;
+  uint64_t *src = a, *dst = b;
+  const dim3 grid = dim3(static_cast<unsigned>(ntiles)), block = dim3(kThreads);
+  for (int p = 0; p < npass; ++p) {
+    const int bits = base_bits + (p < extra ? 1 : 0);
+    const RadixIn in{src, nullptr, nullptr};
+    const RadixOut out{dst, nullptr, nullptr};
+    hipLaunchKernelGGL((k_radix_count<false, false>), grid, block, 0, s, in, m, shift, bits,
+                       ntiles, counts, int64_t(0), 0, nullptr);
+    PP_LAUNCHED("k_radix_count (pingpong)");
+    pp_status st = exscan_u32(counts, counts, (int64_t(1) << bits) * ntiles, scan_ws, nullptr, s);
+    if (st != PP_OK) return st;
+    hipLaunchKernelGGL((k_radix_scatter<false, false>), grid, block, 0, s, in, out, m, shift,
+                       bits, ntiles, counts);
+    PP_LAUNCHED("k_radix_scatter (pingpong)");
+    shift += bits;
+    uint64_t *t = src;
+    src = dst;
+    dst = t;
+  }
+  return PP_OK;
+}
 
 pp_status radix_sort(RadixIn in, RadixOut out, int64_t m, int32_t key_bits, void *ws,
                      size_t ws_bytes, int64_t check_n, bool check_sorted_lo, uint32_t *flag,

@@ -41,6 +41,7 @@ constexpr int kItemsMax = kThreads * 16;     // largest SpMV tile (sizes relabel
 struct K3Config {
   int ipt = 8;
   int rhs_lanes = 0;  // 0: next power of two >= nrhs
+  int slab_log2 = 0;  // 0: one pass over all columns; else slab width 2^slab_log2
 };
 K3Config g_cfg;
 constexpr int kFinishPer = kThreads;         // spmv workgroups per finish workgroup
@@ -130,12 +131,16 @@ __device__ __forceinline__ AccF shfl_up_acc(AccF a, int o) {
   return AccF{__shfl_up(a.s, o, kWave), __shfl_up(a.e, o, kWave)};
 }
 
-template <typename V, int IPT>
+// With kRaw the rows are (slab, row) pairs of the column-segmented layout
+// below: each completed row stores its raw accumulator into part[] instead
+// of c * sum + t into y, and no sum(y) is formed.
+template <typename V, int IPT, bool kRaw>
 __global__ __launch_bounds__(kThreads) void k_spmv(
     const int32_t *__restrict__ rp, const int32_t *__restrict__ col, const V *__restrict__ val,
     const V *__restrict__ x, V *__restrict__ y, int32_t n, const int2 *__restrict__ coord,
     double c, const double *__restrict__ tele, double *__restrict__ blk_ysum,
-    typename Form<V>::Acc *__restrict__ blk_carry, typename Form<V>::Acc *__restrict__ blk_head) {
+    typename Form<V>::Acc *__restrict__ blk_carry, typename Form<V>::Acc *__restrict__ blk_head,
+    typename Form<V>::Acc *__restrict__ part) {
   using Acc = typename Form<V>::Acc;
   constexpr int kD = kThreads * IPT;
   constexpr int kWaves = kThreads / kWave;
@@ -217,6 +222,8 @@ __global__ __launch_bounds__(kThreads) void k_spmv(
       if (first_row < 0) {
         first_row = ti;
         first = acc;
+      } else if constexpr (kRaw) {
+        part[i0 + ti] = acc;
       } else {
         const V yv = Form<V>::finish(acc, c, tk);
         y[i0 + ti] = yv;
@@ -266,6 +273,8 @@ __global__ __launch_bounds__(kThreads) void k_spmv(
     const Acc sum = tid > 0 ? merge(s_pre[tid - 1], first) : first;
     if (R == i0 && mid_row) {
       blk_head[b] = sum;  // row began in an earlier workgroup: completed later
+    } else if constexpr (kRaw) {
+      part[R] = sum;
     } else {
       const V yv = Form<V>::finish(sum, c, tk);
       y[R] = yv;
@@ -273,8 +282,10 @@ __global__ __launch_bounds__(kThreads) void k_spmv(
     }
   }
   if (tid == kThreads - 1) blk_carry[b] = c1.x < n ? v : Acc{};
-  const double bs = block_sum256(ysum, s_red);
-  if (tid == 0) blk_ysum[b] = bs;
+  if constexpr (!kRaw) {
+    const double bs = block_sum256(ysum, s_red);
+    if (tid == 0) blk_ysum[b] = bs;
+  }
 }
 
 // ------------------------------------------------------------------ SpMM
@@ -714,6 +725,312 @@ __global__ __launch_bounds__(256) void k_permute_out(const V *__restrict__ src,
   }
 }
 
+// --------------------------------------------- column-segmented iteration
+// CSR segmenting (Zhang, Kiriansky et al., "Making caches work for graph
+// analytics", IEEE BigData 2017).  The columns of the iterate matrix are cut
+// into slabs of 2^sbits vertices.  Entries are stored slab by slab, each
+// slab in row order (entries of a row keep their order), so one pass over a
+// slab gathers only from a range of r small enough to stay in L2.  Every
+// (slab, row) run of entries is a "pair"; the pairs form a CSR of their own
+// that the merge-path SpMV walks in raw mode, writing one partial sum per
+// pair.  A combine pass then adds each row's partials in slab order and
+// applies c * sum + t.  Sums stay in a fixed order, so results are
+// reproducible; they differ from the unsegmented order only by rounding.
+constexpr int kSegTile = kThreads * 16;   // merge items per build tile
+constexpr int kSegPer = kSegTile / kThreads;
+constexpr int kMaxSlabs = 256;
+constexpr int kCombItems = kThreads * 16; // rows + pairs per combine workgroup
+
+__device__ __forceinline__ int32_t row_of(const int32_t *s_end, int32_t na, int32_t e) {
+  int32_t lo = 0, hi = na;
+  while (lo < hi) {
+    const int32_t m = (lo + hi) >> 1;
+    if (s_end[m] <= e)
+      lo = m + 1;
+    else
+      hi = m;
+  }
+  return lo;
+}
+
+// Entries of each build tile per slab -> cnt[s * ntiles + tile].
+__global__ __launch_bounds__(kThreads) void k_seg_count(const int32_t *__restrict__ col,
+                                                        const int2 *__restrict__ coord,
+                                                        int32_t sbits, int32_t ns, int32_t dbits,
+                                                        int32_t ntiles, uint32_t *__restrict__ cnt) {
+  constexpr int kWaves = kThreads / kWave;
+  __shared__ uint32_t wh[kWaves][kMaxSlabs];
+  for (int i = threadIdx.x; i < kWaves * kMaxSlabs; i += kThreads) (&wh[0][0])[i] = 0u;
+  __syncthreads();
+  const int b = blockIdx.x, w = threadIdx.x / kWave;
+  const int32_t j0 = coord[b].y, nz = coord[b + 1].y - j0;
+#pragma unroll 4
+  for (int r = 0; r < kSegPer; ++r) {
+    const int32_t e = w * (kSegTile / kWaves) + r * kWave + lane_id();
+    const bool valid = e < nz;
+    const uint32_t d = valid ? uint32_t(col[j0 + e]) >> sbits : 0u;
+    wave_digit_rank(d, valid, dbits, wh[w]);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < ns; d += kThreads) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) t += wh[q][d];
+    cnt[int64_t(d) * ntiles + b] = t;
+  }
+}
+
+// Stable scatter of each build tile's entries (column, value, row) to their
+// slab-major positions.  Ranks come from wave ballots in entry order; the
+// tile is staged in LDS in slab order so that the stores of one slab's run
+// are contiguous.
+template <typename V>
+__global__ __launch_bounds__(kThreads) void k_seg_scatter(
+    const int32_t *__restrict__ rp, const int32_t *__restrict__ col, const V *__restrict__ val,
+    int32_t n, const int2 *__restrict__ coord, int32_t sbits, int32_t ns, int32_t dbits,
+    int32_t ntiles, const uint32_t *__restrict__ off, int32_t *__restrict__ seg_col,
+    V *__restrict__ seg_val, int32_t *__restrict__ seg_row) {
+  constexpr int kWaves = kThreads / kWave;
+  __shared__ uint32_t wh[kWaves][kMaxSlabs];
+  __shared__ uint32_t s_toff[kMaxSlabs], s_goff[kMaxSlabs];
+  __shared__ uint32_t s_scan[4];
+  __shared__ int32_t s_end[kSegTile];   // row ends; reused for staged rows
+  __shared__ int32_t s_col[kSegTile];
+  __shared__ V s_val[kSegTile];
+  for (int i = threadIdx.x; i < kWaves * kMaxSlabs; i += kThreads) (&wh[0][0])[i] = 0u;
+  const int b = blockIdx.x, tid = threadIdx.x, w = tid / kWave;
+  const int2 c0 = coord[b], c1 = coord[b + 1];
+  const int32_t i0 = c0.x, j0 = c0.y, na = c1.x - c0.x, nz = c1.y - c0.y;
+  for (int k = tid; k < na; k += kThreads) s_end[k] = rp[i0 + 1 + k] - j0;
+  __syncthreads();
+  int32_t cc[kSegPer], rr[kSegPer];
+  V vv[kSegPer];
+  uint32_t rank[kSegPer];
+#pragma unroll
+  for (int r = 0; r < kSegPer; ++r) {
+    const int32_t e = w * (kSegTile / kWaves) + r * kWave + lane_id();
+    const bool valid = e < nz;
+    cc[r] = valid ? col[j0 + e] : 0;
+    vv[r] = valid ? val[j0 + e] : V(0);
+    rr[r] = valid ? i0 + row_of(s_end, na, e) : 0;
+    rank[r] = wave_digit_rank(uint32_t(cc[r]) >> sbits, valid, dbits, wh[w]);
+  }
+  __syncthreads();
+  const int d = tid;   // one slab per thread (ns <= 256 = kThreads)
+  uint32_t total = 0;
+  if (d < ns) {
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) {
+      const uint32_t t = wh[q][d];
+      wh[q][d] = total;
+      total += t;
+    }
+  }
+  uint32_t all;
+  const uint32_t first = block_exscan256(total, s_scan, &all);
+  if (d < ns) {
+    s_toff[d] = first;
+    s_goff[d] = off[int64_t(d) * ntiles + b];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSegPer; ++r) {
+    const int32_t e = w * (kSegTile / kWaves) + r * kWave + lane_id();
+    if (e < nz) {
+      const uint32_t dg = uint32_t(cc[r]) >> sbits;
+      const uint32_t slot = s_toff[dg] + wh[w][dg] + rank[r];
+      s_col[slot] = cc[r];
+      s_val[slot] = vv[r];
+      s_end[slot] = rr[r];
+    }
+  }
+  __syncthreads();
+  for (int32_t slot = tid; slot < nz; slot += kThreads) {
+    const int32_t cv = s_col[slot];
+    const uint32_t dg = uint32_t(cv) >> sbits;
+    const int64_t pos = int64_t(s_goff[dg]) + (slot - int32_t(s_toff[dg]));
+    seg_col[pos] = cv;
+    seg_val[pos] = s_val[slot];
+    seg_row[pos] = s_end[slot];
+  }
+}
+
+// flag[j] = 1 where a (slab, row) pair starts in the slab-major order.
+__global__ __launch_bounds__(256) void k_pair_flags(const int32_t *__restrict__ seg_col,
+                                                    const int32_t *__restrict__ seg_row,
+                                                    int64_t nnz, int32_t sbits,
+                                                    uint32_t *__restrict__ flag) {
+  for (int64_t j = blockIdx.x * int64_t(256) + threadIdx.x; j < nnz;
+       j += int64_t(gridDim.x) * 256) {
+    bool f = j == 0;
+    if (!f) f = seg_row[j] != seg_row[j - 1] || (seg_col[j] >> sbits) != (seg_col[j - 1] >> sbits);
+    flag[j] = f ? 1u : 0u;
+  }
+}
+
+// pid = exclusive scan of the flags: pair p starts at entry prp[p] and
+// belongs to row pair_row[p]; prp[P] = nnz.
+__global__ __launch_bounds__(256) void k_pair_emit(const uint32_t *__restrict__ pid,
+                                                   const int32_t *__restrict__ seg_row,
+                                                   int64_t nnz, const int64_t *__restrict__ total,
+                                                   int32_t *__restrict__ prp,
+                                                   int32_t *__restrict__ pair_row) {
+  const int64_t P = *total;
+  for (int64_t j = blockIdx.x * int64_t(256) + threadIdx.x; j < nnz;
+       j += int64_t(gridDim.x) * 256) {
+    const uint32_t p = pid[j];
+    const uint32_t next = j + 1 < nnz ? pid[j + 1] : uint32_t(P);
+    if (next != p) {
+      prp[p] = int32_t(j);
+      pair_row[p] = seg_row[j];
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) prp[P] = int32_t(nnz);
+}
+
+// Row-major order of the pairs: key = row << 32 | pair, sorted stably by
+// row (so a row's pairs stay in slab order); pcount[row] counts its pairs.
+__global__ __launch_bounds__(256) void k_pair_keys(const int32_t *__restrict__ pair_row, int64_t P,
+                                                   uint64_t *__restrict__ keys,
+                                                   uint32_t *__restrict__ pcount) {
+  for (int64_t p = blockIdx.x * int64_t(256) + threadIdx.x; p < P; p += int64_t(gridDim.x) * 256) {
+    const int32_t v = pair_row[p];
+    keys[p] = (uint64_t(uint32_t(v)) << 32) | uint64_t(uint32_t(p));
+    atomicAdd(pcount + v, 1u);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_pair_index(const uint64_t *__restrict__ keys, int64_t P,
+                                                    int32_t *__restrict__ pidx) {
+  for (int64_t j = blockIdx.x * int64_t(256) + threadIdx.x; j < P; j += int64_t(gridDim.x) * 256)
+    pidx[j] = int32_t(uint32_t(keys[j]));
+}
+
+// Completes pairs that span SpMV workgroups (raw accumulators, no sum).
+template <typename V>
+__global__ __launch_bounds__(256) void k_fix_raw(typename Form<V>::Acc *__restrict__ part,
+                                                 int32_t nb, const int2 *__restrict__ coord,
+                                                 const uint8_t *__restrict__ closes,
+                                                 const int32_t *__restrict__ carry_row,
+                                                 const typename Form<V>::Acc *__restrict__ blk_carry,
+                                                 const typename Form<V>::Acc *__restrict__ blk_head) {
+  using Acc = typename Form<V>::Acc;
+  for (int32_t b = blockIdx.x * 256 + threadIdx.x; b < nb; b += gridDim.x * 256) {
+    if (!closes[b]) continue;
+    const int32_t R = coord[b].x;
+    int32_t q = b - 1;
+    while (q >= 0 && carry_row[q] == R) --q;
+    Acc sum{};
+    for (int32_t k = q + 1; k < b; ++k) sum = merge(sum, blk_carry[k]);
+    part[R] = merge(sum, blk_head[b]);
+  }
+}
+
+// Combine blocks: rows [cstart[b], cstart[b+1]) with cstart[b] the first
+// row v whose cost v + rpp[v] (rows plus pairs before it) reaches
+// b * kCombItems, so a block never splits a row and holds at most
+// kCombItems + kMaxSlabs rows plus pairs, hub rows and empty ones alike.
+// cstart[b] = (first row, its first pair rpp[row]).
+__global__ __launch_bounds__(256) void k_comb_bounds(const int32_t *__restrict__ rpp, int32_t n,
+                                                     int32_t nblk, int2 *__restrict__ cstart) {
+  for (int32_t b = blockIdx.x * 256 + threadIdx.x; b <= nblk; b += gridDim.x * 256) {
+    const int64_t target = int64_t(b) * kCombItems;
+    int32_t lo = 0, hi = n;   // first v in [0, n] with v + rpp[v] >= target
+    while (lo < hi) {
+      const int32_t m = (lo + hi) >> 1;
+      if (int64_t(m) + rpp[m] < target)
+        lo = m + 1;
+      else
+        hi = m;
+    }
+    const int32_t R = b == nblk ? n : lo;
+    cstart[b] = make_int2(R, rpp[R]);
+  }
+}
+
+// y[v] = c * (partials of row v, slab by slab) + t.  The block's row
+// offsets and pairs, row-major (part[pidx[rpp[v] ..]], each row's in slab
+// order), are gathered into LDS with every load in flight, then one thread
+// per row adds its run.  Each workgroup stores its part of sum(y) in
+// blk_ysum; k_sum_blocks adds them (tens of thousands of workgroups would
+// queue on a shared arrival counter).
+template <typename V>
+__global__ __launch_bounds__(kThreads) void k_seg_combine(
+    const typename Form<V>::Acc *__restrict__ part, const int32_t *__restrict__ rpp,
+    const int32_t *__restrict__ pidx, const int2 *__restrict__ cstart, double c,
+    const double *__restrict__ tele_in, V *__restrict__ y, double *__restrict__ blk_ysum) {
+  using Acc = typename Form<V>::Acc;
+  constexpr int kCap = kCombItems + kMaxSlabs;
+  constexpr int kPer = kCap / kThreads;
+  __shared__ Acc s_part[kCap];
+  __shared__ uint16_t s_off[kCap + 1];   // rpp[R0 + i] - rpp[R0]
+  __shared__ double sh[4];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int2 c0 = cstart[b], c1 = cstart[b + 1];
+  const int32_t R0 = c0.x, nr = c1.x - c0.x, j0 = c0.y, np = c1.y - c0.y;
+  {
+    int32_t pi[kPer], ro[kPer + 1];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int32_t q = k * kThreads + tid;
+      pi[k] = q < np ? pidx[j0 + q] : 0;
+      ro[k] = q <= nr ? rpp[R0 + q] : 0;
+    }
+    {
+      const int32_t q = kPer * kThreads + tid;
+      ro[kPer] = q <= nr ? rpp[R0 + q] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k <= kPer; ++k) {
+      const int32_t q = k * kThreads + tid;
+      if (q <= nr) s_off[q] = uint16_t(ro[k] - j0);
+    }
+    Acc pa[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int32_t q = k * kThreads + tid;
+      if (q < np) pa[k] = part[pi[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int32_t q = k * kThreads + tid;
+      if (q < np) s_part[q] = pa[k];
+    }
+  }
+  __syncthreads();
+  const double tk = *tele_in;
+  double ysum = 0.0;
+  for (int32_t i = tid; i < nr; i += kThreads) {
+    const int32_t e = s_off[i + 1];
+    Acc acc{};
+    for (int32_t j = s_off[i]; j < e; ++j) acc = merge(acc, s_part[j]);
+    const V yv = Form<V>::finish(acc, c, tk);
+    y[R0 + i] = yv;
+    ysum += double(yv);
+  }
+  const double tot = block_sum256(ysum, sh);
+  if (tid == 0) blk_ysum[b] = tot;
+}
+
+// sum(y) = the nblk workgroup partials added in a fixed order by one
+// workgroup of 1024 threads; stores it and the next teleport scalar.
+__global__ __launch_bounds__(1024) void k_sum_blocks(const double *__restrict__ blk_ysum,
+                                                     int32_t nblk, double w, double *sum_out,
+                                                     double *tele_out) {
+  __shared__ double sh[1024 / kWave];
+  double a = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += 1024) a += blk_ysum[k];
+  a = wave_sum(a);
+  if (lane_id() == 0) sh[threadIdx.x / kWave] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int q = 0; q < 1024 / kWave; ++q) s += sh[q];
+    if (sum_out) *sum_out = s;
+    *tele_out = w * s;
+  }
+}
+
 // Optional event pairs around each SpMV launch (benchmark instrumentation).
 struct Timing {
   bool on = false;
@@ -752,6 +1069,12 @@ struct Layout {
   int32_t *order, *newlabel, *rp2, *col2;
   V *val2, *x2;
   int64_t *total;
+  // column segmenting
+  int32_t *seg_col, *prp, *pair_row, *seg_row, *rpp, *pidx;
+  int2 *cstart;
+  V *seg_val;
+  typename Form<V>::Acc *seg_part;
+  uint32_t *seg_flag, *seg_cnt, *seg_scan;
 };
 
 // One layout function serves both measuring (ws == nullptr) and carving.
@@ -760,7 +1083,10 @@ Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs, size_t *byte
   using Acc = typename Form<V>::Acc;
   Carve c(ws);
   Layout<V> L{};
-  const int64_t nb = (n + nnz_cap + kItemsMin - 1) / kItemsMin + 1;
+  // SpMV tiles: over (rows, entries), or over (pairs, entries) when the
+  // columns are segmented (at most one pair per entry).
+  const int64_t rows_cap = n > nnz_cap ? n : nnz_cap;
+  const int64_t nb = (rows_cap + nnz_cap + kItemsMin - 1) / kItemsMin + 1;
   const int64_t G = (nb + kFinishPer - 1) / kFinishPer + 1;
   const int64_t G0 = (n + kSumChunk - 1) / kSumChunk + 1;
   L.ksum = c.take<unsigned long long>(64);
@@ -782,9 +1108,41 @@ Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs, size_t *byte
   L.order = c.take<int32_t>(size_t(n));
   L.newlabel = c.take<int32_t>(size_t(n));
   L.rp2 = c.take<int32_t>(size_t(n + 1));
-  L.col2 = c.take<int32_t>(size_t(nnz_cap > 0 ? nnz_cap : 1));
-  L.val2 = c.take<V>(size_t(nnz_cap > 0 ? nnz_cap : 1));
+  {
+    // One region for the relabelled entries; when the columns are
+    // segmented it is free after the build and holds the pairs' row-major
+    // index (and, during the build, the second buffer of a sort of pairs).
+    const size_t z = size_t(nnz_cap > 0 ? nnz_cap : 1);
+    const size_t colb = (z * 4 + 255) / 256 * 256;
+    uint8_t *rl = c.take<uint8_t>(colb + z * sizeof(V));
+    L.col2 = reinterpret_cast<int32_t *>(rl);
+    L.val2 = rl ? reinterpret_cast<V *>(rl + colb) : nullptr;
+  }
   L.x2 = c.take<V>(size_t(n) * nrhs);
+  if (nrhs == 1) {
+    const int64_t z = nnz_cap > 0 ? nnz_cap : 1;
+    const int64_t ntiles = (n + nnz_cap + kSegTile - 1) / kSegTile + 1;
+    L.seg_col = c.take<int32_t>(size_t(z));
+    L.seg_val = c.take<V>(size_t(z));
+    L.prp = c.take<int32_t>(size_t(z + 1));
+    L.pair_row = c.take<int32_t>(size_t(z));
+    // The partials are written only by the iterations; during the build
+    // the same bytes hold the entries' rows and the pair flags.
+    const size_t part_bytes = size_t(z) * sizeof(typename Form<V>::Acc);
+    const size_t tmp_bytes = size_t(z) * 4 + 256 + size_t(z + 1) * 4;
+    uint8_t *region = c.take<uint8_t>(part_bytes > tmp_bytes ? part_bytes : tmp_bytes);
+    L.seg_part = reinterpret_cast<typename Form<V>::Acc *>(region);
+    L.seg_row = reinterpret_cast<int32_t *>(region);
+    L.seg_flag = region ? reinterpret_cast<uint32_t *>(region + (size_t(z) * 4 + 255) / 256 * 256)
+                        : nullptr;
+    L.seg_cnt = c.take<uint32_t>(size_t(kMaxSlabs) * ntiles);
+    int64_t scan_n = z + 1 > kMaxSlabs * ntiles ? z + 1 : kMaxSlabs * ntiles;
+    if (n + 1 > scan_n) scan_n = n + 1;
+    L.seg_scan = c.take<uint32_t>(size_t(scan_ws_elems(scan_n)));
+    L.rpp = c.take<int32_t>(size_t(n + 1));
+    L.cstart = c.take<int2>(size_t((n + z + kCombItems - 1) / kCombItems + 2));
+    L.pidx = L.col2;
+  }
   if (bytes) *bytes = c.bytes();
   return L;
 }
@@ -818,6 +1176,88 @@ void launch_spmm(int G, int32_t nb, hipStream_t s, const int32_t *rp, const int3
     case 32: launch_spmm_g<V, 32>(nb, s, rp, col, val, x, y, n, k, coord, c, tele, blk_ysum, blk_carry, blk_head); break;
     default: launch_spmm_g<V, 64>(nb, s, rp, col, val, x, y, n, k, coord, c, tele, blk_ysum, blk_carry, blk_head); break;
   }
+}
+
+template <typename V, bool kRaw>
+void launch_spmv(int ipt, int32_t nb, hipStream_t s, const int32_t *rp, const int32_t *col,
+                 const V *val, const V *x, V *y, int32_t n, const int2 *coord, double c,
+                 const double *tele, double *blk_ysum, typename Form<V>::Acc *blk_carry,
+                 typename Form<V>::Acc *blk_head, typename Form<V>::Acc *part) {
+  if (ipt == 4)
+    hipLaunchKernelGGL((k_spmv<V, 4, kRaw>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x, y,
+                       n, coord, c, tele, blk_ysum, blk_carry, blk_head, part);
+  else if (ipt == 16)
+    hipLaunchKernelGGL((k_spmv<V, 16, kRaw>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x, y,
+                       n, coord, c, tele, blk_ysum, blk_carry, blk_head, part);
+  else
+    hipLaunchKernelGGL((k_spmv<V, 8, kRaw>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x, y,
+                       n, coord, c, tele, blk_ysum, blk_carry, blk_head, part);
+}
+
+// Segmented layout of the matrix (rp, col, val): see the kernels above.
+// Returns the pair count through *P_out, or 0 when segmenting does not
+// apply (fewer than two slabs, or pairs + entries beyond int32).  Reads the
+// pair count back to the host, so it synchronizes the stream once.
+template <typename V>
+pp_status build_segments(const Layout<V> &L, const int32_t *rp, const int32_t *col, const V *val,
+                         int64_t n, int64_t nnz, int slab_log2, int32_t *sbits_out,
+                         int32_t *ns_out, int64_t *P_out, hipStream_t s) {
+  *P_out = 0;
+  int sbits = slab_log2;
+  while (((n - 1) >> sbits) + 1 > kMaxSlabs) ++sbits;
+  const int32_t ns = int32_t(((n - 1) >> sbits) + 1);
+  if (ns < 2 || nnz <= 0) return PP_OK;
+  const int32_t dbits = 32 - __builtin_clz(uint32_t(ns - 1));
+  const int32_t n32 = int32_t(n);
+  const int32_t ntiles = int32_t((n + nnz + kSegTile - 1) / kSegTile);
+  hipLaunchKernelGGL(k_partition, dim3(grid_for(int64_t(ntiles) + 1, 256, 4096)), dim3(256), 0, s,
+                     rp, n32, int32_t(nnz), ntiles, kSegTile, L.coord);
+  hipLaunchKernelGGL(k_seg_count, dim3(ntiles), dim3(kThreads), 0, s, col, L.coord, sbits, ns,
+                     dbits, ntiles, L.seg_cnt);
+  PP_LAUNCHED("k_seg_count");
+  pp_status st = exscan_u32(L.seg_cnt, L.seg_cnt, int64_t(ns) * ntiles, L.seg_scan, nullptr, s);
+  if (st != PP_OK) return st;
+  hipLaunchKernelGGL(k_seg_scatter<V>, dim3(ntiles), dim3(kThreads), 0, s, rp, col, val, n32,
+                     L.coord, sbits, ns, dbits, ntiles, L.seg_cnt, L.seg_col, L.seg_val, L.seg_row);
+  PP_LAUNCHED("k_seg_scatter");
+  const int gZ = grid_for(nnz, 256, 16384);
+  hipLaunchKernelGGL(k_pair_flags, dim3(gZ), dim3(256), 0, s, L.seg_col, L.seg_row, nnz, sbits,
+                     L.seg_flag);
+  st = exscan_u32(L.seg_flag, L.seg_flag, nnz, L.seg_scan, L.total, s);
+  if (st != PP_OK) return st;
+  hipLaunchKernelGGL(k_pair_emit, dim3(gZ), dim3(256), 0, s, L.seg_flag, L.seg_row, nnz, L.total,
+                     L.prp, L.pair_row);
+  PP_LAUNCHED("k_pair_flags/k_pair_emit");
+  int64_t P = 0;
+  PP_HIP(hipMemcpyAsync(&P, L.total, sizeof(P), hipMemcpyDeviceToHost, s));
+  PP_HIP(hipStreamSynchronize(s));
+  if (P <= 0 || P > nnz || P + nnz > int64_t(INT32_MAX)) return PP_OK;
+  // Row-major index of the pairs for the combine: the keys sort in the
+  // partials' region (free until the first iteration) against the
+  // relabelled-entry region (free once the slab-major copy exists).
+  uint64_t *keys = reinterpret_cast<uint64_t *>(L.seg_part);
+  uint64_t *keys_b = reinterpret_cast<uint64_t *>(L.col2);
+  st = fill_i32(L.rpp, n + 1, 0, s);
+  if (st != PP_OK) return st;
+  hipLaunchKernelGGL(k_pair_keys, dim3(grid_for(P, 256, 16384)), dim3(256), 0, s, L.pair_row, P,
+                     keys, reinterpret_cast<uint32_t *>(L.rpp));
+  PP_LAUNCHED("k_pair_keys");
+  st = exscan_u32(reinterpret_cast<uint32_t *>(L.rpp), reinterpret_cast<uint32_t *>(L.rpp), n + 1,
+                  L.seg_scan, nullptr, s);
+  if (st != PP_OK) return st;
+  const int32_t rbits = 32 - __builtin_clz(uint32_t(n - 1));
+  st = radix_sort_pingpong(keys, keys_b, P, rbits, L.seg_cnt, L.seg_scan, s);
+  if (st != PP_OK) return st;
+  hipLaunchKernelGGL(k_pair_index, dim3(grid_for(P, 256, 16384)), dim3(256), 0, s, keys, P,
+                     L.pidx);
+  const int32_t ncomb = int32_t((n + P + kCombItems - 1) / kCombItems);
+  hipLaunchKernelGGL(k_comb_bounds, dim3(grid_for(int64_t(ncomb) + 1, 256, 4096)), dim3(256), 0, s,
+                     L.rpp, n32, ncomb, L.cstart);
+  PP_LAUNCHED("k_pair_index/k_comb_bounds");
+  *sbits_out = sbits;
+  *ns_out = ns;
+  *P_out = P;
+  return PP_OK;
 }
 
 template <typename V>
@@ -880,6 +1320,23 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
     PP_LAUNCHED("k_relabel_copy/k_permute_in");
   }
 
+  // Column segmenting (single vector only).
+  int32_t sbits = 0, ns = 0, nbp = 0, ncomb = 0;
+  int64_t P = 0;
+  if (k == 1 && g_cfg.slab_log2 > 0 && iters > 0) {
+    st = build_segments<V>(L, rp, col, val, n, nnz, g_cfg.slab_log2, &sbits, &ns, &P, s);
+    if (st != PP_OK) return st;
+    if (P > 0) {
+      nbp = int32_t((P + nnz + D - 1) / D);
+      ncomb = int32_t((n + P + kCombItems - 1) / kCombItems);
+      hipLaunchKernelGGL(k_partition, dim3(grid_for(int64_t(nbp) + 1, 256, 4096)), dim3(256), 0,
+                         s, L.prp, int32_t(P), int32_t(nnz), nbp, D, L.coord);
+      hipLaunchKernelGGL(k_block_flags, dim3(grid_for(nbp, 256, 4096)), dim3(256), 0, s, L.prp,
+                         int32_t(P), nbp, L.coord, L.carry_row, L.closes);
+      PP_LAUNCHED("k_partition/k_block_flags (pairs)");
+    }
+  }
+
   const int G0 = int((n + kSumChunk - 1) / kSumChunk);
   if (k == 1)
     hipLaunchKernelGGL(k_sum0<V>, dim3(G0), dim3(kThreads), 0, s, x0, n, kSumChunk, L.part,
@@ -897,15 +1354,23 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
     double *t_out = L.tele + 64 * ((it + 1) & 1);
     double *s_out = sums ? sums + int64_t(it + 1) * k : nullptr;
     if ((st = timed_begin(s)) != PP_OK) return st;
-    if (k == 1 && ipt == 4)
-      hipLaunchKernelGGL((k_spmv<V, 4>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x, yv,
-                         n32, L.coord, c, t_in, L.blk_ysum, L.blk_carry, L.blk_head);
-    else if (k == 1 && ipt == 16)
-      hipLaunchKernelGGL((k_spmv<V, 16>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x, yv,
-                         n32, L.coord, c, t_in, L.blk_ysum, L.blk_carry, L.blk_head);
-    else if (k == 1)
-      hipLaunchKernelGGL((k_spmv<V, 8>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x, yv,
-                         n32, L.coord, c, t_in, L.blk_ysum, L.blk_carry, L.blk_head);
+    if (P > 0) {
+      launch_spmv<V, true>(ipt, nbp, s, L.prp, L.seg_col, L.seg_val, x, nullptr, int32_t(P),
+                           L.coord, c, t_in, nullptr, L.blk_carry, L.blk_head, L.seg_part);
+      hipLaunchKernelGGL(k_fix_raw<V>, dim3(grid_for(nbp, 256, 4096)), dim3(256), 0, s,
+                         L.seg_part, nbp, L.coord, L.closes, L.carry_row, L.blk_carry,
+                         L.blk_head);
+      hipLaunchKernelGGL(k_seg_combine<V>, dim3(ncomb), dim3(kThreads), 0, s, L.seg_part, L.rpp,
+                         L.pidx, L.cstart, c, t_in, yv, L.blk_ysum);
+      hipLaunchKernelGGL(k_sum_blocks, dim3(1), dim3(1024), 0, s, L.blk_ysum, ncomb, w, s_out,
+                         t_out);
+      if ((st = timed_end(s)) != PP_OK) return st;
+      PP_LAUNCHED("k_spmv raw/k_fix_raw/k_seg_combine");
+      continue;
+    }
+    if (k == 1)
+      launch_spmv<V, false>(ipt, nb, s, rp, col, val, x, yv, n32, L.coord, c, t_in, L.blk_ysum,
+                            L.blk_carry, L.blk_head, nullptr);
     else
       launch_spmm<V>(lanes, nb, s, rp, col, val, x, yv, n32, k, L.coord, c, t_in, L.blk_ysum,
                      L.blk_carry, L.blk_head);
@@ -955,18 +1420,21 @@ int32_t kernel_times(float *ms, int32_t cap) {
   return n;
 }
 
-pp_status set_k3_config(int32_t ipt, int32_t rhs_lanes) {
+pp_status set_k3_config(int32_t ipt, int32_t rhs_lanes, int32_t slab_log2) {
   if (ipt != 4 && ipt != 8 && ipt != 16) return fail(PP_EINVAL, "items per thread %d", ipt);
   if (rhs_lanes != 0 && (rhs_lanes < 2 || rhs_lanes > 64 || (rhs_lanes & (rhs_lanes - 1))))
     return fail(PP_EINVAL, "rhs lanes %d", rhs_lanes);
+  if (slab_log2 < 0 || slab_log2 > 30) return fail(PP_EINVAL, "slab log2 %d", slab_log2);
   g_cfg.ipt = ipt;
   g_cfg.rhs_lanes = rhs_lanes;
+  g_cfg.slab_log2 = slab_log2;
   return PP_OK;
 }
 
-void get_k3_config(int32_t *ipt, int32_t *rhs_lanes) {
+void get_k3_config(int32_t *ipt, int32_t *rhs_lanes, int32_t *slab_log2) {
   *ipt = g_cfg.ipt;
   *rhs_lanes = g_cfg.rhs_lanes;
+  *slab_log2 = g_cfg.slab_log2;
 }
 
 size_t pagerank_ws_bytes(int64_t n, int64_t nnz_cap, pp_dtype dt, int32_t nrhs) {

@@ -60,6 +60,26 @@ __device__ __forceinline__ uint64_t lanes_below() {
   return (1ull << lane_id()) - 1ull;
 }
 
+// Rank of this lane's digit d among the earlier lanes of the wave holding
+// the same digit, plus the wave's running count wh[d] of that digit from
+// earlier calls; advances wh[d] by the digit's lanes in this call.  Digits
+// have `bits` bits and are matched with one ballot per bit.  Stable: lanes
+// and calls are ranked in order.
+__device__ __forceinline__ uint32_t wave_digit_rank(uint32_t d, bool valid, int bits,
+                                                    uint32_t *wh) {
+  uint64_t match = __ballot(valid);
+  for (int b = 0; b < bits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t bal = __ballot(bit);
+    match &= bit ? bal : ~bal;
+  }
+  const uint64_t below = match & lanes_below();
+  uint32_t before = 0;
+  if (valid) before = wh[d];
+  if (valid && below == 0) wh[d] = before + uint32_t(__popcll(match));
+  return before + uint32_t(__popcll(below));
+}
+
 // Philox4x32-10 block (Salmon et al., SC'11): ten rounds; each round
 // multiplies counter words 0 and 2 by fixed odd constants, swaps the halves
 // across the state and mixes in a key that advances by a Weyl step.
@@ -183,6 +203,13 @@ pp_status radix_sort(RadixIn in, RadixOut out, int64_t m, int32_t key_bits, void
                      size_t ws_bytes, int64_t check_n, bool check_sorted_lo, uint32_t *flag,
                      hipStream_t s, bool sync_after_first_pass);
 
+// Same ordering with a and b as the only key buffers: an even number of
+// passes alternates a -> b -> a, so the sorted keys end in a.  counts holds
+// radix_pingpong_counts(m) words, scan_ws scan_ws_elems() of that.
+size_t radix_pingpong_counts(int64_t m);
+pp_status radix_sort_pingpong(uint64_t *a, uint64_t *b, int64_t m, int32_t key_bits,
+                              uint32_t *counts, uint32_t *scan_ws, hipStream_t s);
+
 // K2 (k2_filter.hip)
 size_t filter_ws_bytes(int64_t n, int64_t m);
 pp_status launch_filter(int32_t scale, int64_t m, const int64_t *u, const int64_t *v,
@@ -203,8 +230,8 @@ pp_status launch_graphs(int32_t ngraphs, const pp_graph *graphs, int64_t max_n, 
                         int32_t iters, double c, int32_t use_graph, void *ws, size_t ws_bytes,
                         hipStream_t s);
 
-pp_status set_k3_config(int32_t ipt, int32_t rhs_lanes);
-void get_k3_config(int32_t *ipt, int32_t *rhs_lanes);
+pp_status set_k3_config(int32_t ipt, int32_t rhs_lanes, int32_t slab_log2);
+void get_k3_config(int32_t *ipt, int32_t *rhs_lanes, int32_t *slab_log2);
 pp_status set_kernel_timing(bool enable);
 int32_t kernel_times(float *ms, int32_t cap);
 

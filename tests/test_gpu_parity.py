@@ -435,11 +435,14 @@ def test_spmm_lane_width_and_autotuner(tmp_path):
     trp, tcol, tval = oracle.transpose_csr(n, rp, col, val)
     AT = pp.CSR.from_arrays(n, trp, tcol, tval, "f32")
     cache = str(tmp_path / "tune.json")
-    for k in (1, 12):
-        entry = autotune.tune(AT, "f32", k, cache=cache)
-        assert tuple(entry["config"]) in autotune.candidates(k)
-        assert set(entry["ms"]) == {f"{a},{b}" for a, b in autotune.candidates(k)}
+    weights = torch.as_tensor(np.bincount(col, minlength=n)).to(torch.int32).cuda()
+    for k, w in ((1, None), (1, weights), (12, None)):
+        entry = autotune.tune(AT, "f32", k, weights=w, iters=5, cache=cache)
+        opts = (False, True) if w is not None else (False,)
+        names = {autotune.name(cand) for cand in autotune.candidates(k, opts)}
+        assert set(entry["ms"]) == names
+        assert autotune.name(entry["config"] + [entry["relabel"]]) in names
         assert pp.get_k3_config() == tuple(entry["config"])
-        again = autotune.tune(AT, "f32", k, cache=cache)       # served from the cache
+        again = autotune.tune(AT, "f32", k, weights=w, iters=5, cache=cache)   # from the cache
         assert again == entry
     pp.set_k3_config(8, 0)

@@ -1,0 +1,162 @@
+"""GPU parity of the column-segmented K3 iteration (pp_k3_config.slab_log2).
+
+The segmented path stores the matrix slab by slab, runs the merge-path SpMV
+over (slab, row) pairs and combines each row's partial sums in slab order.
+It must reach the oracle's ranks within the same tolerances as the one-pass
+path (1e-12 relative L1 in FP64, 1e-5 in FP32), on Kronecker matrices and on
+structured ones that stress the layout: rows of A^T spanning many SpMV
+workgroups (pairs carried between workgroups), slabs with no entries, a
+single slab (falls back to the one-pass path), n not a multiple of the slab
+width or of the combine block, and an empty matrix.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1603_01876_amd import native as pp
+from paper_1603_01876_amd import workloads
+from test_gpu_parity import TOL, host, okron, random_matrix, rel_l1, spec
+
+pytestmark = pytest.mark.gpu
+
+C = workloads.DAMPING
+
+
+@pytest.fixture(autouse=True)
+def restore_config():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    yield
+    pp.set_k3_config(8, 0, 0)
+
+
+def gpu_k3(AT, n, dtype, slab, ipt=8, iters=20, seed=7, weights=None):
+    pp.set_k3_config(ipt, 0, slab)
+    r = pp.init_r(n, seed, dtype)
+    sums = pp.pagerank(AT, r, iters=iters, c=C, weights=weights)
+    return host(r), host(sums)
+
+
+def check(n, rp, col, val, dtype, slabs, iters=20, weights=None, ipt=8):
+    """Oracle vs the GPU with each slab width; also the segmented result
+    against the one-pass GPU result (same matrix, different sum order)."""
+    trp, tcol, tval = oracle.transpose_csr(n, rp, col, val)
+    AT = pp.CSR.from_arrays(n, trp, tcol, tval, dtype)
+    want, wsums = oracle.pagerank(n, rp, col, val, oracle.init_r(n, 7), iters, C)
+    w = None if weights is None else torch.as_tensor(weights).to(torch.int32).cuda()
+    base, _ = gpu_k3(AT, n, dtype, 0, ipt, iters, weights=w)
+    for slab in slabs:
+        got, sums = gpu_k3(AT, n, dtype, slab, ipt, iters, weights=w)
+        assert rel_l1(got, want) <= TOL[dtype], (slab, rel_l1(got, want))
+        assert np.abs(sums / wsums - 1).max() <= TOL[dtype], slab
+        assert rel_l1(got, base) <= TOL[dtype], slab
+
+
+def kron_matrix(scale):
+    ou, ov = oracle.generate(okron(spec(scale)))
+    ous, ovs = oracle.sort(scale, ou, ov)
+    return oracle.filter(scale, ous, ovs)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("scale", [10, 14, 18])
+def test_segmented_kronecker(scale, dtype):
+    f = kron_matrix(scale)
+    # slab 4 at S=14 asks for 1024 slabs and is widened to 256
+    check(f.n, f.A_rp, f.A_col, f.A_val, dtype, slabs=[4, 7, scale - 3])
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("ipt", [4, 16])
+def test_segmented_relabelled(ipt, dtype):
+    f = kron_matrix(16)
+    check(f.n, f.A_rp, f.A_col, f.A_val, dtype, slabs=[8, 12], weights=f.d_out, ipt=ipt)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["long-rows", "ragged", "dense-ish", "tiny", "empty-slabs"])
+def test_segmented_structured(case, dtype):
+    rng = np.random.default_rng({"long-rows": 11, "ragged": 12, "dense-ish": 13, "tiny": 14,
+                                 "empty-slabs": 15}[case])
+    if case == "long-rows":       # pairs spanning many workgroups, in several slabs
+        n = 60000
+        rp, col, val = random_matrix(n, rng, long_rows=[(5, 50000), (n - 1, 30000), (777, 4097)])
+        slabs = [9, 12, 14]
+    elif case == "ragged":        # n not a multiple of slab or combine block
+        n = 12345
+        rp, col, val = random_matrix(n, rng, long_rows=[(0, 2048), (1, 2049), (2, 2047)])
+        slabs = [5, 8, 11, 13]
+    elif case == "dense-ish":
+        n = 700
+        rp, col, val = random_matrix(n, rng, density=200.0)
+        slabs = [2, 4, 8]
+    elif case == "tiny":
+        n = 3
+        rp, col, val = random_matrix(n, rng, density=2.0)
+        slabs = [1, 2]
+    else:                          # sources only in the lowest and highest slabs
+        n = 40000
+        rp, col, val = random_matrix(n, rng, density=3.0)
+        src = np.repeat(np.arange(n), np.diff(rp))
+        keep = (src < 3000) | (src >= n - 2000)
+        rp = np.concatenate([[0], np.cumsum(np.bincount(src[keep], minlength=n))])
+        col, val = col[keep], val[keep]
+        slabs = [8, 10]
+    check(n, rp, col, val, dtype, slabs)
+
+
+def test_single_slab_falls_back_to_one_pass():
+    f = kron_matrix(12)
+    trp, tcol, tval = oracle.transpose_csr(f.n, f.A_rp, f.A_col, f.A_val)
+    AT = pp.CSR.from_arrays(f.n, trp, tcol, tval, "f32")
+    base, bsums = gpu_k3(AT, f.n, "f32", 0)
+    for slab in (12, 20, 30):      # one slab covers all 2^12 vertices
+        got, sums = gpu_k3(AT, f.n, "f32", slab)
+        assert got.tobytes() == base.tobytes() and sums.tobytes() == bsums.tobytes()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_segmented_empty_matrix(dtype):
+    n = 5000
+    AT = pp.CSR.from_arrays(n, np.zeros(n + 1), np.zeros(0, np.int32), np.zeros(0), dtype)
+    got, _ = gpu_k3(AT, n, dtype, 6)
+    closed = (1 - C) ** 20 * oracle.init_r(n, 7).sum() / n
+    assert np.abs(got / closed - 1).max() <= TOL[dtype]
+
+
+@pytest.mark.parametrize("iters", [0, 1, 2, 7])
+def test_segmented_iteration_counts(iters):
+    n = 5000
+    rng = np.random.default_rng(100 + iters)
+    rp, col, val = random_matrix(n, rng)
+    check(n, rp, col, val, "f64", slabs=[6], iters=iters)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_segmented_closed_form_permutation(dtype):
+    n = 100003
+    perm = np.random.default_rng(5).permutation(n)
+    trp = np.arange(n + 1)
+    # A(i, perm[i]) = 1, so A^T row perm[i] holds column i.
+    AT = pp.CSR.from_arrays(n, trp, np.argsort(perm).astype(np.int32), np.ones(n), dtype)
+    got, sums = gpu_k3(AT, n, dtype, 10)
+    x = oracle.init_r(n, 7)
+    r0 = x.copy()
+    for _ in range(20):
+        y = np.empty(n)
+        y[perm] = x
+        x = y
+    closed = C**20 * x + (1 - C**20) * r0.sum() / n
+    assert rel_l1(got, closed) <= TOL[dtype]
+
+
+def test_segmented_is_deterministic():
+    s = spec(16)
+    u, v = pp.generate(s)
+    us, vs = pp.sort(16, u, v)
+    AT, _, d_out = pp.filter(16, us, vs, "f32")
+    outs = []
+    for w in (None, None, d_out, d_out):
+        got, sums = gpu_k3(AT, AT.n, "f32", 9, weights=w)
+        outs.append((got.tobytes(), sums.tobytes()))
+    assert outs[0] == outs[1] and outs[2] == outs[3]
