@@ -72,23 +72,28 @@ def calibrate_copy():
     print(json.dumps({"calibrate_copy_bytes": 1 << 30, "copies": 3}), flush=True)
 
 
-def measured_traffic(scale: int, dtype: str):
-    """HBM bytes per SpMV launch from the committed rocprofv3 counter summary
-    for this workload, or None when there is none or when the kernel source
-    has changed since the counters were taken."""
+def measured_traffic(scale: int, dtype: str, cfg, relabel: bool):
+    """HBM bytes per K3 iteration from the committed rocprofv3 counter summary
+    for this workload, or None when there is none, when it was taken with
+    another launch configuration, or when the kernel source has changed
+    since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"k3_spmv_kron_s{scale}_{dtype}_counters.md")
     src = os.path.join(ROOT, "paper_1603_01876_amd", "csrc", "k3_pagerank.hip")
     if not os.path.exists(path):
         return None
+    keys = ("kernel_source_sha256", "fetch_bytes_per_launch", "write_bytes_per_launch",
+            "k3_config", "relabel")
     fields = {}
     for line in open(path):
-        if ":" in line and line.split(":", 1)[0].strip() in (
-                "kernel_source_sha256", "fetch_bytes_per_launch", "write_bytes_per_launch"):
+        if ":" in line and line.split(":", 1)[0].strip() in keys:
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if fields.get("kernel_source_sha256") != sha:
+        return None
+    if fields.get("k3_config") != ",".join(str(x) for x in cfg) or \
+            fields.get("relabel") != str(int(relabel)):
         return None
     return (float(fields["fetch_bytes_per_launch"]) + float(fields["write_bytes_per_launch"])) / 1e9
 
@@ -396,8 +401,9 @@ def main():
         },
         "roofline": {"bound": "hbm", "kernel": spmv_label(pp.get_k3_config(), dt),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(S, dt),
-                     "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(S, dt, pp.get_k3_config(), state["relabel"]),
+                     "traffic_unit": "GB per iteration (rocprofv3 FETCH_SIZE + WRITE_SIZE over the iteration's launches, copy-calibrated)",
                      "algorithmic_bytes_per_launch": nbytes},
         "sum_r": {"first": float(sums_h[0]), "last": float(sums_h[-1])},
         "k3_config": {"items_per_thread": pp.get_k3_config()[0],

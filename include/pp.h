@@ -201,15 +201,17 @@ int64_t pp_graphs_max_n(pp_dtype dt);
  * the sparse matrix-vector kernel (a workgroup tile is 256 times that);
  * rhs_lanes: lanes per right-hand-side group of the sparse matrix-dense
  * matrix kernel, 0 = the next power of two >= nrhs, else a power of two in
- * [nrhs, 64].  slab_log2 in [0, 30]: 0 iterates over the whole matrix in
- * one pass; k > 0 (nrhs == 1 only) cuts the columns into slabs of 2^k
+ * [nrhs, 64].  slab_log2 in [-1, 30]: 0 iterates over the whole matrix
+ * in one pass; k > 0 (nrhs == 1 only) cuts the columns into slabs of 2^k
  * vertices (widened until there are at most 256) and stores the matrix
  * slab by slab, so each pass gathers from an L2-sized range of r
- * (column segmenting, Zhang et al., IEEE BigData 2017).  The segmented
- * layout is built inside each pp_pagerank call, which then synchronizes
- * its stream once to read the number of (slab, row) pairs.  Results do not
- * depend on the configuration beyond the order of floating-point sums.
- * pp_set_k3_config(NULL) restores the defaults (8, 0, 0). */
+ * (column segmenting, Zhang et al., IEEE BigData 2017); -1 chooses: slabs
+ * of 2 MiB of r (2^19 FP32 or 2^18 FP64 vertices) once r exceeds 4 MiB,
+ * else one pass.  The segmented layout is built inside each pp_pagerank
+ * call, which then synchronizes its stream once to read the number of
+ * (slab, row) pairs.  Results do not depend on the configuration beyond
+ * the order of floating-point sums.  pp_set_k3_config(NULL) restores the
+ * defaults (8, 0, -1). */
 typedef struct {
   int32_t items_per_thread;
   int32_t rhs_lanes;

@@ -41,7 +41,7 @@ constexpr int kItemsMax = kThreads * 16;     // largest SpMV tile (sizes relabel
 struct K3Config {
   int ipt = 8;
   int rhs_lanes = 0;  // 0: next power of two >= nrhs
-  int slab_log2 = 0;  // 0: one pass over all columns; else slab width 2^slab_log2
+  int slab_log2 = -1; // 0: one pass over all columns; > 0: slab width 2^slab_log2; -1: auto
 };
 K3Config g_cfg;
 constexpr int kFinishPer = kThreads;         // spmv workgroups per finish workgroup
@@ -736,7 +736,7 @@ __global__ __launch_bounds__(256) void k_permute_out(const V *__restrict__ src,
 // pair.  A combine pass then adds each row's partials in slab order and
 // applies c * sum + t.  Sums stay in a fixed order, so results are
 // reproducible; they differ from the unsegmented order only by rounding.
-constexpr int kSegTile = kThreads * 16;   // merge items per build tile
+constexpr int kSegTile = kThreads * 4;    // merge items per build tile
 constexpr int kSegPer = kSegTile / kThreads;
 constexpr int kMaxSlabs = 256;
 constexpr int kCombItems = kThreads * 16; // rows + pairs per combine workgroup
@@ -1320,11 +1320,15 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
     PP_LAUNCHED("k_relabel_copy/k_permute_in");
   }
 
-  // Column segmenting (single vector only).
+  // Column segmenting (single vector only).  Automatic choice: segment
+  // once r no longer fits one XCD's 4 MiB L2, in slabs of 2 MiB of r.
   int32_t sbits = 0, ns = 0, nbp = 0, ncomb = 0;
   int64_t P = 0;
-  if (k == 1 && g_cfg.slab_log2 > 0 && iters > 0) {
-    st = build_segments<V>(L, rp, col, val, n, nnz, g_cfg.slab_log2, &sbits, &ns, &P, s);
+  int slab_log2 = g_cfg.slab_log2;
+  if (slab_log2 < 0)
+    slab_log2 = n * int64_t(sizeof(V)) > (int64_t(4) << 20) ? (sizeof(V) == 4 ? 19 : 18) : 0;
+  if (k == 1 && slab_log2 > 0 && iters > 0) {
+    st = build_segments<V>(L, rp, col, val, n, nnz, slab_log2, &sbits, &ns, &P, s);
     if (st != PP_OK) return st;
     if (P > 0) {
       nbp = int32_t((P + nnz + D - 1) / D);
@@ -1424,7 +1428,7 @@ pp_status set_k3_config(int32_t ipt, int32_t rhs_lanes, int32_t slab_log2) {
   if (ipt != 4 && ipt != 8 && ipt != 16) return fail(PP_EINVAL, "items per thread %d", ipt);
   if (rhs_lanes != 0 && (rhs_lanes < 2 || rhs_lanes > 64 || (rhs_lanes & (rhs_lanes - 1))))
     return fail(PP_EINVAL, "rhs lanes %d", rhs_lanes);
-  if (slab_log2 < 0 || slab_log2 > 30) return fail(PP_EINVAL, "slab log2 %d", slab_log2);
+  if (slab_log2 < -1 || slab_log2 > 30) return fail(PP_EINVAL, "slab log2 %d", slab_log2);
   g_cfg.ipt = ipt;
   g_cfg.rhs_lanes = rhs_lanes;
   g_cfg.slab_log2 = slab_log2;

@@ -291,7 +291,7 @@ def pagerank_graphs(batch: GraphBatch, iters: int = 20, c: float = 0.85, use_gra
                                     batch.ws.numel(), _stream()), "pp_pagerank_graphs")
 
 
-def set_k3_config(items_per_thread: int = 8, rhs_lanes: int = 0, slab_log2: int = 0) -> None:
+def set_k3_config(items_per_thread: int = 8, rhs_lanes: int = 0, slab_log2: int = -1) -> None:
     """Launch configuration of pagerank() (see pp_set_k3_config)."""
     cfg = _K3Config(items_per_thread, rhs_lanes, slab_log2)
     _check(lib().pp_set_k3_config(ctypes.addressof(cfg)), "pp_set_k3_config")

@@ -419,7 +419,7 @@ def test_spmv_configs_agree(ipt):
         got, sums, want, wsums = run_k3(f.n, f.A_rp, f.A_col, f.A_val, "f32")
         assert rel_l1(got, want) <= 1e-5
     finally:
-        pp.set_k3_config(8, 0)
+        pp.set_k3_config()
 
 
 def test_spmm_lane_width_and_autotuner(tmp_path):
@@ -431,7 +431,7 @@ def test_spmm_lane_width_and_autotuner(tmp_path):
     try:
         run_k3_multi(n, rp, col, val, "f32", 12)
     finally:
-        pp.set_k3_config(8, 0)
+        pp.set_k3_config()
     trp, tcol, tval = oracle.transpose_csr(n, rp, col, val)
     AT = pp.CSR.from_arrays(n, trp, tcol, tval, "f32")
     cache = str(tmp_path / "tune.json")
@@ -445,4 +445,4 @@ def test_spmm_lane_width_and_autotuner(tmp_path):
         assert pp.get_k3_config() == tuple(entry["config"])
         again = autotune.tune(AT, "f32", k, weights=w, iters=5, cache=cache)   # from the cache
         assert again == entry
-    pp.set_k3_config(8, 0)
+    pp.set_k3_config()

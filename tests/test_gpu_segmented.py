@@ -27,7 +27,7 @@ C = workloads.DAMPING
 def restore_config():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     yield
-    pp.set_k3_config(8, 0, 0)
+    pp.set_k3_config()
 
 
 def gpu_k3(AT, n, dtype, slab, ipt=8, iters=20, seed=7, weights=None):
@@ -160,3 +160,19 @@ def test_segmented_is_deterministic():
         got, sums = gpu_k3(AT, AT.n, "f32", 9, weights=w)
         outs.append((got.tobytes(), sums.tobytes()))
     assert outs[0] == outs[1] and outs[2] == outs[3]
+
+
+@pytest.mark.parametrize("dtype,scale,same_as", [("f32", 21, 19), ("f64", 21, 18),
+                                                 ("f32", 20, 0), ("f64", 19, 0)])
+def test_automatic_slab_width(dtype, scale, same_as):
+    # slab_log2 = -1 segments once r exceeds 4 MiB, in slabs of 2 MiB of r:
+    # bit for bit the explicit choice (r is 8 MiB at S=21 FP32, 4 MiB at
+    # S=20 FP32 and S=19 FP64).
+    s = spec(scale)
+    u, v = pp.generate(s)
+    us, vs = pp.sort(scale, u, v)
+    AT, _, _ = pp.filter(scale, us, vs, dtype)
+    auto = gpu_k3(AT, AT.n, dtype, -1)
+    explicit = gpu_k3(AT, AT.n, dtype, same_as)
+    assert auto[0].tobytes() == explicit[0].tobytes()
+    assert auto[1].tobytes() == explicit[1].tobytes()
