@@ -101,9 +101,10 @@ def measured_traffic(scale: int, dtype: str, cfg, relabel: bool):
 def spmv_label(cfg, dt):
     v = "float" if dt == "f32" else "double"
     if cfg[2] > 0:
-        return (f"segmented SpMV iteration, slabs of 2^{cfg[2]} columns: k_spmv<{v},{cfg[0]},raw> "
-                f"+ k_fix_raw<{v}> + k_seg_combine<{v}>")
-    return f"k_spmv<{v},{cfg[0]}>"
+        hot = f"k_spmv_win<{v}> (slab 0 through LDS windows) + " if cfg[3] == 1 else ""
+        return (f"segmented SpMV iteration, slabs of 2^{cfg[2]} columns: {hot}"
+                f"k_spmv<{v},{cfg[0]},raw> + k_fix_raw<{v}> + k_seg_combine<{v}> + k_sum_blocks")
+    return f"k_spmv<{v},{cfg[0]}> + k_finish<{v}>"
 
 
 def batched_form(args, pp, workloads, torch):
@@ -408,6 +409,7 @@ def main():
         "sum_r": {"first": float(sums_h[0]), "last": float(sums_h[-1])},
         "k3_config": {"items_per_thread": pp.get_k3_config()[0],
                       "slab_log2": pp.get_k3_config()[2],
+                      "hot_windows": pp.get_k3_config()[3],
                       "relabel": state["relabel"],
                       "tuned": None if args.no_tune or args.warmup < 1 else tuned["ms"]},
     }

@@ -175,13 +175,13 @@ pp_status pp_pagerank_graphs(int32_t ngraphs, const pp_graph *graphs, int64_t ma
 }
 
 pp_status pp_set_k3_config(const pp_k3_config *cfg) {
-  if (!cfg) return set_k3_config(8, 0, -1);
-  return set_k3_config(cfg->items_per_thread, cfg->rhs_lanes, cfg->slab_log2);
+  if (!cfg) return set_k3_config(8, 0, -1, 0);
+  return set_k3_config(cfg->items_per_thread, cfg->rhs_lanes, cfg->slab_log2, cfg->hot_windows);
 }
 
 pp_status pp_get_k3_config(pp_k3_config *cfg) {
   if (!cfg) return fail(PP_EINVAL, "pp_get_k3_config: null");
-  get_k3_config(&cfg->items_per_thread, &cfg->rhs_lanes, &cfg->slab_log2);
+  get_k3_config(&cfg->items_per_thread, &cfg->rhs_lanes, &cfg->slab_log2, &cfg->hot_windows);
   return PP_OK;
 }
 

@@ -47,7 +47,7 @@ class _Csr(ctypes.Structure):
 
 class _K3Config(ctypes.Structure):
     _fields_ = [("items_per_thread", ctypes.c_int32), ("rhs_lanes", ctypes.c_int32),
-                ("slab_log2", ctypes.c_int32)]
+                ("slab_log2", ctypes.c_int32), ("hot_windows", ctypes.c_int32)]
 
 
 class _Graph(ctypes.Structure):
@@ -291,16 +291,18 @@ def pagerank_graphs(batch: GraphBatch, iters: int = 20, c: float = 0.85, use_gra
                                     batch.ws.numel(), _stream()), "pp_pagerank_graphs")
 
 
-def set_k3_config(items_per_thread: int = 8, rhs_lanes: int = 0, slab_log2: int = -1) -> None:
+def set_k3_config(items_per_thread: int = 8, rhs_lanes: int = 0, slab_log2: int = -1,
+                  hot_windows: int = 0) -> None:
     """Launch configuration of pagerank() (see pp_set_k3_config)."""
-    cfg = _K3Config(items_per_thread, rhs_lanes, slab_log2)
+    cfg = _K3Config(items_per_thread, rhs_lanes, slab_log2, hot_windows)
     _check(lib().pp_set_k3_config(ctypes.addressof(cfg)), "pp_set_k3_config")
 
 
-def get_k3_config() -> tuple[int, int, int]:
+def get_k3_config() -> tuple[int, int, int, int]:
     cfg = _K3Config()
     _check(lib().pp_get_k3_config(ctypes.addressof(cfg)), "pp_get_k3_config")
-    return int(cfg.items_per_thread), int(cfg.rhs_lanes), int(cfg.slab_log2)
+    return (int(cfg.items_per_thread), int(cfg.rhs_lanes), int(cfg.slab_log2),
+            int(cfg.hot_windows))
 
 
 # ------------------------------------------------------------ instrumentation
