@@ -52,7 +52,8 @@ typedef enum {
   PP_K1 = 1,
   PP_K2 = 2,
   PP_K3 = 3,
-  PP_K3_GRAPHS = 4 /* pp_pagerank_graphs; the m argument is the number of graphs */
+  PP_K3_GRAPHS = 4, /* pp_pagerank_graphs; the m argument is the number of graphs */
+  PP_K2_ROWFORM = 5 /* pp_transpose; the m argument is the number of stored entries */
 } pp_kernel;
 
 /* Kronecker generator parameters [host] (Sec. IV.A): N = 2^scale vertices,
@@ -140,6 +141,15 @@ pp_status pp_sort(int32_t scale, int64_t m, const int64_t *u, const int64_t *v,
 pp_status pp_filter(int32_t scale, int64_t m, const int64_t *u, const int64_t *v, pp_dtype dt,
                     pp_csr *AT, int32_t *d_in, int32_t *d_out, void *ws, size_t ws_bytes,
                     void *stream);
+
+/* Row form of K2's matrix (Sec. IV.C, A indexed by (u, v)): writes CSR(A)
+ * from the CSR(A^T) that pp_filter produced -- A->row_ptr[u] ..
+ * A->row_ptr[u+1] lists the columns v (ascending) of row u with the same
+ * values, copied bit for bit (value type dt).  A->n must equal AT->n and
+ * A->cap >= AT->nnz; sets A->nnz.  Workspace:
+ * pp_workspace_bytes(PP_K2_ROWFORM, n, AT->nnz, dt, 1). */
+pp_status pp_transpose(const pp_csr *AT, pp_dtype dt, pp_csr *A, void *ws, size_t ws_bytes,
+                       void *stream);
 
 /* K3 initial vector (Sec. IV.D, r = rand(1,N); r = r./norm(r,1)): for each
  * right-hand side j < nrhs, k_ij = top 24 bits of word 0 of Philox4x32-10

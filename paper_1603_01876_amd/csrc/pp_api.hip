@@ -73,6 +73,8 @@ size_t pp_workspace_bytes(pp_kernel k, int64_t n, int64_t m, pp_dtype dt, int32_
     case PP_K3_GRAPHS:
       if (m < 1 || m > (int64_t(1) << 24)) return size_t(-1);
       return graphs_ws_bytes(int32_t(m));
+    case PP_K2_ROWFORM:
+      return transpose_ws_bytes(n, m);
   }
   return size_t(-1);
 }
@@ -121,6 +123,25 @@ pp_status pp_filter(int32_t scale, int64_t m, const int64_t *u, const int64_t *v
   const size_t need = filter_ws_bytes(n, m);
   if (!ws || ws_bytes < need) return fail(PP_EWORKSPACE, "pp_filter: workspace needs %zu bytes", need);
   return launch_filter(scale, m, u, v, dt, AT, d_in, d_out, ws, ws_bytes, as_stream(stream));
+}
+
+pp_status pp_transpose(const pp_csr *AT, pp_dtype dt, pp_csr *A, void *ws, size_t ws_bytes,
+                       void *stream) {
+  if (!AT || !A || !AT->row_ptr || !A->row_ptr) return fail(PP_EINVAL, "pp_transpose: null argument");
+  if (dt != PP_F64 && dt != PP_F32) return fail(PP_EINVAL, "pp_transpose: dtype %d", int(dt));
+  if (AT->n < 1 || AT->n > (int64_t(1) << 30))
+    return fail(PP_ERANGE, "pp_transpose: n = %lld", (long long)AT->n);
+  if (AT->nnz < 0 || AT->nnz > kI32Max)
+    return fail(PP_ERANGE, "pp_transpose: nnz = %lld", (long long)AT->nnz);
+  if (AT->nnz > 0 && (!AT->col || !AT->val || !A->col || !A->val))
+    return fail(PP_EINVAL, "pp_transpose: null array");
+  if (A->n != AT->n) return fail(PP_EINVAL, "pp_transpose: A->n %lld != AT->n %lld",
+                                 (long long)A->n, (long long)AT->n);
+  if (A->cap < AT->nnz) return fail(PP_EINVAL, "pp_transpose: A->cap %lld < nnz %lld",
+                                    (long long)A->cap, (long long)AT->nnz);
+  const size_t need = transpose_ws_bytes(AT->n, AT->nnz);
+  if (!ws || ws_bytes < need) return fail(PP_EWORKSPACE, "pp_transpose: workspace needs %zu bytes", need);
+  return launch_transpose(*AT, dt, A, ws, ws_bytes, as_stream(stream));
 }
 
 pp_status pp_init_r(int64_t n, int32_t nrhs, uint64_t seed, pp_dtype dt, void *r, void *ws,

@@ -216,6 +216,11 @@ pp_status launch_filter(int32_t scale, int64_t m, const int64_t *u, const int64_
                         pp_dtype dt, pp_csr *AT, int32_t *d_in, int32_t *d_out, void *ws,
                         size_t ws_bytes, hipStream_t s);
 
+// CSR(A) from CSR(A^T) (k2_transpose.hip)
+size_t transpose_ws_bytes(int64_t n, int64_t z);
+pp_status launch_transpose(const pp_csr &AT, pp_dtype dt, pp_csr *A, void *ws, size_t ws_bytes,
+                           hipStream_t s);
+
 // K3 (k3_pagerank.hip)
 size_t pagerank_ws_bytes(int64_t n, int64_t nnz_cap, pp_dtype dt, int32_t nrhs);
 pp_status launch_init_r(int64_t n, int32_t nrhs, uint64_t seed, pp_dtype dt, void *r,

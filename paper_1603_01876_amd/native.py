@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libpp.so")
 
 PP_OK, PP_EINVAL, PP_ERANGE, PP_EWORKSPACE, PP_EHIP = range(5)
 F64, F32 = 0, 1
-K0, K1, K2, K3, K3_GRAPHS = range(5)
+K0, K1, K2, K3, K3_GRAPHS, K2_ROWFORM = range(6)
 
 _TORCH = {F64: torch.float64, F32: torch.float32}
 _NAMES = {"f64": F64, "f32": F32, F64: F64, F32: F32,
@@ -69,6 +69,8 @@ SIGNATURES = {
     "pp_sort": (ctypes.c_int, [_I32, _I64, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "pp_filter": (ctypes.c_int, [_I32, _I64, _VP, _VP, ctypes.c_int, ctypes.POINTER(_Csr),
                                  _VP, _VP, _VP, _SZ, _VP]),
+    "pp_transpose": (ctypes.c_int, [ctypes.POINTER(_Csr), ctypes.c_int, ctypes.POINTER(_Csr),
+                                    _VP, _SZ, _VP]),
     "pp_init_r": (ctypes.c_int, [_I64, _I32, _U64, ctypes.c_int, _VP, _VP, _SZ, _VP]),
     "pp_pagerank": (ctypes.c_int, [ctypes.POINTER(_Csr), ctypes.c_int, _I32, _I32, _D, _VP,
                                    _VP, _VP, _VP, _SZ, _VP]),
@@ -215,6 +217,23 @@ def filter(scale: int, u, v, dtype="f64", AT: CSR | None = None, d_in=None, d_ou
                            _ptr(d_out), _ptr(ws), ws.numel(), _stream()), "pp_filter")
     AT.nnz = int(c.nnz)
     return AT, d_in, d_out
+
+
+def transpose(AT: CSR, A: CSR | None = None, ws=None) -> CSR:
+    """Row form CSR(A) of K2's matrix from its CSR(A^T) (see pp_transpose)."""
+    dt = AT.dtype
+    dev = AT.row_ptr.device
+    if A is None:
+        cap = max(AT.nnz, 1)
+        A = CSR(AT.n, 0, torch.empty(AT.n + 1, dtype=torch.int32, device=dev),
+                torch.empty(cap, dtype=torch.int32, device=dev),
+                torch.empty(cap, dtype=_TORCH[dt], device=dev))
+    ws = _ws(workspace_bytes(K2_ROWFORM, AT.n, AT.nnz, dt), ws, dev)
+    ca, cat = A._c(), AT._c()
+    _check(lib().pp_transpose(ctypes.byref(cat), dt, ctypes.byref(ca), _ptr(ws), ws.numel(),
+                              _stream()), "pp_transpose")
+    A.nnz = int(ca.nnz)
+    return A
 
 
 # ---------------------------------------------------------------------- K3

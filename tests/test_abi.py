@@ -148,3 +148,22 @@ def test_k3_config_roundtrip_and_validation():
     assert native.get_k3_config() == (16, 0, 19, 1)   # a rejected call changes nothing
     native.lib().pp_set_k3_config(None)
     assert native.get_k3_config() == (8, 0, -1, 0)
+
+
+def test_transpose_validation():
+    L = native.lib()
+    n = 8
+    at = native._Csr(n, 3, 3, 1, 1, 1)
+    a_bad_n = native._Csr(n + 1, 0, 3, 1, 1, 1)
+    a_small = native._Csr(n, 0, 2, 1, 1, 1)
+    for args in ((None, native.F64, ctypes.byref(native._Csr(n, 0, 3, 1, 1, 1))),
+                 (ctypes.byref(at), native.F64, ctypes.byref(a_bad_n)),
+                 (ctypes.byref(at), native.F64, ctypes.byref(a_small)),
+                 (ctypes.byref(at), 7, ctypes.byref(native._Csr(n, 0, 3, 1, 1, 1)))):
+        st = L.pp_transpose(*args, None, 0, None)
+        assert st in (native.PP_EINVAL, native.PP_ERANGE), st
+    # a large enough matrix but no workspace
+    st = L.pp_transpose(ctypes.byref(at), native.F64, ctypes.byref(native._Csr(n, 0, 3, 1, 1, 1)),
+                        None, 0, None)
+    assert st == native.PP_EWORKSPACE
+    assert native.workspace_bytes(native.K2_ROWFORM, n, 3) > 0

@@ -9,7 +9,8 @@ properties that hold at any size:
   K1  non-decreasing u, same multiset of edges (order-independent hash),
       stability on a sample of start vertices;
   K2  d_in and d_out over all edges, and sampled rows of CSR(A^T) (plus the
-      longest ones) bit for bit against the oracle;
+      longest ones) bit for bit against the oracle; the row form CSR(A)
+      transposed back equals CSR(A^T) bit for bit;
   K3  one more damped iteration from the GPU's r_19, recomputed by the
       oracle on sampled rows; the sum(r) recurrence over the empty rows.
 """
@@ -163,3 +164,25 @@ def test_k3_one_step_and_sum_recurrence(pipeline, oracle_rows, dtype):
     if dtype == "f64":
         del AT
         torch.cuda.empty_cache()
+
+
+def test_k2_row_form_round_trip(pipeline):
+    # CSR(A) from CSR(A^T) and back again must give CSR(A^T) bit for bit;
+    # every row of A is sorted and its length is the column count in A^T.
+    spec, u, v, us, vs, AT, d_in, d_out = pipeline
+    z = AT.nnz
+    say("row form: CSR(A) and back")
+    A = pp.transpose(AT)
+    assert A.nnz == z
+    counts = torch.bincount(AT.col[:z].long(), minlength=spec.n)
+    assert torch.equal((A.row_ptr[1:] - A.row_ptr[:-1]).long(), counts)
+    rows = torch.repeat_interleave(torch.arange(spec.n, device="cuda"), counts)
+    key = rows * spec.n + A.col[:z].long()
+    assert bool((key[1:] > key[:-1]).all())
+    del rows, key, counts
+    back = pp.transpose(A)
+    assert torch.equal(back.row_ptr, AT.row_ptr)
+    assert torch.equal(back.col[:z], AT.col[:z])
+    assert torch.equal(back.val[:z], AT.val[:z])
+    del A, back
+    torch.cuda.empty_cache()

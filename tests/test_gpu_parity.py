@@ -127,6 +127,13 @@ def check_filter(scale, u_sorted, v_sorted, dtype):
     assert np.array_equal(host(AT.col)[:z], f.AT_col)
     want = f.AT_val if dtype == "f64" else f.AT_val.astype(np.float32)
     assert np.array_equal(host(AT.val)[:z], want)
+    # the row form CSR(A), bit for bit
+    A = pp.transpose(AT)
+    assert A.nnz == z
+    assert np.array_equal(host(A.row_ptr), f.A_rp)
+    assert np.array_equal(host(A.col)[:z], f.A_col)
+    want = f.A_val if dtype == "f64" else f.A_val.astype(np.float32)
+    assert np.array_equal(host(A.val)[:z], want)
     return AT, f
 
 
@@ -168,6 +175,8 @@ def test_filter_empty_edge_list():
     AT, d_in, d_out = pp.filter(5, dev(np.zeros(0)), dev(np.zeros(0)), "f64")
     assert AT.nnz == 0
     assert (host(AT.row_ptr) == 0).all() and (host(d_in) == 0).all()
+    A = pp.transpose(AT)
+    assert A.nnz == 0 and (host(A.row_ptr) == 0).all()
 
 
 def test_filter_rejects_unsorted_input():
