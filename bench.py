@@ -98,6 +98,26 @@ def measured_traffic(scale: int, dtype: str, cfg, relabel: bool):
     return (float(fields["fetch_bytes_per_launch"]) + float(fields["write_bytes_per_launch"])) / 1e9
 
 
+def copy_ceiling(torch, nbytes=1 << 31, reps=5):
+    """Streaming-copy bandwidth of the device (read + write bytes per second
+    of a plain device-to-device copy), the practical ceiling beside the
+    8 TB/s vendor figure."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / t / 1e9
+
+
 def spmv_label(cfg, dt):
     v = "float" if dt == "f32" else "double"
     if cfg[2] > 0:
@@ -376,6 +396,8 @@ def main():
     achieved = nbytes / spmv_avg_s / 1e9
     sums_h = sums.cpu().numpy()
 
+    copy_bw = copy_ceiling(torch)
+    log(f"device copy ceiling {copy_bw:.0f} GB/s")
     out = {
         "metric": "K3 PageRank edges/s (20*M/t_K3)",
         "value": value,
@@ -405,7 +427,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(S, dt, pp.get_k3_config(), state["relabel"]),
                      "traffic_unit": "GB per iteration (rocprofv3 FETCH_SIZE + WRITE_SIZE over the iteration's launches, copy-calibrated)",
-                     "algorithmic_bytes_per_launch": nbytes},
+                     "algorithmic_bytes_per_launch": nbytes,
+                     "copy_GBps": copy_bw, "frac_of_copy": achieved / copy_bw},
         "sum_r": {"first": float(sums_h[0]), "last": float(sums_h[-1])},
         "k3_config": {"items_per_thread": pp.get_k3_config()[0],
                       "slab_log2": pp.get_k3_config()[2],

@@ -134,7 +134,6 @@ def test_k3_one_step_and_sum_recurrence(pipeline, oracle_rows, dtype):
         AT, _, _ = pp.filter(S, us, vs, "f64", degrees=False)
     else:
         AT = AT32
-    tdt = torch.float32 if dtype == "f32" else torch.float64
     ws = torch.empty(pp.workspace_bytes(pp.K3, n, AT.nnz, dtype), dtype=torch.uint8, device="cuda")
     say(f"K3 {dtype}: 19 iterations, then one more")
     r = pp.init_r(n, workloads.BASE_SEED, dtype, ws=ws)
