@@ -754,66 +754,56 @@ __device__ __forceinline__ int32_t row_of(const int32_t *s_end, int32_t na, int3
   return lo;
 }
 
-// Entries of each build tile per slab -> cnt[s * ntiles + tile].
-__global__ __launch_bounds__(kThreads) void k_seg_count(const int32_t *__restrict__ col,
-                                                        const int2 *__restrict__ coord,
-                                                        int32_t sbits, int32_t ns, int32_t dbits,
-                                                        int32_t ntiles, uint32_t *__restrict__ cnt) {
-  constexpr int kWaves = kThreads / kWave;
-  __shared__ uint32_t wh[kWaves][kMaxSlabs];
-  for (int i = threadIdx.x; i < kWaves * kMaxSlabs; i += kThreads) (&wh[0][0])[i] = 0u;
-  __syncthreads();
-  const int b = blockIdx.x, w = threadIdx.x / kWave;
-  const int32_t j0 = coord[b].y, nz = coord[b + 1].y - j0;
-#pragma unroll 4
-  for (int r = 0; r < kSegPer; ++r) {
-    const int32_t e = w * (kSegTile / kWaves) + r * kWave + lane_id();
-    const bool valid = e < nz;
-    const uint32_t d = valid ? uint32_t(col[j0 + e]) >> sbits : 0u;
-    wave_digit_rank(d, valid, dbits, wh[w]);
-  }
-  __syncthreads();
-  for (int d = threadIdx.x; d < ns; d += kThreads) {
-    uint32_t t = 0;
-#pragma unroll
-    for (int q = 0; q < kWaves; ++q) t += wh[q][d];
-    cnt[int64_t(d) * ntiles + b] = t;
-  }
-}
+constexpr int kMaskWords = kMaxSlabs / 32;
 
-// Stable scatter of each build tile's entries (column, value, row) to their
-// slab-major positions.  Ranks come from wave ballots in entry order; the
-// tile is staged in LDS in slab order so that the stores of one slab's run
-// are contiguous.
-template <typename V>
-__global__ __launch_bounds__(kThreads) void k_seg_scatter(
+// One build tile (kSegTile merge items of the matrix) ordered stably by
+// slab: ranks come from wave ballots in entry order, so inside a slab the
+// entries keep their order and rows ascend.  Every (slab, row) run of the
+// tile starts a pair, except the run of the tile's first row in a slab
+// where that row already had entries in an earlier tile (cont).
+//
+// Count pass (kScatter false), per slab d of tile b: entries -> ecnt[d *
+// ntiles + b], runs -> pcnt[...]; slab masks of the tile's first row ->
+// fmask[b], of the row left open at its end -> lmask[b].
+// Scatter pass: ecnt / pcnt hold the exclusive scans (slab-major, then
+// tile) and fmask the cont masks.  The tile is staged in LDS in slab order
+// so that one slab's run is stored contiguously; a pair start also stores
+// its entry position and row (prp, pair_row).
+template <typename V, bool kScatter>
+__global__ __launch_bounds__(kThreads) void k_seg_tile(
     const int32_t *__restrict__ rp, const int32_t *__restrict__ col, const V *__restrict__ val,
-    int32_t n, const int2 *__restrict__ coord, int32_t sbits, int32_t ns, int32_t dbits,
-    int32_t ntiles, const uint32_t *__restrict__ off, int32_t *__restrict__ seg_col,
-    V *__restrict__ seg_val, int32_t *__restrict__ seg_row) {
+    const int2 *__restrict__ coord, int32_t sbits, int32_t ns, int32_t dbits, int32_t ntiles,
+    uint32_t *__restrict__ ecnt, uint32_t *__restrict__ pcnt, uint32_t *__restrict__ fmask,
+    uint32_t *__restrict__ lmask, int32_t *__restrict__ seg_col, V *__restrict__ seg_val,
+    int32_t *__restrict__ prp, int32_t *__restrict__ pair_row) {
   constexpr int kWaves = kThreads / kWave;
+  constexpr int kChunks = kSegTile / kWave;   // 64 consecutive slots each
   __shared__ uint32_t wh[kWaves][kMaxSlabs];
-  __shared__ uint32_t s_toff[kMaxSlabs], s_goff[kMaxSlabs];
+  __shared__ uint32_t s_toff[kMaxSlabs], s_goff[kMaxSlabs], s_poff[kMaxSlabs];
   __shared__ uint32_t s_scan[4];
-  __shared__ int32_t s_end[kSegTile];   // row ends; reused for staged rows
+  __shared__ uint32_t s_cont[kMaskWords];
+  __shared__ uint64_t s_bal[kChunks];          // pair starts of each chunk
+  __shared__ uint32_t s_pre[kChunks + 1];      // pair starts before each chunk
+  __shared__ int32_t s_end[kSegTile];   // row ends; then the staged local rows
   __shared__ int32_t s_col[kSegTile];
-  __shared__ V s_val[kSegTile];
+  __shared__ V s_val[kScatter ? kSegTile : 1];
   for (int i = threadIdx.x; i < kWaves * kMaxSlabs; i += kThreads) (&wh[0][0])[i] = 0u;
-  const int b = blockIdx.x, tid = threadIdx.x, w = tid / kWave;
+  const int b = blockIdx.x, tid = threadIdx.x, w = tid / kWave, lane = lane_id();
   const int2 c0 = coord[b], c1 = coord[b + 1];
   const int32_t i0 = c0.x, j0 = c0.y, na = c1.x - c0.x, nz = c1.y - c0.y;
   for (int k = tid; k < na; k += kThreads) s_end[k] = rp[i0 + 1 + k] - j0;
+  if (kScatter && tid < kMaskWords) s_cont[tid] = fmask[int64_t(b) * kMaskWords + tid];
   __syncthreads();
   int32_t cc[kSegPer], rr[kSegPer];
   V vv[kSegPer];
   uint32_t rank[kSegPer];
 #pragma unroll
   for (int r = 0; r < kSegPer; ++r) {
-    const int32_t e = w * (kSegTile / kWaves) + r * kWave + lane_id();
+    const int32_t e = w * (kSegTile / kWaves) + r * kWave + lane;
     const bool valid = e < nz;
     cc[r] = valid ? col[j0 + e] : 0;
-    vv[r] = valid ? val[j0 + e] : V(0);
-    rr[r] = valid ? i0 + row_of(s_end, na, e) : 0;
+    if constexpr (kScatter) vv[r] = valid ? val[j0 + e] : V(0);
+    rr[r] = valid ? row_of(s_end, na, e) : 0;
     rank[r] = wave_digit_rank(uint32_t(cc[r]) >> sbits, valid, dbits, wh[w]);
   }
   __syncthreads();
@@ -831,62 +821,132 @@ __global__ __launch_bounds__(kThreads) void k_seg_scatter(
   const uint32_t first = block_exscan256(total, s_scan, &all);
   if (d < ns) {
     s_toff[d] = first;
-    s_goff[d] = off[int64_t(d) * ntiles + b];
+    if constexpr (kScatter) {
+      s_goff[d] = ecnt[int64_t(d) * ntiles + b];
+      s_poff[d] = pcnt[int64_t(d) * ntiles + b];
+    }
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kSegPer; ++r) {
-    const int32_t e = w * (kSegTile / kWaves) + r * kWave + lane_id();
+    const int32_t e = w * (kSegTile / kWaves) + r * kWave + lane;
     if (e < nz) {
       const uint32_t dg = uint32_t(cc[r]) >> sbits;
       const uint32_t slot = s_toff[dg] + wh[w][dg] + rank[r];
       s_col[slot] = cc[r];
-      s_val[slot] = vv[r];
       s_end[slot] = rr[r];
+      if constexpr (kScatter) s_val[slot] = vv[r];
     }
   }
   __syncthreads();
-  for (int32_t slot = tid; slot < nz; slot += kThreads) {
-    const int32_t cv = s_col[slot];
-    const uint32_t dg = uint32_t(cv) >> sbits;
-    const int64_t pos = int64_t(s_goff[dg]) + (slot - int32_t(s_toff[dg]));
-    seg_col[pos] = cv;
-    seg_val[pos] = s_val[slot];
-    seg_row[pos] = s_end[slot];
+  // Pair starts: slot k * kThreads + tid, so each wave flags 64 consecutive
+  // slots (chunk k * kWaves + w) with one ballot.
+  uint64_t bal[kSegPer];
+#pragma unroll
+  for (int k = 0; k < kSegPer; ++k) {
+    const int32_t slot = k * kThreads + tid;
+    bool f = false;
+    if (slot < nz) {
+      const uint32_t dg = uint32_t(s_col[slot]) >> sbits;
+      const int32_t lr = s_end[slot];
+      const bool head = slot == 0 || (uint32_t(s_col[slot - 1]) >> sbits) != dg;
+      f = head || s_end[slot - 1] != lr;
+      if (kScatter && head && lr == 0 && ((s_cont[dg >> 5] >> (dg & 31)) & 1u)) f = false;
+    }
+    bal[k] = __ballot(f);
+    if (lane == 0) s_bal[k * kWaves + w] = bal[k];
   }
-}
-
-// flag[j] = 1 where a (slab, row) pair starts in the slab-major order.
-__global__ __launch_bounds__(256) void k_pair_flags(const int32_t *__restrict__ seg_col,
-                                                    const int32_t *__restrict__ seg_row,
-                                                    int64_t nnz, int32_t sbits,
-                                                    uint32_t *__restrict__ flag) {
-  for (int64_t j = blockIdx.x * int64_t(256) + threadIdx.x; j < nnz;
-       j += int64_t(gridDim.x) * 256) {
-    bool f = j == 0;
-    if (!f) f = seg_row[j] != seg_row[j - 1] || (seg_col[j] >> sbits) != (seg_col[j - 1] >> sbits);
-    flag[j] = f ? 1u : 0u;
+  __syncthreads();
+  if (tid <= kChunks) {
+    uint32_t a = 0;
+    for (int q = 0; q < tid; ++q) a += uint32_t(__popcll(s_bal[q]));
+    s_pre[tid] = a;
   }
-}
-
-// pid = exclusive scan of the flags: pair p starts at entry prp[p] and
-// belongs to row pair_row[p]; prp[P] = nnz.
-__global__ __launch_bounds__(256) void k_pair_emit(const uint32_t *__restrict__ pid,
-                                                   const int32_t *__restrict__ seg_row,
-                                                   int64_t nnz, const int64_t *__restrict__ total,
-                                                   int32_t *__restrict__ prp,
-                                                   int32_t *__restrict__ pair_row) {
-  const int64_t P = *total;
-  for (int64_t j = blockIdx.x * int64_t(256) + threadIdx.x; j < nnz;
-       j += int64_t(gridDim.x) * 256) {
-    const uint32_t p = pid[j];
-    const uint32_t next = j + 1 < nnz ? pid[j + 1] : uint32_t(P);
-    if (next != p) {
-      prp[p] = int32_t(j);
-      pair_row[p] = seg_row[j];
+  __syncthreads();
+  // Pair starts before slot x of the tile.
+  auto starts_before = [&](uint32_t x) -> uint32_t {
+    const uint32_t q = x / kWave, o = x % kWave;
+    return s_pre[q] + (o ? uint32_t(__popcll(s_bal[q] & ((1ull << o) - 1ull))) : 0u);
+  };
+  if constexpr (!kScatter) {
+    bool fb = false, lb = false;
+    if (d < ns) {
+      const uint32_t a0 = s_toff[d];
+      ecnt[int64_t(d) * ntiles + b] = total;
+      pcnt[int64_t(d) * ntiles + b] = starts_before(a0 + total) - starts_before(a0);
+      // Slots of a slab run are in row order: its head holds the smallest
+      // local row, its tail the largest.
+      fb = total > 0 && s_end[a0] == 0;
+      lb = total > 0 && s_end[a0 + total - 1] == na;
+    }
+    const uint64_t fmb = __ballot(fb), lmb = __ballot(lb);
+    if (lane == 0) {
+      fmask[int64_t(b) * kMaskWords + 2 * w] = uint32_t(fmb);
+      fmask[int64_t(b) * kMaskWords + 2 * w + 1] = uint32_t(fmb >> 32);
+      lmask[int64_t(b) * kMaskWords + 2 * w] = uint32_t(lmb);
+      lmask[int64_t(b) * kMaskWords + 2 * w + 1] = uint32_t(lmb >> 32);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kSegPer; ++k) {
+      const int32_t slot = k * kThreads + tid;
+      if (slot < nz) {
+        const int32_t cv = s_col[slot];
+        const uint32_t dg = uint32_t(cv) >> sbits;
+        const int64_t pos = int64_t(s_goff[dg]) + (slot - int32_t(s_toff[dg]));
+        seg_col[pos] = cv;
+        seg_val[pos] = s_val[slot];
+        if ((bal[k] >> lane) & 1ull) {
+          const uint32_t here = s_pre[k * kWaves + w] + uint32_t(__popcll(bal[k] & lanes_below()));
+          const uint32_t pid = s_poff[dg] + here - starts_before(s_toff[dg]);
+          prp[pid] = int32_t(pos);
+          pair_row[pid] = i0 + s_end[slot];
+        }
+      }
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) prp[P] = int32_t(nnz);
+}
+
+// A tile that starts inside a row R continues R's runs from the earlier
+// tiles that hold R: their end-of-tile slab masks are OR-ed (walking back
+// while the tiles stay inside R), kept where the tile's first row has
+// entries too, and stored as the tile's cont mask; each such slab's run is
+// taken off the tile's pair count.
+__global__ __launch_bounds__(256) void k_seg_cont(const int32_t *__restrict__ rp, int32_t n,
+                                                  const int2 *__restrict__ coord, int32_t ntiles,
+                                                  const uint32_t *__restrict__ lmask,
+                                                  uint32_t *__restrict__ fmask,
+                                                  uint32_t *__restrict__ pcnt) {
+  for (int32_t b = blockIdx.x * 256 + threadIdx.x; b < ntiles; b += gridDim.x * 256) {
+    const int2 c0 = coord[b];
+    const int32_t R = c0.x;
+    uint32_t m[kMaskWords];
+#pragma unroll
+    for (int k = 0; k < kMaskWords; ++k) m[k] = 0u;
+    if (b > 0 && R < n && rp[R] < c0.y) {
+      int32_t q = b - 1;
+      for (;;) {
+#pragma unroll
+        for (int k = 0; k < kMaskWords; ++k) m[k] |= lmask[int64_t(q) * kMaskWords + k];
+        if (q > 0 && coord[q].x == R && rp[R] < coord[q].y)
+          --q;
+        else
+          break;
+      }
+#pragma unroll
+      for (int k = 0; k < kMaskWords; ++k) {
+        m[k] &= fmask[int64_t(b) * kMaskWords + k];
+        uint32_t bits = m[k];
+        while (bits) {
+          const int d = k * 32 + __builtin_ctz(bits);
+          pcnt[int64_t(d) * ntiles + b] -= 1u;
+          bits &= bits - 1u;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kMaskWords; ++k) fmask[int64_t(b) * kMaskWords + k] = m[k];
+  }
 }
 
 // Row-major order of the pairs: key = row << 32 | pair, sorted stably by
@@ -1132,12 +1192,12 @@ __global__ __launch_bounds__(kThreads) void k_win_count(const int32_t *__restric
 
 // Stable scatter of each build tile to its (window, row) order inside its
 // block, packing each entry as local row << kWinBits | column in window.
-// The pair of entry e is (pid[e + 1] or P) - 1, pid being the exclusive scan
-// of the pair-start flags.
+// The pair of entry e is the last pair of the block whose first entry
+// prp[p] is <= e.
 template <typename V>
 __global__ __launch_bounds__(kThreads) void k_win_scatter(
     const int32_t *__restrict__ seg_col, const V *__restrict__ seg_val,
-    const uint32_t *__restrict__ pid, int64_t nnz, int64_t P, const int2 *__restrict__ wb,
+    const int32_t *__restrict__ prp, const int2 *__restrict__ wb,
     const uint32_t *__restrict__ tbase, int32_t nblk, int32_t nwin, int32_t wbits,
     const uint32_t *__restrict__ off, uint32_t *__restrict__ out_pk, V *__restrict__ out_val) {
   constexpr int kWaves = kThreads / kWave;
@@ -1171,7 +1231,15 @@ __global__ __launch_bounds__(kThreads) void k_win_scatter(
     vv[r] = V(0);
     if (valid) {
       const uint32_t c = uint32_t(seg_col[e]);
-      const uint32_t pe = (e + 1 < nnz ? pid[e + 1] : uint32_t(P)) - 1u;
+      int32_t lo = blk.x, hi = wb[b + 1].x;   // prp[lo] <= e < prp[hi]
+      while (hi - lo > 1) {
+        const int32_t m = (lo + hi) >> 1;
+        if (prp[m] <= e)
+          lo = m;
+        else
+          hi = m;
+      }
+      const uint32_t pe = uint32_t(lo);
       dg[r] = c >> kWinBits;
       pk[r] = ((pe - uint32_t(blk.x)) << kWinBits) | (c & uint32_t(kWinSize - 1));
       vv[r] = seg_val[e];
@@ -1467,7 +1535,7 @@ struct Layout {
   V *val2, *x2;
   int64_t *total;
   // column segmenting
-  int32_t *seg_col, *prp, *pair_row, *seg_row, *rpp, *pidx;
+  int32_t *seg_col, *prp, *pair_row, *rpp, *pidx;
   int2 *cstart;
   // hot slab through LDS windows
   int2 *wb;
@@ -1476,7 +1544,7 @@ struct Layout {
   int64_t *info;
   V *seg_val;
   typename Form<V>::Acc *seg_part;
-  uint32_t *seg_flag, *seg_cnt, *seg_scan;
+  uint32_t *seg_cnt, *seg_pcnt, *seg_fmask, *seg_lmask, *seg_scan;
 };
 
 // One layout function serves both measuring (ws == nullptr) and carving.
@@ -1529,17 +1597,14 @@ Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs, size_t *byte
     L.prp = c.take<int32_t>(size_t(z + 1));
     L.pair_row = c.take<int32_t>(size_t(z));
     // The partials are written only by the iterations; during the build
-    // the same bytes hold the entries' rows and the pair flags.
-    const size_t part_bytes = size_t(z) * sizeof(typename Form<V>::Acc);
-    const size_t tmp_bytes = size_t(z) * 4 + 256 + size_t(z + 1) * 4;
-    uint8_t *region = c.take<uint8_t>(part_bytes > tmp_bytes ? part_bytes : tmp_bytes);
-    L.seg_part = reinterpret_cast<typename Form<V>::Acc *>(region);
-    L.seg_row = reinterpret_cast<int32_t *>(region);
-    L.seg_flag = region ? reinterpret_cast<uint32_t *>(region + (size_t(z) * 4 + 255) / 256 * 256)
-                        : nullptr;
+    // the same bytes hold the keys of the pairs' row-major sort.
+    L.seg_part = c.take<typename Form<V>::Acc>(size_t(z));
     const int64_t wcnt = int64_t(kMaxWins) * (z / kWinTile + z * (kWinRowCost + 1) / kWinBlock + 4);
     const int64_t cnt_n = kMaxSlabs * ntiles > wcnt ? kMaxSlabs * ntiles : wcnt;
     L.seg_cnt = c.take<uint32_t>(size_t(cnt_n));
+    L.seg_pcnt = c.take<uint32_t>(size_t(kMaxSlabs * ntiles));
+    L.seg_fmask = c.take<uint32_t>(size_t(kMaskWords * ntiles));
+    L.seg_lmask = c.take<uint32_t>(size_t(kMaskWords * ntiles));
     int64_t scan_n = z + 1 > cnt_n ? z + 1 : cnt_n;
     if (n + 1 > scan_n) scan_n = n + 1;
     L.seg_scan = c.take<uint32_t>(size_t(scan_ws_elems(scan_n)));
@@ -1603,16 +1668,18 @@ void launch_spmv(int ipt, int32_t nb, hipStream_t s, const int32_t *rp, const in
                        n, coord, c, tele, blk_ysum, blk_carry, blk_head, part);
 }
 
-// info[0] = P, info[1] = E0 (entries of slab 0), info[2] = P0 (its pairs).
-__global__ void k_seg_info(const uint32_t *__restrict__ cnt, int32_t ntiles,
-                           const uint32_t *__restrict__ pid, int64_t nnz,
-                           const int64_t *__restrict__ total, int64_t *__restrict__ info) {
+// info[0] = P, info[1] = E0 (entries of slab 0), info[2] = P0 (its pairs);
+// prp[P] = nnz.  eoff / poff are the scanned per-(slab, tile) counts, so
+// their entry for (slab 1, tile 0) is slab 0's total.
+__global__ void k_seg_info(const uint32_t *__restrict__ eoff, const uint32_t *__restrict__ poff,
+                           int32_t ntiles, int64_t nnz, const int64_t *__restrict__ total,
+                           int32_t *__restrict__ prp, int64_t *__restrict__ info) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     const int64_t P = *total;
-    const int64_t E0 = cnt[ntiles];   // scanned (slab 1, tile 0): entries of slab 0
     info[0] = P;
-    info[1] = E0;
-    info[2] = E0 < nnz ? int64_t(pid[E0]) : P;
+    info[1] = eoff[ntiles];
+    info[2] = poff[ntiles];
+    if (P >= 0 && P <= nnz) prp[P] = int32_t(nnz);
   }
 }
 
@@ -1643,24 +1710,22 @@ pp_status build_segments(const Layout<V> &L, const int32_t *rp, const int32_t *c
   const int32_t ntiles = int32_t((n + nnz + kSegTile - 1) / kSegTile);
   hipLaunchKernelGGL(k_partition, dim3(grid_for(int64_t(ntiles) + 1, 256, 4096)), dim3(256), 0, s,
                      rp, n32, int32_t(nnz), ntiles, kSegTile, L.coord);
-  hipLaunchKernelGGL(k_seg_count, dim3(ntiles), dim3(kThreads), 0, s, col, L.coord, sbits, ns,
-                     dbits, ntiles, L.seg_cnt);
-  PP_LAUNCHED("k_seg_count");
+  hipLaunchKernelGGL((k_seg_tile<V, false>), dim3(ntiles), dim3(kThreads), 0, s, rp, col, val,
+                     L.coord, sbits, ns, dbits, ntiles, L.seg_cnt, L.seg_pcnt, L.seg_fmask,
+                     L.seg_lmask, nullptr, nullptr, nullptr, nullptr);
+  hipLaunchKernelGGL(k_seg_cont, dim3(grid_for(ntiles, 256, 4096)), dim3(256), 0, s, rp, n32,
+                     L.coord, ntiles, L.seg_lmask, L.seg_fmask, L.seg_pcnt);
+  PP_LAUNCHED("k_seg_tile (count)/k_seg_cont");
   pp_status st = exscan_u32(L.seg_cnt, L.seg_cnt, int64_t(ns) * ntiles, L.seg_scan, nullptr, s);
   if (st != PP_OK) return st;
-  hipLaunchKernelGGL(k_seg_scatter<V>, dim3(ntiles), dim3(kThreads), 0, s, rp, col, val, n32,
-                     L.coord, sbits, ns, dbits, ntiles, L.seg_cnt, L.seg_col, L.seg_val, L.seg_row);
-  PP_LAUNCHED("k_seg_scatter");
-  const int gZ = grid_for(nnz, 256, 16384);
-  hipLaunchKernelGGL(k_pair_flags, dim3(gZ), dim3(256), 0, s, L.seg_col, L.seg_row, nnz, sbits,
-                     L.seg_flag);
-  st = exscan_u32(L.seg_flag, L.seg_flag, nnz, L.seg_scan, L.total, s);
+  st = exscan_u32(L.seg_pcnt, L.seg_pcnt, int64_t(ns) * ntiles, L.seg_scan, L.total, s);
   if (st != PP_OK) return st;
-  hipLaunchKernelGGL(k_pair_emit, dim3(gZ), dim3(256), 0, s, L.seg_flag, L.seg_row, nnz, L.total,
-                     L.prp, L.pair_row);
-  hipLaunchKernelGGL(k_seg_info, dim3(1), dim3(64), 0, s, L.seg_cnt, ntiles, L.seg_flag, nnz,
-                     L.total, L.info);
-  PP_LAUNCHED("k_pair_flags/k_pair_emit/k_seg_info");
+  hipLaunchKernelGGL((k_seg_tile<V, true>), dim3(ntiles), dim3(kThreads), 0, s, rp, col, val,
+                     L.coord, sbits, ns, dbits, ntiles, L.seg_cnt, L.seg_pcnt, L.seg_fmask,
+                     nullptr, L.seg_col, L.seg_val, L.prp, L.pair_row);
+  hipLaunchKernelGGL(k_seg_info, dim3(1), dim3(64), 0, s, L.seg_cnt, L.seg_pcnt, ntiles, nnz,
+                     L.total, L.prp, L.info);
+  PP_LAUNCHED("k_seg_tile (scatter)/k_seg_info");
   int64_t info[3] = {0, 0, 0};
   PP_HIP(hipMemcpyAsync(info, L.info, sizeof(info), hipMemcpyDeviceToHost, s));
   PP_HIP(hipStreamSynchronize(s));
@@ -1697,7 +1762,7 @@ pp_status build_segments(const Layout<V> &L, const int32_t *rp, const int32_t *c
     uint32_t *tmp_pk = reinterpret_cast<uint32_t *>(L.col2);
     V *tmp_val = L.val2;
     hipLaunchKernelGGL(k_win_scatter<V>, dim3(unsigned(tmax)), dim3(kThreads), 0, s, L.seg_col,
-                       L.seg_val, L.seg_flag, nnz, P, L.wb, L.wtb, nblk, nwin, wbits, L.seg_cnt,
+                       L.seg_val, L.prp, L.wb, L.wtb, nblk, nwin, wbits, L.seg_cnt,
                        tmp_pk, tmp_val);
     hipLaunchKernelGGL(k_win_chunks, dim3(grid_for(int64_t(nblk) * (nwin + 1), 256, 4096)),
                        dim3(256), 0, s, L.wb, L.wtb, L.seg_cnt, nblk, nwin, L.wchunk);
