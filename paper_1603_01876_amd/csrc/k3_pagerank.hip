@@ -764,18 +764,27 @@ constexpr int kMaskWords = kMaxSlabs / 32;
 //
 // Count pass (kScatter false), per slab d of tile b: entries -> ecnt[d *
 // ntiles + b], runs -> pcnt[...]; slab masks of the tile's first row ->
-// fmask[b], of the row left open at its end -> lmask[b].
+// fmask[b], of the row left open at its end -> lmask[b].  With kRelabel the
+// tile is one of the relabelled matrix (row pointers rp): the count pass
+// also produces its entries, new row p taking old row order[p] of (rp0,
+// col0, val0) with every column mapped through newlabel, into (col, val).
 // Scatter pass: ecnt / pcnt hold the exclusive scans (slab-major, then
 // tile) and fmask the cont masks.  The tile is staged in LDS in slab order
 // so that one slab's run is stored contiguously; a pair start also stores
 // its entry position and row (prp, pair_row).
-template <typename V, bool kScatter>
+struct RelabelSrc {
+  const int32_t *rp0, *col0, *order, *newlabel;
+  const void *val0;
+};
+
+template <typename V, bool kScatter, bool kRelabel>
 __global__ __launch_bounds__(kThreads) void k_seg_tile(
-    const int32_t *__restrict__ rp, const int32_t *__restrict__ col, const V *__restrict__ val,
-    const int2 *__restrict__ coord, int32_t sbits, int32_t ns, int32_t dbits, int32_t ntiles,
-    uint32_t *__restrict__ ecnt, uint32_t *__restrict__ pcnt, uint32_t *__restrict__ fmask,
-    uint32_t *__restrict__ lmask, int32_t *__restrict__ seg_col, V *__restrict__ seg_val,
-    int32_t *__restrict__ prp, int32_t *__restrict__ pair_row) {
+    const int32_t *__restrict__ rp, int32_t *__restrict__ col, V *__restrict__ val, int32_t n,
+    RelabelSrc rs, const int2 *__restrict__ coord, int32_t sbits, int32_t ns, int32_t dbits,
+    int32_t ntiles, uint32_t *__restrict__ ecnt, uint32_t *__restrict__ pcnt,
+    uint32_t *__restrict__ fmask, uint32_t *__restrict__ lmask, int32_t *__restrict__ seg_col,
+    V *__restrict__ seg_val, int32_t *__restrict__ prp, int32_t *__restrict__ pair_row) {
+  static_assert(!(kScatter && kRelabel), "relabelling happens in the count pass");
   constexpr int kWaves = kThreads / kWave;
   constexpr int kChunks = kSegTile / kWave;   // 64 consecutive slots each
   __shared__ uint32_t wh[kWaves][kMaxSlabs];
@@ -787,11 +796,16 @@ __global__ __launch_bounds__(kThreads) void k_seg_tile(
   __shared__ int32_t s_end[kSegTile];   // row ends; then the staged local rows
   __shared__ int32_t s_col[kSegTile];
   __shared__ V s_val[kScatter ? kSegTile : 1];
+  __shared__ int32_t s_src[kRelabel ? kSegTile + 1 : 1];   // old row start - new row start
   for (int i = threadIdx.x; i < kWaves * kMaxSlabs; i += kThreads) (&wh[0][0])[i] = 0u;
   const int b = blockIdx.x, tid = threadIdx.x, w = tid / kWave, lane = lane_id();
   const int2 c0 = coord[b], c1 = coord[b + 1];
   const int32_t i0 = c0.x, j0 = c0.y, na = c1.x - c0.x, nz = c1.y - c0.y;
   for (int k = tid; k < na; k += kThreads) s_end[k] = rp[i0 + 1 + k] - j0;
+  if constexpr (kRelabel) {
+    for (int k = tid; k <= na; k += kThreads)
+      if (i0 + k < n) s_src[k] = rs.rp0[rs.order[i0 + k]] - rp[i0 + k];
+  }
   if (kScatter && tid < kMaskWords) s_cont[tid] = fmask[int64_t(b) * kMaskWords + tid];
   __syncthreads();
   int32_t cc[kSegPer], rr[kSegPer];
@@ -801,9 +815,32 @@ __global__ __launch_bounds__(kThreads) void k_seg_tile(
   for (int r = 0; r < kSegPer; ++r) {
     const int32_t e = w * (kSegTile / kWaves) + r * kWave + lane;
     const bool valid = e < nz;
-    cc[r] = valid ? col[j0 + e] : 0;
-    if constexpr (kScatter) vv[r] = valid ? val[j0 + e] : V(0);
     rr[r] = valid ? row_of(s_end, na, e) : 0;
+    if constexpr (kRelabel) {
+      const int32_t src = valid ? j0 + e + s_src[rr[r]] : 0;
+      cc[r] = valid ? rs.col0[src] : 0;
+      vv[r] = valid ? static_cast<const V *>(rs.val0)[src] : V(0);
+    } else {
+      cc[r] = valid ? col[j0 + e] : 0;
+      if constexpr (kScatter) vv[r] = valid ? val[j0 + e] : V(0);
+    }
+  }
+  if constexpr (kRelabel) {
+#pragma unroll
+    for (int r = 0; r < kSegPer; ++r)
+      if (w * (kSegTile / kWaves) + r * kWave + lane < nz) cc[r] = rs.newlabel[cc[r]];
+#pragma unroll
+    for (int r = 0; r < kSegPer; ++r) {
+      const int32_t e = w * (kSegTile / kWaves) + r * kWave + lane;
+      if (e < nz) {
+        col[j0 + e] = cc[r];
+        val[j0 + e] = vv[r];
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kSegPer; ++r) {
+    const bool valid = w * (kSegTile / kWaves) + r * kWave + lane < nz;
     rank[r] = wave_digit_rank(uint32_t(cc[r]) >> sbits, valid, dbits, wh[w]);
   }
   __syncthreads();
@@ -1536,7 +1573,7 @@ struct Layout {
   int64_t *total;
   // column segmenting
   int32_t *seg_col, *prp, *pair_row, *rpp, *pidx;
-  int2 *cstart;
+  int2 *cstart, *seg_coord;
   // hot slab through LDS windows
   int2 *wb;
   uint32_t *wtb;
@@ -1605,6 +1642,7 @@ Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs, size_t *byte
     L.seg_pcnt = c.take<uint32_t>(size_t(kMaxSlabs * ntiles));
     L.seg_fmask = c.take<uint32_t>(size_t(kMaskWords * ntiles));
     L.seg_lmask = c.take<uint32_t>(size_t(kMaskWords * ntiles));
+    L.seg_coord = c.take<int2>(size_t(ntiles + 1));
     int64_t scan_n = z + 1 > cnt_n ? z + 1 : cnt_n;
     if (n + 1 > scan_n) scan_n = n + 1;
     L.seg_scan = c.take<uint32_t>(size_t(scan_ws_elems(scan_n)));
@@ -1690,16 +1728,19 @@ struct SegInfo {
   int32_t sbits = 0, ns = 0;
   int64_t P = 0, E0 = 0, P0 = 0;
   int32_t nblk_w = 0, nwin = 0;
+  bool relabelled = false;   // the count pass wrote the relabelled entries
 };
 
 // Segmented layout of the matrix (rp, col, val): see the kernels above.
-// Segmenting does not apply with fewer than two slabs or when pairs +
-// entries reach 2^31.  Reads the pair counts back to the host, so it
+// With rl the matrix is the relabelled one, whose entries (col, val) the
+// count pass writes from rl's source matrix (out->relabelled tells whether
+// it ran).  Segmenting does not apply with fewer than two slabs or when
+// pairs + entries reach 2^31.  Reads the pair counts back to the host, so it
 // synchronizes the stream once.
 template <typename V>
-pp_status build_segments(const Layout<V> &L, const int32_t *rp, const int32_t *col, const V *val,
-                         int64_t n, int64_t nnz, int slab_log2, int hot_windows, SegInfo *out,
-                         hipStream_t s) {
+pp_status build_segments(const Layout<V> &L, const int32_t *rp, int32_t *col, V *val, int64_t n,
+                         int64_t nnz, int slab_log2, int hot_windows, const RelabelSrc *rl,
+                         SegInfo *out, hipStream_t s) {
   *out = SegInfo{};
   int sbits = slab_log2;
   while (((n - 1) >> sbits) + 1 > kMaxSlabs) ++sbits;
@@ -1709,20 +1750,27 @@ pp_status build_segments(const Layout<V> &L, const int32_t *rp, const int32_t *c
   const int32_t n32 = int32_t(n);
   const int32_t ntiles = int32_t((n + nnz + kSegTile - 1) / kSegTile);
   hipLaunchKernelGGL(k_partition, dim3(grid_for(int64_t(ntiles) + 1, 256, 4096)), dim3(256), 0, s,
-                     rp, n32, int32_t(nnz), ntiles, kSegTile, L.coord);
-  hipLaunchKernelGGL((k_seg_tile<V, false>), dim3(ntiles), dim3(kThreads), 0, s, rp, col, val,
-                     L.coord, sbits, ns, dbits, ntiles, L.seg_cnt, L.seg_pcnt, L.seg_fmask,
-                     L.seg_lmask, nullptr, nullptr, nullptr, nullptr);
+                     rp, n32, int32_t(nnz), ntiles, kSegTile, L.seg_coord);
+  if (rl) {
+    hipLaunchKernelGGL((k_seg_tile<V, false, true>), dim3(ntiles), dim3(kThreads), 0, s, rp, col,
+                       val, n32, *rl, L.seg_coord, sbits, ns, dbits, ntiles, L.seg_cnt,
+                       L.seg_pcnt, L.seg_fmask, L.seg_lmask, nullptr, nullptr, nullptr, nullptr);
+    out->relabelled = true;
+  } else {
+    hipLaunchKernelGGL((k_seg_tile<V, false, false>), dim3(ntiles), dim3(kThreads), 0, s, rp, col,
+                       val, n32, RelabelSrc{}, L.seg_coord, sbits, ns, dbits, ntiles, L.seg_cnt,
+                       L.seg_pcnt, L.seg_fmask, L.seg_lmask, nullptr, nullptr, nullptr, nullptr);
+  }
   hipLaunchKernelGGL(k_seg_cont, dim3(grid_for(ntiles, 256, 4096)), dim3(256), 0, s, rp, n32,
-                     L.coord, ntiles, L.seg_lmask, L.seg_fmask, L.seg_pcnt);
+                     L.seg_coord, ntiles, L.seg_lmask, L.seg_fmask, L.seg_pcnt);
   PP_LAUNCHED("k_seg_tile (count)/k_seg_cont");
   pp_status st = exscan_u32(L.seg_cnt, L.seg_cnt, int64_t(ns) * ntiles, L.seg_scan, nullptr, s);
   if (st != PP_OK) return st;
   st = exscan_u32(L.seg_pcnt, L.seg_pcnt, int64_t(ns) * ntiles, L.seg_scan, L.total, s);
   if (st != PP_OK) return st;
-  hipLaunchKernelGGL((k_seg_tile<V, true>), dim3(ntiles), dim3(kThreads), 0, s, rp, col, val,
-                     L.coord, sbits, ns, dbits, ntiles, L.seg_cnt, L.seg_pcnt, L.seg_fmask,
-                     nullptr, L.seg_col, L.seg_val, L.prp, L.pair_row);
+  hipLaunchKernelGGL((k_seg_tile<V, true, false>), dim3(ntiles), dim3(kThreads), 0, s, rp, col,
+                     val, n32, RelabelSrc{}, L.seg_coord, sbits, ns, dbits, ntiles, L.seg_cnt,
+                     L.seg_pcnt, L.seg_fmask, nullptr, L.seg_col, L.seg_val, L.prp, L.pair_row);
   hipLaunchKernelGGL(k_seg_info, dim3(1), dim3(64), 0, s, L.seg_cnt, L.seg_pcnt, ntiles, nnz,
                      L.total, L.prp, L.info);
   PP_LAUNCHED("k_seg_tile (scatter)/k_seg_info");
@@ -1732,6 +1780,7 @@ pp_status build_segments(const Layout<V> &L, const int32_t *rp, const int32_t *c
   const int64_t P = info[0], E0 = info[1], P0 = info[2];
   if (P <= 0 || P > nnz || P + nnz > int64_t(INT32_MAX)) return PP_OK;
   SegInfo si;
+  si.relabelled = out->relabelled;
   si.sbits = sbits;
   si.ns = ns;
   si.P = P;
@@ -1856,25 +1905,35 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
   hipLaunchKernelGGL(k_block_flags, dim3(grid_for(nb, 256, 4096)), dim3(256), 0, s, rp, n32, nb,
                      L.coord, L.carry_row, L.closes);
   PP_LAUNCHED("k_partition/k_block_flags");
-  if (weights) {
-    hipLaunchKernelGGL(k_relabel_copy<V>, dim3(nb), dim3(kThreads), 0, s, AT0.row_ptr, AT0.col,
-                       static_cast<const V *>(AT0.val), L.order, L.newlabel, L.rp2, n32, L.coord,
-                       L.col2, L.val2);
-    hipLaunchKernelGGL(k_permute_in<V>, dim3(gNK), dim3(256), 0, s, r, L.order, n32, k, L.x2);
-    PP_LAUNCHED("k_relabel_copy/k_permute_in");
-  }
 
   // Column segmenting (single vector only).  Automatic choice: segment
   // once r no longer fits one XCD's 4 MiB L2, in slabs of 2 MiB of r.
-  SegInfo si;
-  int32_t nbp = 0, ncomb = 0;
-  int64_t Pr = 0;   // pairs (and their entries) left to the raw SpMV
+  // When it applies to a relabelled matrix, its first pass writes the
+  // relabelled entries; otherwise k_relabel_copy does.
   int slab_log2 = g_cfg.slab_log2;
   if (slab_log2 < 0)
     slab_log2 = n * int64_t(sizeof(V)) > (int64_t(4) << 20) ? (sizeof(V) == 4 ? 19 : 18) : 0;
-  if (k == 1 && slab_log2 > 0 && iters > 0) {
-    st = build_segments<V>(L, rp, col, val, n, nnz, slab_log2, g_cfg.hot_windows, &si, s);
+  const bool segment = k == 1 && slab_log2 > 0 && iters > 0;
+  if (weights) {
+    hipLaunchKernelGGL(k_permute_in<V>, dim3(gNK), dim3(256), 0, s, r, L.order, n32, k, L.x2);
+    PP_LAUNCHED("k_permute_in");
+  }
+  SegInfo si;
+  int32_t nbp = 0, ncomb = 0;
+  int64_t Pr = 0;   // pairs (and their entries) left to the raw SpMV
+  if (segment) {
+    const RelabelSrc rl{AT0.row_ptr, AT0.col, L.order, L.newlabel, AT0.val};
+    st = build_segments<V>(L, rp, const_cast<int32_t *>(col), const_cast<V *>(val), n, nnz,
+                           slab_log2, g_cfg.hot_windows, weights ? &rl : nullptr, &si, s);
     if (st != PP_OK) return st;
+  }
+  if (weights && !si.relabelled) {
+    hipLaunchKernelGGL(k_relabel_copy<V>, dim3(nb), dim3(kThreads), 0, s, AT0.row_ptr, AT0.col,
+                       static_cast<const V *>(AT0.val), L.order, L.newlabel, L.rp2, n32, L.coord,
+                       L.col2, L.val2);
+    PP_LAUNCHED("k_relabel_copy");
+  }
+  if (segment) {
     if (si.P > 0) {
       Pr = si.P - si.P0;
       const int64_t Er = nnz - si.E0;

@@ -105,14 +105,34 @@ def test_segmented_structured(case, dtype):
     check(n, rp, col, val, dtype, slabs)
 
 
-def test_single_slab_falls_back_to_one_pass():
+@pytest.mark.parametrize("relabel", [False, True])
+def test_single_slab_falls_back_to_one_pass(relabel):
+    # With weights, a matrix that is not segmented is relabelled by its own
+    # copy pass instead of the segment build's count pass.
     f = kron_matrix(12)
     trp, tcol, tval = oracle.transpose_csr(f.n, f.A_rp, f.A_col, f.A_val)
     AT = pp.CSR.from_arrays(f.n, trp, tcol, tval, "f32")
-    base, bsums = gpu_k3(AT, f.n, "f32", 0)
+    w = torch.as_tensor(f.d_out).to(torch.int32).cuda() if relabel else None
+    base, bsums = gpu_k3(AT, f.n, "f32", 0, weights=w)
     for slab in (12, 20, 30):      # one slab covers all 2^12 vertices
-        got, sums = gpu_k3(AT, f.n, "f32", slab)
+        got, sums = gpu_k3(AT, f.n, "f32", slab, weights=w)
         assert got.tobytes() == base.tobytes() and sums.tobytes() == bsums.tobytes()
+    if relabel:
+        want, _ = oracle.pagerank(f.n, f.A_rp, f.A_col, f.A_val, oracle.init_r(f.n, 7), 20, C)
+        assert rel_l1(base, want) <= TOL["f32"]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_segmented_relabelled_long_rows(dtype):
+    # Relabelled in the segment build's count pass, with rows of A^T that span
+    # many build tiles (runs continued across tiles) in several slabs, and
+    # weights that leave many vertices in one bucket.
+    rng = np.random.default_rng(31)
+    n = 50000
+    rp, col, val = random_matrix(n, rng, long_rows=[(5, 40000), (n - 1, 30000), (777, 4097),
+                                                     (778, 1025)])
+    weights = rng.integers(-3, 5000, n) * (rng.random(n) < 0.3)
+    check(n, rp, col, val, dtype, slabs=[9, 12, 14], weights=weights, ipt=16)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
