@@ -762,14 +762,14 @@ constexpr int kMaskWords = kMaxSlabs / 32;
 // tile starts a pair, except the run of the tile's first row in a slab
 // where that row already had entries in an earlier tile (cont).
 //
-// Count pass (kScatter false), per slab d of tile b: entries -> ecnt[d *
-// ntiles + b], runs -> pcnt[...]; slab masks of the tile's first row ->
+// Count pass (kScatter false), per slab d of tile b: entries -> ecnt[b *
+// ns + d], runs -> pcnt[...]; slab masks of the tile's first row ->
 // fmask[b], of the row left open at its end -> lmask[b].  With kRelabel the
 // tile is one of the relabelled matrix (row pointers rp): the count pass
 // also produces its entries, new row p taking old row order[p] of (rp0,
 // col0, val0) with every column mapped through newlabel, into (col, val).
-// Scatter pass: ecnt / pcnt hold the exclusive scans (slab-major, then
-// tile) and fmask the cont masks.  The tile is staged in LDS in slab order
+// Scatter pass: ecnt / pcnt hold the offsets in slab-major, then tile,
+// order (still stored tile by tile) and fmask the cont masks.  The tile is staged in LDS in slab order
 // so that one slab's run is stored contiguously; a pair start also stores
 // its entry position and row (prp, pair_row).
 struct RelabelSrc {
@@ -859,8 +859,8 @@ __global__ __launch_bounds__(kThreads) void k_seg_tile(
   if (d < ns) {
     s_toff[d] = first;
     if constexpr (kScatter) {
-      s_goff[d] = ecnt[int64_t(d) * ntiles + b];
-      s_poff[d] = pcnt[int64_t(d) * ntiles + b];
+      s_goff[d] = ecnt[int64_t(b) * ns + d];
+      s_poff[d] = pcnt[int64_t(b) * ns + d];
     }
   }
   __syncthreads();
@@ -909,8 +909,8 @@ __global__ __launch_bounds__(kThreads) void k_seg_tile(
     bool fb = false, lb = false;
     if (d < ns) {
       const uint32_t a0 = s_toff[d];
-      ecnt[int64_t(d) * ntiles + b] = total;
-      pcnt[int64_t(d) * ntiles + b] = starts_before(a0 + total) - starts_before(a0);
+      ecnt[int64_t(b) * ns + d] = total;
+      pcnt[int64_t(b) * ns + d] = starts_before(a0 + total) - starts_before(a0);
       // Slots of a slab run are in row order: its head holds the smallest
       // local row, its tail the largest.
       fb = total > 0 && s_end[a0] == 0;
@@ -944,6 +944,44 @@ __global__ __launch_bounds__(kThreads) void k_seg_tile(
   }
 }
 
+// Offsets of a tiles x slabs count matrix stored tile by tile (row b =
+// tile b, ns counts): out[b * ns + d] = counts of all slabs d' < d plus
+// those of slab d in tiles before b, i.e. an exclusive scan in slab-major
+// order, computed with whole rows only.  Tiles are taken kColTiles at a time:
+// block sums per slab, a scan of those (slab-major), then each block's
+// running prefix.
+constexpr int kColTiles = 256;
+
+__global__ __launch_bounds__(kThreads) void k_col_sums(const uint32_t *__restrict__ cnt,
+                                                       int32_t ntiles, int32_t ns, int32_t nblk,
+                                                       uint32_t *__restrict__ bsum) {
+  const int d = threadIdx.x, blk = blockIdx.x;
+  if (d >= ns) return;
+  const int32_t b0 = blk * kColTiles;
+  const int32_t b1 = b0 + kColTiles < ntiles ? b0 + kColTiles : ntiles;
+  uint32_t a = 0;
+#pragma unroll 8
+  for (int32_t b = b0; b < b1; ++b) a += cnt[int64_t(b) * ns + d];
+  bsum[int64_t(d) * nblk + blk] = a;
+}
+
+__global__ __launch_bounds__(kThreads) void k_col_offsets(const uint32_t *__restrict__ cnt,
+                                                          int32_t ntiles, int32_t ns,
+                                                          int32_t nblk,
+                                                          const uint32_t *__restrict__ boff,
+                                                          uint32_t *__restrict__ out) {
+  const int d = threadIdx.x, blk = blockIdx.x;
+  if (d >= ns) return;
+  const int32_t b0 = blk * kColTiles;
+  const int32_t b1 = b0 + kColTiles < ntiles ? b0 + kColTiles : ntiles;
+  uint32_t run = boff[int64_t(d) * nblk + blk];
+  for (int32_t b = b0; b < b1; ++b) {
+    const uint32_t v = cnt[int64_t(b) * ns + d];
+    out[int64_t(b) * ns + d] = run;
+    run += v;
+  }
+}
+
 // A tile that starts inside a row R continues R's runs from the earlier
 // tiles that hold R: their end-of-tile slab masks are OR-ed (walking back
 // while the tiles stay inside R), kept where the tile's first row has
@@ -951,7 +989,7 @@ __global__ __launch_bounds__(kThreads) void k_seg_tile(
 // taken off the tile's pair count.
 __global__ __launch_bounds__(256) void k_seg_cont(const int32_t *__restrict__ rp, int32_t n,
                                                   const int2 *__restrict__ coord, int32_t ntiles,
-                                                  const uint32_t *__restrict__ lmask,
+                                                  int32_t ns, const uint32_t *__restrict__ lmask,
                                                   uint32_t *__restrict__ fmask,
                                                   uint32_t *__restrict__ pcnt) {
   for (int32_t b = blockIdx.x * 256 + threadIdx.x; b < ntiles; b += gridDim.x * 256) {
@@ -976,7 +1014,7 @@ __global__ __launch_bounds__(256) void k_seg_cont(const int32_t *__restrict__ rp
         uint32_t bits = m[k];
         while (bits) {
           const int d = k * 32 + __builtin_ctz(bits);
-          pcnt[int64_t(d) * ntiles + b] -= 1u;
+          pcnt[int64_t(b) * ns + d] -= 1u;
           bits &= bits - 1u;
         }
       }
@@ -1581,7 +1619,7 @@ struct Layout {
   int64_t *info;
   V *seg_val;
   typename Form<V>::Acc *seg_part;
-  uint32_t *seg_cnt, *seg_pcnt, *seg_fmask, *seg_lmask, *seg_scan;
+  uint32_t *seg_cnt, *seg_pcnt, *seg_bsum, *seg_fmask, *seg_lmask, *seg_scan;
 };
 
 // One layout function serves both measuring (ws == nullptr) and carving.
@@ -1640,6 +1678,7 @@ Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs, size_t *byte
     const int64_t cnt_n = kMaxSlabs * ntiles > wcnt ? kMaxSlabs * ntiles : wcnt;
     L.seg_cnt = c.take<uint32_t>(size_t(cnt_n));
     L.seg_pcnt = c.take<uint32_t>(size_t(kMaxSlabs * ntiles));
+    L.seg_bsum = c.take<uint32_t>(size_t(kMaxSlabs) * size_t((ntiles + kColTiles - 1) / kColTiles + 1));
     L.seg_fmask = c.take<uint32_t>(size_t(kMaskWords * ntiles));
     L.seg_lmask = c.take<uint32_t>(size_t(kMaskWords * ntiles));
     L.seg_coord = c.take<int2>(size_t(ntiles + 1));
@@ -1707,16 +1746,16 @@ void launch_spmv(int ipt, int32_t nb, hipStream_t s, const int32_t *rp, const in
 }
 
 // info[0] = P, info[1] = E0 (entries of slab 0), info[2] = P0 (its pairs);
-// prp[P] = nnz.  eoff / poff are the scanned per-(slab, tile) counts, so
-// their entry for (slab 1, tile 0) is slab 0's total.
+// prp[P] = nnz.  eoff / poff are the per-(tile, slab) offsets, so their
+// entry for (tile 0, slab 1) is slab 0's total.
 __global__ void k_seg_info(const uint32_t *__restrict__ eoff, const uint32_t *__restrict__ poff,
-                           int32_t ntiles, int64_t nnz, const int64_t *__restrict__ total,
+                           int64_t nnz, const int64_t *__restrict__ total,
                            int32_t *__restrict__ prp, int64_t *__restrict__ info) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     const int64_t P = *total;
     info[0] = P;
-    info[1] = eoff[ntiles];
-    info[2] = poff[ntiles];
+    info[1] = eoff[1];
+    info[2] = poff[1];
     if (P >= 0 && P <= nnz) prp[P] = int32_t(nnz);
   }
 }
@@ -1730,6 +1769,21 @@ struct SegInfo {
   int32_t nblk_w = 0, nwin = 0;
   bool relabelled = false;   // the count pass wrote the relabelled entries
 };
+
+// In-place slab-major offsets of a tile-by-tile count matrix (k_col_sums,
+// a scan of the block sums, k_col_offsets); *total gets the sum when given.
+pp_status col_offsets(uint32_t *cnt, int32_t ntiles, int32_t ns, uint32_t *bsum, uint32_t *scan_ws,
+                      int64_t *total, hipStream_t s) {
+  const int32_t nblk = (ntiles + kColTiles - 1) / kColTiles;
+  hipLaunchKernelGGL(k_col_sums, dim3(nblk), dim3(kThreads), 0, s, cnt, ntiles, ns, nblk, bsum);
+  PP_LAUNCHED("k_col_sums");
+  pp_status st = exscan_u32(bsum, bsum, int64_t(ns) * nblk, scan_ws, total, s);
+  if (st != PP_OK) return st;
+  hipLaunchKernelGGL(k_col_offsets, dim3(nblk), dim3(kThreads), 0, s, cnt, ntiles, ns, nblk, bsum,
+                     cnt);
+  PP_LAUNCHED("k_col_offsets");
+  return PP_OK;
+}
 
 // Segmented layout of the matrix (rp, col, val): see the kernels above.
 // With rl the matrix is the relabelled one, whose entries (col, val) the
@@ -1762,17 +1816,17 @@ pp_status build_segments(const Layout<V> &L, const int32_t *rp, int32_t *col, V 
                        L.seg_pcnt, L.seg_fmask, L.seg_lmask, nullptr, nullptr, nullptr, nullptr);
   }
   hipLaunchKernelGGL(k_seg_cont, dim3(grid_for(ntiles, 256, 4096)), dim3(256), 0, s, rp, n32,
-                     L.seg_coord, ntiles, L.seg_lmask, L.seg_fmask, L.seg_pcnt);
+                     L.seg_coord, ntiles, ns, L.seg_lmask, L.seg_fmask, L.seg_pcnt);
   PP_LAUNCHED("k_seg_tile (count)/k_seg_cont");
-  pp_status st = exscan_u32(L.seg_cnt, L.seg_cnt, int64_t(ns) * ntiles, L.seg_scan, nullptr, s);
+  pp_status st = col_offsets(L.seg_cnt, ntiles, ns, L.seg_bsum, L.seg_scan, nullptr, s);
   if (st != PP_OK) return st;
-  st = exscan_u32(L.seg_pcnt, L.seg_pcnt, int64_t(ns) * ntiles, L.seg_scan, L.total, s);
+  st = col_offsets(L.seg_pcnt, ntiles, ns, L.seg_bsum, L.seg_scan, L.total, s);
   if (st != PP_OK) return st;
   hipLaunchKernelGGL((k_seg_tile<V, true, false>), dim3(ntiles), dim3(kThreads), 0, s, rp, col,
                      val, n32, RelabelSrc{}, L.seg_coord, sbits, ns, dbits, ntiles, L.seg_cnt,
                      L.seg_pcnt, L.seg_fmask, nullptr, L.seg_col, L.seg_val, L.prp, L.pair_row);
-  hipLaunchKernelGGL(k_seg_info, dim3(1), dim3(64), 0, s, L.seg_cnt, L.seg_pcnt, ntiles, nnz,
-                     L.total, L.prp, L.info);
+  hipLaunchKernelGGL(k_seg_info, dim3(1), dim3(64), 0, s, L.seg_cnt, L.seg_pcnt, nnz, L.total,
+                     L.prp, L.info);
   PP_LAUNCHED("k_seg_tile (scatter)/k_seg_info");
   int64_t info[3] = {0, 0, 0};
   PP_HIP(hipMemcpyAsync(info, L.info, sizeof(info), hipMemcpyDeviceToHost, s));
