@@ -71,6 +71,9 @@ def lib():
                                    ctypes.c_double, _f64p, _f64p]
         L.ppo_step_rows.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _f64p,
                                     _f64p, ctypes.c_double, ctypes.c_double, _f64p]
+        L.ppo_pagerank_converge.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, ctypes.c_int32,
+                                            ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                            _f64p, _f64p, _f64p, _i32p]
         _lib = L
     return _lib
 
@@ -247,6 +250,32 @@ def pagerank(n: int, A_rp, A_col, A_val, r0, iters: int = 20, c: float = 0.85):
     _check(lib().ppo_pagerank(n, _p(A_rp, _i64p), _p(A_col, _i32p), _p(A_val, _f64p),
                               iters, c, _p(r, _f64p), _p(sums, _f64p)), "pagerank")
     return r, sums
+
+
+DANGLING = {"none": 0, "uniform": 1, "self": 2}
+
+
+def pagerank_converge(n: int, A_rp, A_col, A_val, r0, max_iters: int, tol: float,
+                      mode: str = "none", c: float = 0.85):
+    """K3 until the normalised L1 difference of successive iterates is
+    <= tol (or max_iters), with a dangling-vertex mode ("none", "uniform",
+    "self").  Returns (r, sums[0..k], deltas[0..k-1], k)."""
+    A_rp = np.ascontiguousarray(A_rp, dtype=np.int64)
+    A_col = np.ascontiguousarray(A_col, dtype=np.int32)
+    A_val = np.ascontiguousarray(A_val, dtype=np.float64)
+    r = np.array(r0, dtype=np.float64, copy=True)
+    sums = np.empty(max_iters + 1, np.float64)
+    deltas = np.empty(max(max_iters, 1), np.float64)
+    done = np.zeros(1, np.int32)
+    if A_col.size == 0:
+        A_col = np.zeros(1, np.int32)
+        A_val = np.zeros(1, np.float64)
+    _check(lib().ppo_pagerank_converge(n, _p(A_rp, _i64p), _p(A_col, _i32p), _p(A_val, _f64p),
+                                       max_iters, c, tol, DANGLING[mode], _p(r, _f64p),
+                                       _p(sums, _f64p), _p(deltas, _f64p), _p(done, _i32p)),
+           "pagerank_converge")
+    k = int(done[0])
+    return r, sums[:k + 1], deltas[:k], k
 
 
 def step_rows(n: int, rp, col, val, r, s: float, c: float = 0.85):

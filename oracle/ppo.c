@@ -25,6 +25,11 @@
  *                matrix and for A = 0; the sum(r) recurrence; the Perron
  *                vector of c*A.' + (1-c)/N from numpy.linalg.eig (Sec. IV.D)
  *   step_rows    equals one pagerank iteration on every row
+ *   pagerank_converge
+ *                Perron vector of the dense matrix of each dangling mode
+ *                (numpy.linalg.eig); sum(r) conserved by the two modes
+ *                that make A stochastic; closed forms of every iterate
+ *                and difference for a permutation matrix and for A = 0
  */
 #include "ppo.h"
 
@@ -511,6 +516,67 @@ int ppo_pagerank(int64_t n, const int64_t *A_rp, const int32_t *A_col, const dou
     for (int64_t j = 0; j < n; ++j) r[j] = csum_value(&y[j]) + t;
   }
   if (sums) sums[iters] = sum_r(n, r);
+  free(y);
+  return PPO_OK;
+}
+
+int ppo_pagerank_converge(int64_t n, const int64_t *A_rp, const int32_t *A_col,
+                          const double *A_val, int32_t max_iters, double c, double tol,
+                          int32_t mode, double *r, double *sums, double *deltas,
+                          int32_t *iters_done) {
+  if (n < 1 || max_iters < 0 || mode < PPO_DANGLING_NONE || mode > PPO_DANGLING_SELF || !A_rp ||
+      !r || !iters_done)
+    return PPO_EINVAL;
+  if (A_rp[n] > 0 && (!A_col || !A_val)) return PPO_EINVAL;
+  csum *acc = (csum *)malloc((size_t)n * sizeof(csum));
+  double *y = (double *)malloc((size_t)n * sizeof(double));
+  if (!acc || !y) {
+    free(acc);
+    free(y);
+    return PPO_ENOMEM;
+  }
+  double a = (1.0 - c) / (double)n;
+  double cn = c / (double)n;
+  double s = sum_r(n, r);
+  if (sums) sums[0] = s;
+  int32_t it = 0;
+  while (it < max_iters) {
+    /* Mass on dangling vertices: those whose row of A is empty. */
+    csum dm = {0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i)
+      if (A_rp[i + 1] == A_rp[i]) csum_add(&dm, r[i]);
+    /* The benchmark's step: the row vector c.*r times A, sums over i in
+     * ascending order.  Mode SELF gives every empty row i of A the entry
+     * A(i,i) = 1, taken at its place i in that order. */
+    for (int64_t j = 0; j < n; ++j) acc[j].s = acc[j].c = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      double cr = c * r[i];
+      if (mode == PPO_DANGLING_SELF && A_rp[i + 1] == A_rp[i]) csum_add(&acc[i], cr * 1.0);
+      for (int64_t q = A_rp[i]; q < A_rp[i + 1]; ++q) csum_add(&acc[A_col[q]], cr * A_val[q]);
+    }
+    /* Teleport (1-c)/N * sum(r); mode UNIFORM adds the dangling mass spread
+     * evenly, c/N * sum of r over dangling vertices. */
+    double t = a * s;
+    if (mode == PPO_DANGLING_UNIFORM) t = t + cn * csum_value(&dm);
+    for (int64_t j = 0; j < n; ++j) y[j] = csum_value(&acc[j]) + t;
+    double s1 = sum_r(n, y);
+    /* Normed sum of the differences between the two iterates, each divided
+     * by its own sum (the un-adjusted iteration loses mass every step). */
+    double delta = INFINITY;
+    if (s > 0.0 && s1 > 0.0) {
+      csum d = {0.0, 0.0};
+      for (int64_t j = 0; j < n; ++j) csum_add(&d, fabs(y[j] / s1 - r[j] / s));
+      delta = csum_value(&d);
+    }
+    for (int64_t j = 0; j < n; ++j) r[j] = y[j];
+    s = s1;
+    if (deltas) deltas[it] = delta;
+    ++it;
+    if (sums) sums[it] = s;
+    if (delta <= tol) break;
+  }
+  *iters_done = it;
+  free(acc);
   free(y);
   return PPO_OK;
 }

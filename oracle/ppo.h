@@ -79,6 +79,30 @@ int ppo_init_r(int64_t n, uint64_t seed, int32_t rhs, double *r);
 int ppo_pagerank(int64_t n, const int64_t *A_rp, const int32_t *A_col, const double *A_val,
                  int32_t iters, double c, double *r, double *sums);
 
+/* K3 run until a convergence test passes (Sec. IV.D remarks that real
+ * applications iterate until the normed sum of the differences between
+ * iterations is small), optionally with a term for dangling vertices (rows
+ * of A that are empty; Sec. IV.C/IV.D name the adjustments, Sec. V asks
+ * about a diagonal entry in empty rows):
+ *   PPO_DANGLING_NONE     the benchmark's iteration;
+ *   PPO_DANGLING_UNIFORM  a dangling vertex's damped mass c*r_i is spread
+ *                         evenly: the teleport becomes (1-c)/N*sum(r) +
+ *                         c/N*sum(r over dangling vertices);
+ *   PPO_DANGLING_SELF     every empty row i of A gets A(i,i) = 1.
+ * Iteration k computes y from r as in ppo_pagerank (plus the mode's term),
+ * delta_k = sum_j |y_j/sum(y) - r_j/sum(r)| (infinite if a sum is not
+ * positive), sets r = y, and stops after the first k with delta_k <= tol or
+ * after max_iters iterations.  *iters_done = iterations run; sums (max_iters
+ * + 1 entries, may be NULL) gets sum(r_k) for k = 0..iters_done, deltas
+ * (max_iters entries, may be NULL) gets delta_k. */
+#define PPO_DANGLING_NONE 0
+#define PPO_DANGLING_UNIFORM 1
+#define PPO_DANGLING_SELF 2
+int ppo_pagerank_converge(int64_t n, const int64_t *A_rp, const int32_t *A_col,
+                          const double *A_val, int32_t max_iters, double c, double tol,
+                          int32_t mode, double *r, double *sums, double *deltas,
+                          int32_t *iters_done);
+
 /* One damped step for a set of output entries, pull form: row q of the
  * given rows-of-A^T (entries rp[q]..rp[q+1], u ascending) yields
  * y[q] = sum_i (c*r_i)*val (i ascending, compensated) + ((1-c)/n)*s.  With rp = the

@@ -206,3 +206,131 @@ def test_pagerank_matches_extended_precision(ora, scale):
     err = float(np.abs(r.astype(np.longdouble) - x).sum() / np.abs(x).sum())
     assert err <= 1e-15
     assert abs(float(sums[-1] / x.sum()) - 1.0) <= 1e-15
+
+
+# ------------------------------------------------- run to convergence (Sec. IV.D)
+# The convergence test is the normed sum of the differences between two
+# iterates, each divided by its sum; dangling modes: "none" (the benchmark),
+# "uniform" (a dangling vertex spreads c*r_i evenly), "self" (A(i,i) = 1 in
+# every empty row of A, Sec. V).
+def mode_matrix(n, A, mode):
+    """Dense matrix whose leading eigenvector the converged r must be."""
+    d = (np.abs(A).sum(axis=1) == 0).astype(float)
+    if mode == "uniform":
+        A = A + np.outer(d, np.ones(n)) / n
+    elif mode == "self":
+        A = A + np.diag(d)
+    return C * A.T + (1 - C) / n
+
+
+@pytest.mark.parametrize("mode", ["none", "uniform", "self"])
+@pytest.mark.parametrize("scale", [6, 8])
+def test_converge_eigenvector(ora, scale, mode):
+    p, f = pipeline_matrix(ora, scale)
+    n = p.n
+    A = dense_A(n, f.A_rp, f.A_col, f.A_val)
+    assert (np.diff(f.A_rp) == 0).sum() > n // 10       # plenty of dangling vertices
+    w, V = np.linalg.eig(mode_matrix(n, A, mode))
+    k = int(np.argmax(w.real))
+    r1 = np.abs(V[:, k].real)
+    r1 /= r1.sum()
+    r, sums, deltas, done = ora.pagerank_converge(n, f.A_rp, f.A_col, f.A_val, ora.init_r(n, 1),
+                                                  max_iters=2000, tol=1e-13, mode=mode, c=C)
+    assert done < 2000 and deltas[-1] <= 1e-13 and (deltas[:-1] > 1e-13).all()
+    assert np.abs(r / r.sum() - r1).sum() <= 1e-10
+    if mode != "none":
+        assert abs(w[k].real - 1.0) <= 1e-12              # stochastic: eigenvalue 1
+
+
+@pytest.mark.parametrize("mode", ["uniform", "self"])
+def test_converge_stochastic_modes_keep_sum(ora, mode):
+    p, f = pipeline_matrix(ora, 12)
+    n = p.n
+    r, sums, deltas, done = ora.pagerank_converge(n, f.A_rp, f.A_col, f.A_val, ora.init_r(n, 5),
+                                                  max_iters=30, tol=-1.0, mode=mode, c=C)
+    assert done == 30
+    assert np.abs(sums / sums[0] - 1).max() <= 1e-13
+
+
+def test_converge_none_sum_recurrence(ora):
+    # Without an adjustment each step loses c * (mass on dangling vertices).
+    p, f = pipeline_matrix(ora, 11)
+    n = p.n
+    dangling = np.diff(f.A_rp) == 0
+    r = ora.init_r(n, 6)
+    for k in range(4):
+        r1, sums, _, done = ora.pagerank_converge(n, f.A_rp, f.A_col, f.A_val, r, max_iters=1,
+                                                  tol=-1.0, mode="none", c=C)
+        want = r.sum() - C * r[dangling].sum()
+        assert done == 1 and abs(sums[1] - want) <= 1e-13 * want
+        r = r1
+
+
+def test_converge_none_is_the_benchmark_iteration(ora):
+    # With a test that never passes, mode "none" runs exactly the fixed
+    # iterations of the benchmark's K3.
+    p, f = pipeline_matrix(ora, 10)
+    n = p.n
+    r0 = ora.init_r(n, 9)
+    want, wsums = ora.pagerank(n, f.A_rp, f.A_col, f.A_val, r0, iters=20, c=C)
+    r, sums, deltas, done = ora.pagerank_converge(n, f.A_rp, f.A_col, f.A_val, r0, max_iters=20,
+                                                  tol=-1.0, mode="none", c=C)
+    assert done == 20 and np.array_equal(r, want) and np.array_equal(sums, wsums)
+    r, sums, deltas, done = ora.pagerank_converge(n, f.A_rp, f.A_col, f.A_val, r0, max_iters=0,
+                                                  tol=1.0, mode="none", c=C)
+    assert done == 0 and np.array_equal(r, r0) and deltas.size == 0
+
+
+@pytest.mark.parametrize("mode", ["none", "uniform", "self"])
+def test_converge_closed_form_permutation(ora, mode):
+    # A permutation matrix has no empty row, so every mode is the same:
+    # r_k = c^k r0 P^k + (1 - c^k) s0/N, sum(r_k) = s0, and delta_k is the
+    # L1 norm of r_{k+1} - r_k over s0.  The run stops after the first k
+    # with delta_k <= tol.
+    n = 1000
+    perm = np.random.default_rng(6).permutation(n)
+    rp = np.arange(n + 1, dtype=np.int64)
+    col = perm.astype(np.int32)
+    val = np.ones(n)
+    r0 = ora.init_r(n, 12)
+    s0 = r0.sum()
+    xs, x = [r0], r0
+    for k in range(200):
+        y = np.empty(n)
+        y[perm] = x
+        x = y
+        xs.append(x)
+    rk = [C**k * xs[k] + (1 - C**k) * s0 / n for k in range(201)]
+    want_d = np.array([np.abs(rk[k + 1] - rk[k]).sum() / s0 for k in range(200)])
+    tol = float(np.sqrt(want_d[60] * want_d[61]))       # between two iterates, far from both
+    stop = int(np.argmax(want_d <= tol)) + 1
+    r, sums, deltas, done = ora.pagerank_converge(n, rp, col, val, r0, max_iters=200, tol=tol,
+                                                  mode=mode, c=C)
+    assert done == stop == 62
+    assert np.abs(deltas / want_d[:done] - 1).max() <= 1e-9
+    assert relL1(r, rk[done]) <= 1e-14
+    assert np.abs(sums / s0 - 1).max() <= 1e-14
+
+
+def test_converge_closed_form_zero_matrix(ora):
+    # A = 0: every vertex dangling.
+    n = 777
+    rp = np.zeros(n + 1, np.int64)
+    z32, z = np.zeros(0, np.int32), np.zeros(0)
+    r0 = ora.init_r(n, 13)
+    s0 = r0.sum()
+    d0 = np.abs(1.0 / n - r0 / s0).sum()
+    # none: r_k = (1-c)^k s0/N (uniform from the first step), so delta_0 is
+    # the distance of r0/s0 from uniform and delta_1 vanishes.
+    r, sums, deltas, done = ora.pagerank_converge(n, rp, z32, z, r0, 50, 1e-12, "none", C)
+    assert done == 2 and abs(deltas[0] / d0 - 1) <= 1e-12 and deltas[1] <= 1e-15
+    assert np.abs(r / ((1 - C)**2 * s0 / n) - 1).max() <= 1e-13
+    # uniform: all mass is respread, r_k = s0/N.
+    r, sums, deltas, done = ora.pagerank_converge(n, rp, z32, z, r0, 50, 1e-12, "uniform", C)
+    assert done == 2 and abs(deltas[0] / d0 - 1) <= 1e-12
+    assert np.abs(r / (s0 / n) - 1).max() <= 1e-13 and np.abs(sums / s0 - 1).max() <= 1e-14
+    # self: A = I, r_k = c^k r0 + (1 - c^k) s0/N, delta_k = c^k (1-c) d0.
+    r, sums, deltas, done = ora.pagerank_converge(n, rp, z32, z, r0, 30, -1.0, "self", C)
+    k = np.arange(30)
+    assert done == 30 and np.abs(deltas / (C**k * (1 - C) * d0) - 1).max() <= 1e-11
+    assert relL1(r, C**30 * r0 + (1 - C**30) * s0 / n) <= 1e-14
