@@ -45,6 +45,10 @@ def parse():
                     help="skip the batched-RHS form (S=22, 32 right-hand sides)")
     ap.add_argument("--batched-scale", type=int, default=22)
     ap.add_argument("--nrhs", type=int, default=32)
+    ap.add_argument("--no-converge", action="store_true",
+                    help="skip the run-to-convergence form (dangling modes uniform and self)")
+    ap.add_argument("--converge-tol", type=float, default=1e-6)
+    ap.add_argument("--converge-max-iters", type=int, default=300)
     ap.add_argument("--no-graphs", action="store_true",
                     help="skip the many-small-graphs form (512 graphs, S uniform on 8..14)")
     ap.add_argument("--ngraphs", type=int, default=512)
@@ -250,6 +254,39 @@ def graphs_form(args, pp, workloads, torch):
             "speedup_over_per_graph_calls": t_calls / t,
             "max_rel_l1_vs_per_graph_calls": err,
             "launch": "one persistent kernel, replayed from a hipGraph"}
+
+
+def converge_form(args, pp, workloads, torch, AT, d_out, r, ws, m, relabel, plain_ms):
+    """K3 run to a convergence test on the benchmark's matrix: for dangling
+    modes uniform and self, iterations until the normalised L1 difference
+    is <= tol, timed from pp_init_r to the end (HIP events, best of two
+    calls after one warm-up); rate = iterations * M / t like the K3 metric."""
+    n = AT.n
+    dt = pp.dtype_code(r.dtype)
+    out = {"workload": f"kron-s{args.scale}-{args.dtype}-converge", "tol": args.converge_tol,
+           "max_iters": args.converge_max_iters, "relabel": relabel,
+           "plain_iteration_ms": plain_ms}
+    for mode in ("uniform", "self"):
+        best = None
+        for rep in range(3):
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record()
+            pp.init_r(n, workloads.BASE_SEED, dt, out=r, ws=ws)
+            sums, deltas, k = pp.pagerank_converge(
+                AT, r, args.converge_max_iters, args.converge_tol, mode, d_out=d_out,
+                c=workloads.DAMPING, weights=d_out if relabel else None, ws=ws)
+            t1.record()
+            t1.synchronize()
+            ms = t0.elapsed_time(t1)
+            if rep > 0 and (best is None or ms < best[0]):
+                best = (ms, k, float(deltas[-1]) if k else None,
+                        float(abs(sums[-1] / sums[0] - 1)))
+        ms, k, last, drift = best
+        out[mode] = {"iterations": k, "ms": ms, "edges_per_s": k * m / (ms / 1e3) if k else 0.0,
+                     "ms_per_iteration": ms / k if k else None, "last_delta": last,
+                     "sum_r_rel_drift": drift}
+    return out
 
 
 def spmv_bytes(n: int, nnz: int, dtype: str) -> int:
@@ -487,6 +524,15 @@ def main():
             "f32_rel_l1_vs_f64_gpu": err,
         }
         del AT64, ws64
+
+    if not args.no_converge:
+        log("run to convergence")
+        if not args.no_tune and args.warmup >= 1:
+            pp.set_k3_config(*tuned["config"])
+        elif args.k3_config is None:
+            pp.set_k3_config()
+        out.setdefault("forms", {})["converge"] = converge_form(
+            args, pp, workloads, torch, AT, d_out, r, ws3, m, state["relabel"], spmv_avg_s * 1e3)
 
     if not args.no_batched:
         log("batched right-hand sides")

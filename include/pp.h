@@ -183,6 +183,41 @@ pp_status pp_pagerank(const pp_csr *AT, pp_dtype dt, int32_t nrhs, int32_t iters
                       const int32_t *order_weights, void *r, double *sums, void *ws,
                       size_t ws_bytes, void *stream);
 
+/* Dangling vertices (rows of A without entries, i.e. d_out == 0): the
+ * adjustment applied by pp_pagerank_converge (Sec. IV.C-D name such
+ * adjustments; Sec. V asks about a diagonal entry in empty rows). */
+typedef enum {
+  PP_DANGLING_NONE = 0,    /* the benchmark's iteration: sum(r) decays */
+  PP_DANGLING_UNIFORM = 1, /* a dangling vertex's damped mass c*r_i is spread
+                              evenly: teleport (1-c)/N*sum(r) + c/N*sum of r
+                              over dangling vertices */
+  PP_DANGLING_SELF = 2     /* every empty row i of A gets A(i,i) = 1 */
+} pp_dangling;
+
+/* K3 run until a convergence test passes (Sec. IV.D: applications iterate
+ * until the normed sum of the differences between iterations is small),
+ * single right-hand side.  Iteration k computes r_{k+1} from r_k as
+ * pp_pagerank does, plus the term of `mode`, then
+ *   delta_k = sum_j | r_{k+1,j} / sum(r_{k+1}) - r_{k,j} / sum(r_k) |
+ * (FP64; +infinity unless both sums are positive).  It stops after the first
+ * k with delta_k <= tol, or after max_iters iterations (tol < 0: never
+ * early).  r (device, n values of dt) is r_0 on entry and the last iterate
+ * on return; *iters_done (host) = iterations run.  sums (device, max_iters
+ * + 1 FP64, may be NULL) gets sum(r_k) for k = 0..*iters_done; deltas
+ * (device, max_iters FP64, may be NULL) gets delta_k.  d_out (device, n
+ * int32, pp_filter's out-degrees) marks the dangling vertices and is
+ * required unless mode is PP_DANGLING_NONE; order_weights as in
+ * pp_pagerank.  The workspace is pp_pagerank's for nrhs = 1.  The host
+ * reads a stop flag after every iteration, so the call synchronizes the
+ * stream once per iteration and returns with it idle.  In FP32 the
+ * differences bottom out near the rounding of the iterates (~1e-7), so
+ * useful tolerances start around 1e-6. */
+pp_status pp_pagerank_converge(const pp_csr *AT, pp_dtype dt, int32_t max_iters, double c,
+                               double tol, pp_dangling mode, const int32_t *d_out,
+                               const int32_t *order_weights, void *r, double *sums,
+                               double *deltas, int32_t *iters_done, void *ws, size_t ws_bytes,
+                               void *stream);
+
 /* K3 (Sec. IV.D) for a batch of independent small graphs in one persistent
  * launch: for every graph, r_0 as pp_init_r (right-hand side 0, the graph's
  * seed) followed by `iters` iterations as pp_pagerank, with r and the

@@ -1571,6 +1571,118 @@ __global__ __launch_bounds__(kWinThreads) void k_spmv_win(
   for (int i = tid; i < rows; i += kWinThreads) part[w0.x + i] = s_acc[i];
 }
 
+// ------------------------------------------------ run to a convergence test
+// Sec. IV.D notes that applications iterate until the normed sum of the
+// differences between iterations is small; Sec. IV.C-D and V name the
+// adjustments for dangling vertices (rows of A without entries).  An
+// iteration's launches give y = c * x A + t and S_y = sum(y) (fixed order).
+// One pass over x and y then finishes the step:
+//   mode SELF adds c * x_j to y_j for every dangling j (the entry A(j,j) = 1
+//   of an empty row), so the new sum is S_y + c * D_x, D_x the mass of x on
+//   dangling vertices (from the previous pass);
+//   block sums of |y_j / S_y - x_j / S_x| and of y over dangling vertices.
+// A one-workgroup finish adds them in a fixed order: delta (infinite unless
+// both sums are positive), the stop flag delta <= tol, sum(r) of the new
+// iterate, and the next teleport (1-c)/N * S_y, plus c/N * D_y in mode
+// UNIFORM (a dangling vertex's damped mass spread evenly).  r_0's S and D
+// come from a pass of their own.
+enum : int32_t { kDangNone = 0, kDangUniform = 1, kDangSelf = 2 };
+constexpr int kConvBlocks = 1024;
+
+struct ConvState {
+  double sx, sy, dx, delta, stop;
+};
+
+__global__ __launch_bounds__(256) void k_dflag(const int32_t *__restrict__ d_out,
+                                               const int32_t *__restrict__ order, int32_t n,
+                                               uint8_t *__restrict__ dflag) {
+  for (int32_t p = blockIdx.x * 256 + threadIdx.x; p < n; p += gridDim.x * 256)
+    dflag[p] = d_out[order ? order[p] : p] == 0 ? 1 : 0;
+}
+
+// sum(r_0) and its mass on dangling vertices (dflag may be null).
+template <typename V>
+__global__ __launch_bounds__(kThreads) void k_conv_init(const V *__restrict__ x, int64_t n,
+                                                        const uint8_t *__restrict__ dflag,
+                                                        double *__restrict__ part) {
+  __shared__ double sh[4];
+  double a = 0.0, d = 0.0;
+  for (int64_t j = blockIdx.x * int64_t(kThreads) + threadIdx.x; j < n;
+       j += int64_t(gridDim.x) * kThreads) {
+    const double v = double(x[j]);
+    a += v;
+    if (dflag && dflag[j]) d += v;
+  }
+  const double ba = block_sum256(a, sh);
+  const double bd = block_sum256(d, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = ba;
+    part[kConvBlocks + blockIdx.x] = bd;
+  }
+}
+
+template <typename V>
+__global__ __launch_bounds__(kThreads) void k_conv_step(const V *__restrict__ x, V *__restrict__ y,
+                                                        int64_t n, const uint8_t *__restrict__ dflag,
+                                                        double self_c, const ConvState *__restrict__ st,
+                                                        double *__restrict__ part) {
+  __shared__ double sh[4];
+  const double sx = st->sx, sy = st->sy + self_c * st->dx;
+  const bool ok = sx > 0.0 && sy > 0.0;
+  double a = 0.0, d = 0.0;
+  for (int64_t j = blockIdx.x * int64_t(kThreads) + threadIdx.x; j < n;
+       j += int64_t(gridDim.x) * kThreads) {
+    double v = double(y[j]);
+    const bool dang = dflag && dflag[j];
+    if (dang && self_c != 0.0) {
+      const V nv = V(v + self_c * double(x[j]));
+      y[j] = nv;
+      v = double(nv);
+    }
+    if (ok) a += fabs(v / sy - double(x[j]) / sx);
+    if (dang) d += v;
+  }
+  const double ba = block_sum256(a, sh);
+  const double bd = block_sum256(d, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = ba;
+    part[kConvBlocks + blockIdx.x] = bd;
+  }
+}
+
+// first: the pass was k_conv_init over r_0 (part = sums, not differences).
+__global__ __launch_bounds__(kThreads) void k_conv_fin(const double *__restrict__ part,
+                                                       int32_t nblk, double w, double cn,
+                                                       int32_t uniform, double self_c, double tol,
+                                                       int32_t first, ConvState *st,
+                                                       double *tele_out, double *sum_out,
+                                                       double *delta_out) {
+  __shared__ double sh[4];
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += kThreads) {
+    a += part[k];
+    b += part[kConvBlocks + k];
+  }
+  const double sa = block_sum256(a, sh);
+  const double dn = block_sum256(b, sh);
+  if (threadIdx.x == 0) {
+    double s;
+    if (first) {
+      s = sa;
+    } else {
+      s = st->sy + self_c * st->dx;
+      const double delta = (st->sx > 0.0 && s > 0.0) ? sa : INFINITY;
+      st->delta = delta;
+      st->stop = delta <= tol ? 1.0 : 0.0;
+      if (delta_out) *delta_out = delta;
+    }
+    st->sx = s;
+    st->dx = dn;
+    *tele_out = uniform ? w * s + cn * dn : w * s;
+    if (sum_out) *sum_out = s;
+  }
+}
+
 // Optional event pairs around each SpMV launch (benchmark instrumentation).
 struct Timing {
   bool on = false;
@@ -1619,6 +1731,10 @@ struct Layout {
   int64_t *info;
   V *seg_val;
   typename Form<V>::Acc *seg_part;
+  // run to a convergence test
+  uint8_t *dflag;
+  double *conv_part;
+  ConvState *conv;
   uint32_t *seg_cnt, *seg_pcnt, *seg_bsum, *seg_fmask, *seg_lmask, *seg_scan;
 };
 
@@ -1664,6 +1780,11 @@ Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs, size_t *byte
     L.val2 = rl ? reinterpret_cast<V *>(rl + colb) : nullptr;
   }
   L.x2 = c.take<V>(size_t(n) * nrhs);
+  if (nrhs == 1) {
+    L.dflag = c.take<uint8_t>(size_t(n));
+    L.conv_part = c.take<double>(2 * kConvBlocks);
+    L.conv = c.take<ConvState>(1);
+  }
   if (nrhs == 1) {
     const int64_t z = nnz_cap > 0 ? nnz_cap : 1;
     const int64_t ntiles = (n + nnz_cap + kSegTile - 1) / kSegTile + 1;
@@ -1907,10 +2028,20 @@ pp_status build_segments(const Layout<V> &L, const int32_t *rp, int32_t *col, V 
   return PP_OK;
 }
 
+// Options of a run to a convergence test (see k_conv_sums); null: the
+// benchmark's fixed iteration count.
+struct ConvOpts {
+  int32_t mode;
+  double tol;
+  const int32_t *d_out;
+  double *deltas;
+  int32_t *iters_done;   // host
+};
+
 template <typename V>
 pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
                        const int32_t *weights, V *r, double *sums, void *ws, size_t ws_bytes,
-                       hipStream_t s) {
+                       hipStream_t s, const ConvOpts *cv = nullptr) {
   const int64_t n = AT0.n, nnz = AT0.nnz;
   if (ws_bytes < ws_bytes_t<V>(n, nnz, nrhs))
     return fail(PP_EWORKSPACE, "pagerank workspace too small");
@@ -2011,14 +2142,32 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
     hipLaunchKernelGGL(k_sum0_mm<V>, dim3(G0), dim3(kThreads), 0, s, x0, n, k, lanes, kSumChunk,
                        L.part, L.counter, w, sums, L.tele);
   PP_LAUNCHED("k_sum0");
+  const int cblk = grid_for(n, kThreads * 16, kConvBlocks);
+  const uint8_t *dflag = nullptr;
+  if (cv) {
+    if (cv->mode != kDangNone) {
+      hipLaunchKernelGGL(k_dflag, dim3(gN), dim3(256), 0, s, cv->d_out,
+                         weights ? L.order : nullptr, n32, L.dflag);
+      dflag = L.dflag;
+    }
+    hipLaunchKernelGGL(k_conv_init<V>, dim3(cblk), dim3(kThreads), 0, s, x0, n, dflag,
+                       L.conv_part);
+    hipLaunchKernelGGL(k_conv_fin, dim3(1), dim3(kThreads), 0, s, L.conv_part, cblk, w,
+                       c / double(n), int32_t(cv->mode == kDangUniform), 0.0, cv->tol, 1, L.conv,
+                       L.tele, sums, nullptr);
+    PP_LAUNCHED("k_dflag/k_conv_init/k_conv_fin (r_0)");
+  }
 
   g_timing.used = 0;
+  int32_t done = 0;
   for (int32_t it = 0; it < iters; ++it) {
     const V *x = (it & 1) ? L.y : x0;
     V *yv = (it & 1) ? x0 : L.y;
     const double *t_in = L.tele + 64 * (it & 1);
     double *t_out = L.tele + 64 * ((it + 1) & 1);
-    double *s_out = sums ? sums + int64_t(it + 1) * k : nullptr;
+    // With a convergence test the iteration's sum(y) goes to the test's state.
+    double *s_out = cv ? &L.conv->sy : sums ? sums + int64_t(it + 1) * k : nullptr;
+    done = it + 1;
     if ((st = timed_begin(s)) != PP_OK) return st;
     if (si.P > 0) {
       if (si.nblk_w > 0)
@@ -2039,32 +2188,49 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
                          t_out);
       if ((st = timed_end(s)) != PP_OK) return st;
       PP_LAUNCHED("k_spmv raw/k_fix_raw/k_seg_combine");
-      continue;
+    } else {
+      if (k == 1)
+        launch_spmv<V, false>(ipt, nb, s, rp, col, val, x, yv, n32, L.coord, c, t_in, L.blk_ysum,
+                              L.blk_carry, L.blk_head, nullptr);
+      else
+        launch_spmm<V>(lanes, nb, s, rp, col, val, x, yv, n32, k, L.coord, c, t_in, L.blk_ysum,
+                       L.blk_carry, L.blk_head);
+      if ((st = timed_end(s)) != PP_OK) return st;
+      if (k == 1)
+        hipLaunchKernelGGL(k_finish<V>, dim3(G), dim3(kThreads), 0, s, yv, nb, L.coord, L.closes,
+                           L.carry_row, L.blk_carry, L.blk_head, L.blk_ysum, c, t_in, L.part,
+                           L.counter, w, s_out, t_out);
+      else
+        hipLaunchKernelGGL(k_finish_mm<V>, dim3(G), dim3(kThreads), 0, s, yv, nb, k, lanes,
+                           L.coord, L.closes, L.carry_row, L.blk_carry, L.blk_head, L.blk_ysum,
+                           c, t_in, L.part, L.counter, w, s_out, t_out);
+      PP_LAUNCHED("k_spmv/k_finish");
     }
-    if (k == 1)
-      launch_spmv<V, false>(ipt, nb, s, rp, col, val, x, yv, n32, L.coord, c, t_in, L.blk_ysum,
-                            L.blk_carry, L.blk_head, nullptr);
-    else
-      launch_spmm<V>(lanes, nb, s, rp, col, val, x, yv, n32, k, L.coord, c, t_in, L.blk_ysum,
-                     L.blk_carry, L.blk_head);
-    if ((st = timed_end(s)) != PP_OK) return st;
-    if (k == 1)
-      hipLaunchKernelGGL(k_finish<V>, dim3(G), dim3(kThreads), 0, s, yv, nb, L.coord, L.closes,
-                         L.carry_row, L.blk_carry, L.blk_head, L.blk_ysum, c, t_in, L.part,
-                         L.counter, w, s_out, t_out);
-    else
-      hipLaunchKernelGGL(k_finish_mm<V>, dim3(G), dim3(kThreads), 0, s, yv, nb, k, lanes, L.coord,
-                         L.closes, L.carry_row, L.blk_carry, L.blk_head, L.blk_ysum, c, t_in,
-                         L.part, L.counter, w, s_out, t_out);
-    PP_LAUNCHED("k_spmv/k_finish");
+    if (cv) {
+      // The step's dangling term, difference, sum and teleport; the host
+      // reads the stop flag (one stream synchronisation per iteration).
+      const double self_c = cv->mode == kDangSelf ? c : 0.0;
+      hipLaunchKernelGGL(k_conv_step<V>, dim3(cblk), dim3(kThreads), 0, s, x, yv, n, dflag,
+                         self_c, L.conv, L.conv_part);
+      hipLaunchKernelGGL(k_conv_fin, dim3(1), dim3(kThreads), 0, s, L.conv_part, cblk, w,
+                         c / double(n), int32_t(cv->mode == kDangUniform), self_c, cv->tol, 0,
+                         L.conv, t_out, sums ? sums + it + 1 : nullptr,
+                         cv->deltas ? cv->deltas + it : nullptr);
+      PP_LAUNCHED("k_conv_step/k_conv_fin");
+      double stop = 0.0;
+      PP_HIP(hipMemcpyAsync(&stop, &L.conv->stop, sizeof(double), hipMemcpyDeviceToHost, s));
+      PP_HIP(hipStreamSynchronize(s));
+      if (stop != 0.0) break;
+    }
   }
-  const V *last = (iters & 1) ? L.y : x0;
+  if (cv) *cv->iters_done = done;
+  const V *last = (done & 1) ? L.y : x0;
   if (weights) {
     hipLaunchKernelGGL(k_permute_out<V>, dim3(gNK), dim3(256), 0, s, last, L.order, n32, k, r);
     PP_LAUNCHED("k_permute_out");
     return PP_OK;
   }
-  if (iters & 1) return copy_bytes(r, L.y, size_t(n) * k * sizeof(V), s);
+  if (done & 1) return copy_bytes(r, L.y, size_t(n) * k * sizeof(V), s);
   return PP_OK;
 }
 
@@ -2146,6 +2312,18 @@ pp_status launch_pagerank(const pp_csr &AT, pp_dtype dt, int32_t nrhs, int32_t i
                                 ws_bytes, s);
   return run_pagerank<float>(AT, nrhs, iters, c, weights, static_cast<float *>(r), sums, ws,
                              ws_bytes, s);
+}
+
+pp_status launch_pagerank_converge(const pp_csr &AT, pp_dtype dt, int32_t max_iters, double c,
+                                   double tol, int32_t mode, const int32_t *d_out,
+                                   const int32_t *weights, void *r, double *sums, double *deltas,
+                                   int32_t *iters_done, void *ws, size_t ws_bytes, hipStream_t s) {
+  const ConvOpts cv{mode, tol, d_out, deltas, iters_done};
+  if (dt == PP_F64)
+    return run_pagerank<double>(AT, 1, max_iters, c, weights, static_cast<double *>(r), sums, ws,
+                                ws_bytes, s, &cv);
+  return run_pagerank<float>(AT, 1, max_iters, c, weights, static_cast<float *>(r), sums, ws,
+                             ws_bytes, s, &cv);
 }
 
 }  // namespace pp

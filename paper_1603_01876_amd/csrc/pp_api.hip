@@ -172,6 +172,31 @@ pp_status pp_pagerank(const pp_csr *AT, pp_dtype dt, int32_t nrhs, int32_t iters
                          as_stream(stream));
 }
 
+pp_status pp_pagerank_converge(const pp_csr *AT, pp_dtype dt, int32_t max_iters, double c,
+                               double tol, pp_dangling mode, const int32_t *d_out,
+                               const int32_t *order_weights, void *r, double *sums,
+                               double *deltas, int32_t *iters_done, void *ws, size_t ws_bytes,
+                               void *stream) {
+  if (!AT || !AT->row_ptr || !r || !iters_done)
+    return fail(PP_EINVAL, "pp_pagerank_converge: null argument");
+  *iters_done = 0;
+  if (dt != PP_F64 && dt != PP_F32) return fail(PP_EINVAL, "pp_pagerank_converge: dtype %d", int(dt));
+  if (AT->n < 1 || AT->n > (int64_t(1) << 30)) return fail(PP_ERANGE, "pp_pagerank_converge: n = %lld", (long long)AT->n);
+  if (AT->nnz < 0 || AT->nnz > AT->cap) return fail(PP_EINVAL, "pp_pagerank_converge: nnz %lld, cap %lld", (long long)AT->nnz, (long long)AT->cap);
+  if (AT->n + AT->nnz > kI32Max) return fail(PP_ERANGE, "pp_pagerank_converge: n + nnz >= 2^31");
+  if (AT->nnz > 0 && (!AT->col || !AT->val)) return fail(PP_EINVAL, "pp_pagerank_converge: null col/val");
+  if (max_iters < 0) return fail(PP_EINVAL, "pp_pagerank_converge: max_iters %d", max_iters);
+  if (!(c >= 0.0 && c <= 1.0)) return fail(PP_EINVAL, "pp_pagerank_converge: c = %g", c);
+  if (mode != PP_DANGLING_NONE && mode != PP_DANGLING_UNIFORM && mode != PP_DANGLING_SELF)
+    return fail(PP_EINVAL, "pp_pagerank_converge: dangling mode %d", int(mode));
+  if (mode != PP_DANGLING_NONE && !d_out)
+    return fail(PP_EINVAL, "pp_pagerank_converge: dangling mode %d needs d_out", int(mode));
+  const size_t need = pagerank_ws_bytes(AT->n, AT->nnz, dt, 1);
+  if (!ws || ws_bytes < need) return fail(PP_EWORKSPACE, "pp_pagerank_converge: workspace needs %zu bytes", need);
+  return launch_pagerank_converge(*AT, dt, max_iters, c, tol, int32_t(mode), d_out, order_weights,
+                                  r, sums, deltas, iters_done, ws, ws_bytes, as_stream(stream));
+}
+
 int64_t pp_graphs_max_n(pp_dtype dt) {
   if (dt != PP_F64 && dt != PP_F32) return 0;
   return graphs_max_n(dt);

@@ -228,6 +228,10 @@ pp_status launch_init_r(int64_t n, int32_t nrhs, uint64_t seed, pp_dtype dt, voi
 pp_status launch_pagerank(const pp_csr &AT, pp_dtype dt, int32_t nrhs, int32_t iters, double c,
                           const int32_t *weights, void *r, double *sums, void *ws, size_t ws_bytes,
                           hipStream_t s);
+pp_status launch_pagerank_converge(const pp_csr &AT, pp_dtype dt, int32_t max_iters, double c,
+                                   double tol, int32_t mode, const int32_t *d_out,
+                                   const int32_t *weights, void *r, double *sums, double *deltas,
+                                   int32_t *iters_done, void *ws, size_t ws_bytes, hipStream_t s);
 // K3 batch of small graphs (k3_graphs.hip)
 size_t graphs_ws_bytes(int32_t ngraphs);
 int64_t graphs_max_n(pp_dtype dt);

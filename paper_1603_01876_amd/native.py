@@ -76,6 +76,9 @@ SIGNATURES = {
                                    _VP, _VP, _VP, _SZ, _VP]),
     "pp_pagerank_graphs": (ctypes.c_int, [_I32, _VP, _I64, ctypes.c_int, _I32, _D, _I32, _VP,
                                           _SZ, _VP]),
+    "pp_pagerank_converge": (ctypes.c_int, [ctypes.POINTER(_Csr), ctypes.c_int, _I32, _D, _D,
+                                            ctypes.c_int, _VP, _VP, _VP, _VP, _VP,
+                                            ctypes.POINTER(_I32), _VP, _SZ, _VP]),
     "pp_graphs_max_n": (_I64, [ctypes.c_int]),
     "pp_set_k3_config": (ctypes.c_int, [ctypes.c_void_p]),
     "pp_get_k3_config": (ctypes.c_int, [ctypes.c_void_p]),
@@ -267,6 +270,34 @@ def pagerank(AT: CSR, r, iters: int = 20, c: float = 0.85, sums=True, ws=None, w
     _check(lib().pp_pagerank(ctypes.byref(cs), dt, nrhs, iters, c, _ptr(weights), _ptr(r),
                              _ptr(sums), _ptr(ws), ws.numel(), _stream()), "pp_pagerank")
     return sums
+
+
+DANGLING = {"none": 0, "uniform": 1, "self": 2}
+
+
+def pagerank_converge(AT: CSR, r, max_iters: int, tol: float, mode: str = "none", d_out=None,
+                      c: float = 0.85, weights=None, ws=None):
+    """K3 until the normalised L1 difference between iterates is <= tol (or
+    max_iters), with a dangling-vertex mode ("none", "uniform", "self"; the
+    last two need d_out).  Iterates r in place; returns (sums, deltas,
+    iterations): FP64 tensors of sum(r_k), k = 0..iterations, and of the
+    differences, k = 0..iterations-1."""
+    dt = dtype_code(r.dtype)
+    if dt != AT.dtype:
+        raise PPError(PP_EINVAL, "pagerank_converge", "r and matrix values differ in dtype")
+    if mode not in DANGLING:
+        raise PPError(PP_EINVAL, "pagerank_converge", f"dangling mode {mode!r}")
+    sums = torch.empty(max_iters + 1, dtype=torch.float64, device=r.device)
+    deltas = torch.empty(max(max_iters, 1), dtype=torch.float64, device=r.device)
+    ws = _ws(workspace_bytes(K3, AT.n, AT.nnz, dt, 1), ws, r.device)
+    done = ctypes.c_int32(0)
+    cs = AT._c()
+    _check(lib().pp_pagerank_converge(ctypes.byref(cs), dt, max_iters, c, tol, DANGLING[mode],
+                                      _ptr(d_out), _ptr(weights), _ptr(r), _ptr(sums),
+                                      _ptr(deltas), ctypes.byref(done), _ptr(ws), ws.numel(),
+                                      _stream()), "pp_pagerank_converge")
+    k = int(done.value)
+    return sums[:k + 1], deltas[:k], k
 
 
 def graphs_max_n(dtype="f32") -> int:

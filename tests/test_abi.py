@@ -122,6 +122,29 @@ def test_pagerank_rejects_bad_args():
                          None) == native.PP_ERANGE
 
 
+def test_pagerank_converge_rejects_bad_args():
+    L = native.lib()
+    c = native._Csr(1000, 10, 100, 8, 16, 24)
+    done = ctypes.c_int32(-5)
+
+    def call(csr=c, dt=0, iters=100, damp=0.85, tol=1e-9, mode=0, d_out=None, r=8, ws=64,
+             wsb=1 << 30, done_p=ctypes.byref(done)):
+        return L.pp_pagerank_converge(ctypes.byref(csr), dt, iters, damp, tol, mode, d_out, None,
+                                      r, None, None, done_p, ws, wsb, None)
+
+    assert call(iters=-1) == native.PP_EINVAL and done.value == 0
+    assert call(damp=-0.1) == native.PP_EINVAL
+    assert call(dt=7) == native.PP_EINVAL
+    assert call(mode=3) == native.PP_EINVAL
+    assert call(mode=1) == native.PP_EINVAL          # uniform needs d_out
+    assert call(mode=2) == native.PP_EINVAL          # self needs d_out
+    assert call(r=None) == native.PP_EINVAL
+    assert call(done_p=None) == native.PP_EINVAL
+    assert call(wsb=10) == native.PP_EWORKSPACE
+    assert call(csr=native._Csr(1000, 200, 100, 8, 16, 24)) == native.PP_EINVAL
+    assert call(csr=native._Csr(1 << 30, (1 << 31) - 10, 1 << 31, 8, 16, 24)) == native.PP_ERANGE
+
+
 def test_init_r_rejects_bad_args():
     L = native.lib()
     assert L.pp_init_r(0, 1, 1, 0, 8, 64, 1 << 20, None) == native.PP_ERANGE
