@@ -61,6 +61,7 @@ def lib():
         L.ppo_generate_range.argtypes = [ctypes.POINTER(_Kron), ctypes.c_int64, ctypes.c_int64,
                                          ctypes.c_int, _i64p, _i64p]
         L.ppo_sort.argtypes = [ctypes.c_int32, ctypes.c_int64, _i64p, _i64p, _i64p, _i64p]
+        L.ppo_sort_uv.argtypes = [ctypes.c_int32, ctypes.c_int64, _i64p, _i64p, _i64p, _i64p]
         L.ppo_filter.argtypes = [ctypes.c_int32, ctypes.c_int64, _i64p, _i64p, _i64p, _i64p,
                                  _i64p, _i32p, _f64p, _i64p, _i32p, _f64p, _i64p]
         L.ppo_filter_rows.argtypes = [ctypes.c_int32, ctypes.c_int64, _i64p, _i64p, _i64p,
@@ -153,6 +154,17 @@ def sort(scale: int, u, v):
     vo = np.empty_like(v)
     _check(lib().ppo_sort(scale, u.size, _p(u, _i64p), _p(v, _i64p),
                           _p(uo, _i64p), _p(vo, _i64p)), "sort")
+    return uo, vo
+
+
+def sort_uv(scale: int, u, v):
+    """K1 variant: edges ordered by (u, v)."""
+    u = np.ascontiguousarray(u, dtype=np.int64)
+    v = np.ascontiguousarray(v, dtype=np.int64)
+    uo = np.empty_like(u)
+    vo = np.empty_like(v)
+    _check(lib().ppo_sort_uv(scale, u.size, _p(u, _i64p), _p(v, _i64p),
+                             _p(uo, _i64p), _p(vo, _i64p)), "sort_uv")
     return uo, vo
 
 

@@ -16,6 +16,7 @@
  *   generate     range/count; per-level quadrant frequencies; independence
  *                of e-ranges; label multiset invariant under the bijection
  *   sort         numpy stable argsort by u (a library routine)
+ *   sort_uv      numpy lexsort by (u, v) (a library routine)
  *   filter       dense brute force written from Sec. IV.C's Matlab lines;
  *                special graphs (complete, star, permutation) => A = 0;
  *                invariants (sum of counts, rows summing to one)
@@ -200,6 +201,29 @@ int ppo_sort(int32_t scale, int64_t m, const int64_t *u, const int64_t *v,
     v_out[pos] = v[e];
   }
   free(next);
+  return PPO_OK;
+}
+
+static int cmp_i64(const void *a, const void *b);
+
+/* K1 variant (Sec. V asks whether the end vertices should be sorted too):
+ * edges ordered by (u, v).  Edges are bucketed by u (counting sort), and
+ * each bucket's end vertices are sorted in place; equal (u, v) pairs are
+ * identical records, so the order among them needs no rule. */
+int ppo_sort_uv(int32_t scale, int64_t m, const int64_t *u, const int64_t *v,
+                int64_t *u_out, int64_t *v_out) {
+  int st = ppo_sort(scale, m, u, v, u_out, v_out);
+  if (st != PPO_OK) return st;
+  int64_t n = (int64_t)1 << scale;
+  for (int64_t e = 0; e < m; ++e)
+    if (v[e] < 0 || v[e] >= n) return PPO_EINVAL;
+  int64_t e0 = 0;
+  while (e0 < m) {
+    int64_t e1 = e0;
+    while (e1 < m && u_out[e1] == u_out[e0]) ++e1;
+    qsort(v_out + e0, (size_t)(e1 - e0), sizeof(int64_t), cmp_i64);
+    e0 = e1;
+  }
   return PPO_OK;
 }
 

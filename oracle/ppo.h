@@ -47,6 +47,12 @@ int ppo_generate_range(const ppo_kron *p, int64_t e0, int64_t count, int permute
 int ppo_sort(int32_t scale, int64_t m, const int64_t *u, const int64_t *v,
              int64_t *u_out, int64_t *v_out);
 
+/* K1 variant: edges ordered by u, then v (Sec. V's question whether the
+ * end vertices should be sorted too).  Same arguments as ppo_sort; v must
+ * also lie in [0, 2^scale). */
+int ppo_sort_uv(int32_t scale, int64_t m, const int64_t *u, const int64_t *v,
+                int64_t *u_out, int64_t *v_out);
+
 /* K2 (Sec. IV.C): A = sparse(u,v,1,N,N) with counts; d_in = column sums;
  * drop columns with d_in == max(d_in) and with d_in == 1 (both from the
  * original d_in); d_out = row sums of what is left; non-empty rows divided

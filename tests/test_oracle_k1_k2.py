@@ -38,6 +38,31 @@ def test_sort_generated_graph(ora):
     assert np.array_equal(vo, v[order])
 
 
+@pytest.mark.parametrize("scale,m", [(1, 0), (1, 1), (1, 37), (4, 1000), (10, 16384), (12, 12345)])
+def test_sort_uv_matches_lexsort(ora, scale, m):
+    # K1 with end vertices sorted too: numpy lexsort by (u, v).
+    rng = np.random.default_rng(scale * 1000 + m + 1)
+    n = 1 << scale
+    u = rng.integers(0, n, m).astype(np.int64)
+    v = rng.integers(0, n, m).astype(np.int64)
+    uo, vo = ora.sort_uv(scale, u, v)
+    order = np.lexsort((v, u))
+    assert np.array_equal(uo, u[order]) and np.array_equal(vo, v[order])
+
+
+def test_sort_uv_feeds_the_same_filter(ora):
+    # K2 builds its matrix from the multiset of edges, so the order of the
+    # end vertices within a start vertex cannot change its output.
+    p = kron(11)
+    u, v = ora.generate(p)
+    a = ora.filter(11, *ora.sort(11, u, v))
+    b = ora.filter(11, *ora.sort_uv(11, u, v))
+    for name in ("AT_rp", "AT_col", "AT_val", "A_rp", "A_col", "A_val", "d_in", "d_out"):
+        assert np.array_equal(getattr(a, name), getattr(b, name)), name
+    with pytest.raises(RuntimeError):
+        ora.sort_uv(3, np.array([1], np.int64), np.array([8], np.int64))
+
+
 def test_sort_rejects_out_of_range(ora):
     with pytest.raises(RuntimeError):
         ora.sort(3, np.array([8], np.int64), np.array([0], np.int64))
