@@ -125,6 +125,14 @@ pp_status pp_generate(const pp_kron_params *p, int64_t *u, int64_t *v, void *str
 pp_status pp_sort(int32_t scale, int64_t m, const int64_t *u, const int64_t *v,
                   int64_t *u_out, int64_t *v_out, void *ws, size_t ws_bytes, void *stream);
 
+/* K1 variant (Sec. V asks whether the end vertices should be sorted too):
+ * the edges ordered by u, then by v.  Arguments, workspace and errors as
+ * pp_sort; both labels are checked against [0, 2^scale) and u_out, v_out
+ * must be distinct from the inputs and from each other.  Runs two stable
+ * radix sorts (by v, then by u). */
+pp_status pp_sort_uv(int32_t scale, int64_t m, const int64_t *u, const int64_t *v, int64_t *u_out,
+                     int64_t *v_out, void *ws, size_t ws_bytes, void *stream);
+
 /* K2 (Sec. IV.C): from the K1 output (edges sorted by u), forms the count
  * matrix A(u,v) = number of edges u->v, the in-degrees d_in = column sums
  * of counts, removes every column whose in-degree equals the maximum and

@@ -108,6 +108,35 @@ pp_status pp_sort(int32_t scale, int64_t m, const int64_t *u, const int64_t *v, 
                     rest_bytes, int64_t(1) << scale, false, flag, s, true);
 }
 
+pp_status pp_sort_uv(int32_t scale, int64_t m, const int64_t *u, const int64_t *v,
+                     int64_t *u_out, int64_t *v_out, void *ws, size_t ws_bytes, void *stream) {
+  if (scale < 1 || scale > 30) return fail(PP_ERANGE, "pp_sort_uv: scale %d", scale);
+  if (m < 0) return fail(PP_EINVAL, "pp_sort_uv: m < 0");
+  if (m > kI32Max) return fail(PP_ERANGE, "pp_sort_uv: m = %lld >= 2^31", (long long)m);
+  if (m == 0) return PP_OK;
+  if (!u || !v || !u_out || !v_out) return fail(PP_EINVAL, "pp_sort_uv: null array");
+  if (u_out == u || u_out == v || v_out == u || v_out == v || u_out == v_out)
+    return fail(PP_EINVAL, "pp_sort_uv: output aliases input");
+  const size_t need = radix_ws_bytes(m, 31) + 512;
+  if (!ws || ws_bytes < need) return fail(PP_EWORKSPACE, "pp_sort_uv: workspace needs %zu bytes", need);
+  hipStream_t s = as_stream(stream);
+  Carve c(ws);
+  uint32_t *flag = c.take<uint32_t>(1);
+  void *rest = reinterpret_cast<void *>(c.base + c.used);
+  const size_t rest_bytes = ws_bytes - c.used;
+  pp_status st = fill_i32(reinterpret_cast<int32_t *>(flag), 1, 0, s);
+  if (st != PP_OK) return st;
+  // LSD order: stably by v (both labels range-checked), into the outputs
+  // (v in v_out, u in u_out); then stably by u, in place.  The second sort
+  // takes at least two passes (9 key bits; the extra ones are zero), so no
+  // pass reads the arrays it writes.
+  st = radix_sort(RadixIn{nullptr, v, u}, RadixOut{nullptr, v_out, u_out}, m, scale, rest,
+                  rest_bytes, int64_t(1) << scale, false, flag, s, true);
+  if (st != PP_OK) return st;
+  return radix_sort(RadixIn{nullptr, u_out, v_out}, RadixOut{nullptr, u_out, v_out}, m,
+                    scale < 9 ? 9 : scale, rest, rest_bytes, 0, false, flag, s, false);
+}
+
 pp_status pp_filter(int32_t scale, int64_t m, const int64_t *u, const int64_t *v, pp_dtype dt,
                     pp_csr *AT, int32_t *d_in, int32_t *d_out, void *ws, size_t ws_bytes,
                     void *stream) {

@@ -67,6 +67,7 @@ SIGNATURES = {
     "pp_workspace_bytes": (_SZ, [ctypes.c_int, _I64, _I64, ctypes.c_int, _I32]),
     "pp_generate": (ctypes.c_int, [ctypes.POINTER(_Kron), _VP, _VP, _VP]),
     "pp_sort": (ctypes.c_int, [_I32, _I64, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    "pp_sort_uv": (ctypes.c_int, [_I32, _I64, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "pp_filter": (ctypes.c_int, [_I32, _I64, _VP, _VP, ctypes.c_int, ctypes.POINTER(_Csr),
                                  _VP, _VP, _VP, _SZ, _VP]),
     "pp_transpose": (ctypes.c_int, [ctypes.POINTER(_Csr), ctypes.c_int, ctypes.POINTER(_Csr),
@@ -161,6 +162,19 @@ def sort(scale: int, u, v, u_out=None, v_out=None, ws=None):
     ws = _ws(nbytes, ws, u.device)
     _check(lib().pp_sort(scale, m, _ptr(u), _ptr(v), _ptr(u_out), _ptr(v_out), _ptr(ws),
                          ws.numel(), _stream()), "pp_sort")
+    return u_out, v_out
+
+
+def sort_uv(scale: int, u, v, u_out=None, v_out=None, ws=None):
+    """K1 variant: edges ordered by (u, v).  Returns (u_out, v_out)."""
+    m = u.numel()
+    if u_out is None:
+        u_out = torch.empty_like(u)
+    if v_out is None:
+        v_out = torch.empty_like(v)
+    ws = _ws(workspace_bytes(K1, 1 << scale, m), ws, u.device)
+    _check(lib().pp_sort_uv(scale, m, _ptr(u), _ptr(v), _ptr(u_out), _ptr(v_out), _ptr(ws),
+                            ws.numel(), _stream()), "pp_sort_uv")
     return u_out, v_out
 
 

@@ -86,6 +86,16 @@ def test_sort_rejects_bad_args():
     assert L.pp_sort(10, 0, None, None, None, None, None, 0, None) == native.PP_OK
 
 
+def test_sort_uv_rejects_bad_args():
+    L = native.lib()
+    assert L.pp_sort_uv(31, 10, 8, 8, 16, 16, 8, 1 << 20, None) == native.PP_ERANGE
+    assert L.pp_sort_uv(10, -1, 8, 16, 24, 32, 8, 1 << 20, None) == native.PP_EINVAL
+    assert L.pp_sort_uv(10, 100, 8, 16, 8, 24, 64, 1 << 20, None) == native.PP_EINVAL   # alias
+    assert L.pp_sort_uv(10, 100, 8, 16, 24, 24, 64, 1 << 20, None) == native.PP_EINVAL  # outputs
+    assert L.pp_sort_uv(10, 100, 8, 16, 24, 32, 64, 100, None) == native.PP_EWORKSPACE
+    assert L.pp_sort_uv(10, 0, None, None, None, None, None, 0, None) == native.PP_OK
+
+
 def test_filter_rejects_bad_args():
     L = native.lib()
     c = native._Csr(1 << 10, 0, 1 << 14, 8, 16, 24)

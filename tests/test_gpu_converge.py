@@ -180,3 +180,26 @@ def test_converge_is_reproducible():
     assert runs[0][3] == runs[1][3]
     for a, b in zip(runs[0][:3], runs[1][:3]):
         assert a.tobytes() == b.tobytes()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_converge_eigenvector_check(mode):
+    # Sec. IV.D's own validation, GPU against an eigensolver (no oracle in
+    # between): the converged r / sum(r) is the leading eigenvector of
+    # c*A.' + (1-c)/N, with the mode's dangling adjustment in A.
+    f = kron_matrix(10)
+    n = f.n
+    A = np.zeros((n, n))
+    A[np.repeat(np.arange(n), np.diff(f.A_rp)), f.A_col] = f.A_val
+    d = (np.diff(f.A_rp) == 0).astype(float)
+    if mode == "uniform":
+        A = A + np.outer(d, np.ones(n)) / n
+    elif mode == "self":
+        A = A + np.diag(d)
+    w, V = np.linalg.eig(C * A.T + (1 - C) / n)
+    r1 = np.abs(V[:, int(np.argmax(w.real))].real)
+    r1 /= r1.sum()
+    AT = pp.CSR.from_arrays(n, f.AT_rp, f.AT_col, f.AT_val, "f64")
+    r, sums, deltas, k = gpu_run(AT, n, "f64", 2000, 1e-13, mode, f.d_out, weights=f.d_out)
+    assert k < 2000
+    assert np.abs(r / r.sum() - r1).sum() <= 1e-10

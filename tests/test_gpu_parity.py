@@ -115,6 +115,50 @@ def test_sort_rejects_out_of_range():
     assert e.value.status == pp.PP_EINVAL
 
 
+# ----------------------------------------------------- K1 ordered by (u, v)
+@pytest.mark.parametrize("scale", [1, 3, 8, 9, 10, 16, 20])
+def test_sort_uv_pipeline_matches_oracle(scale):
+    # 8 and 9: the second radix sort is forced to two passes below 9 bits
+    s = spec(scale)
+    u, v = pp.generate(s)
+    us, vs = pp.sort_uv(scale, u, v)
+    ou, ov = oracle.generate(okron(s))
+    ous, ovs = oracle.sort_uv(scale, ou, ov)
+    assert np.array_equal(host(us), ous)
+    assert np.array_equal(host(vs), ovs)
+
+
+@pytest.mark.parametrize("scale,m,skew", [(12, 12345, False), (3, 1, False), (3, 4097, True),
+                                          (16, 100003, True), (24, 70001, False)])
+def test_sort_uv_random_inputs(scale, m, skew):
+    rng = np.random.default_rng(scale * 11 + m)
+    n = 1 << scale
+    u = np.minimum(rng.geometric(0.01, m) - 1, n - 1) if skew else rng.integers(0, n, m)
+    v = rng.integers(0, n, m)
+    us, vs = pp.sort_uv(scale, dev(u), dev(v))
+    ous, ovs = oracle.sort_uv(scale, u, v)
+    assert np.array_equal(host(us), ous) and np.array_equal(host(vs), ovs)
+
+
+def test_sort_uv_feeds_the_same_filter():
+    s = spec(14)
+    u, v = pp.generate(s)
+    (A, ain, aout), (B, bin_, bout) = (pp.filter(14, *srt(14, u, v), "f64")
+                                       for srt in (pp.sort, pp.sort_uv))
+    z = A.nnz
+    assert B.nnz == z and torch.equal(A.row_ptr, B.row_ptr)
+    assert torch.equal(A.col[:z], B.col[:z]) and torch.equal(A.val[:z], B.val[:z])
+    assert torch.equal(ain, bin_) and torch.equal(aout, bout)
+
+
+def test_sort_uv_rejects_out_of_range():
+    u = dev(np.array([0, 1, 2, 3]))
+    v = dev(np.array([0, 1, 1024, 3]))
+    with pytest.raises(pp.PPError) as e:
+        pp.sort_uv(10, u, v)
+    assert e.value.status == pp.PP_EINVAL
+
+
 # ----------------------------------------------------------------------- K2
 def check_filter(scale, u_sorted, v_sorted, dtype):
     f = oracle.filter(scale, u_sorted, v_sorted)
