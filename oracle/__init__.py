@@ -62,6 +62,10 @@ def lib():
                                          ctypes.c_int, _i64p, _i64p]
         L.ppo_sort.argtypes = [ctypes.c_int32, ctypes.c_int64, _i64p, _i64p, _i64p, _i64p]
         L.ppo_sort_uv.argtypes = [ctypes.c_int32, ctypes.c_int64, _i64p, _i64p, _i64p, _i64p]
+        L.ppo_tsv_format.argtypes = [ctypes.c_int64, _i64p, _i64p, ctypes.c_char_p,
+                                     ctypes.c_int64, _i64p]
+        L.ppo_tsv_parse.argtypes = [ctypes.c_int32, ctypes.c_char_p, ctypes.c_int64,
+                                    ctypes.c_int64, _i64p, _i64p, _i64p]
         L.ppo_filter.argtypes = [ctypes.c_int32, ctypes.c_int64, _i64p, _i64p, _i64p, _i64p,
                                  _i64p, _i32p, _f64p, _i64p, _i32p, _f64p, _i64p]
         L.ppo_filter_rows.argtypes = [ctypes.c_int32, ctypes.c_int64, _i64p, _i64p, _i64p,
@@ -166,6 +170,30 @@ def sort_uv(scale: int, u, v):
     _check(lib().ppo_sort_uv(scale, u.size, _p(u, _i64p), _p(v, _i64p),
                              _p(uo, _i64p), _p(vo, _i64p)), "sort_uv")
     return uo, vo
+
+
+def tsv_format(u, v) -> bytes:
+    """Edges as text lines "u<TAB>v<LF>"."""
+    u = np.ascontiguousarray(u, dtype=np.int64)
+    v = np.ascontiguousarray(v, dtype=np.int64)
+    cap = 22 * u.size + 1
+    buf = ctypes.create_string_buffer(cap)
+    nb = np.zeros(1, np.int64)
+    _check(lib().ppo_tsv_format(u.size, _p(u, _i64p), _p(v, _i64p), buf, cap, _p(nb, _i64p)),
+           "tsv_format")
+    return buf.raw[:int(nb[0])]
+
+
+def tsv_parse(scale: int, text: bytes, cap: int | None = None):
+    """Edges back from text; raises on malformed text or labels >= 2^scale."""
+    cap = len(text) // 4 + 1 if cap is None else cap
+    u = np.empty(max(cap, 1), np.int64)
+    v = np.empty(max(cap, 1), np.int64)
+    m = np.zeros(1, np.int64)
+    _check(lib().ppo_tsv_parse(scale, text, len(text), cap, _p(u, _i64p), _p(v, _i64p),
+                               _p(m, _i64p)), "tsv_parse")
+    k = int(m[0])
+    return u[:k].copy(), v[:k].copy()
 
 
 # --------------------------------------------------------------------------

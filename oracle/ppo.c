@@ -17,6 +17,9 @@
  *                of e-ranges; label multiset invariant under the bijection
  *   sort         numpy stable argsort by u (a library routine)
  *   sort_uv      numpy lexsort by (u, v) (a library routine)
+ *   tsv_format   Python's own decimal formatting of the same edges
+ *   tsv_parse    round trip; Python's int() on each field; rejects each
+ *                malformed line of a list
  *   filter       dense brute force written from Sec. IV.C's Matlab lines;
  *                special graphs (complete, star, permutation) => A = 0;
  *                invariants (sum of counts, rows summing to one)
@@ -35,6 +38,7 @@
 #include "ppo.h"
 
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -224,6 +228,65 @@ int ppo_sort_uv(int32_t scale, int64_t m, const int64_t *u, const int64_t *v,
     qsort(v_out + e0, (size_t)(e1 - e0), sizeof(int64_t), cmp_i64);
     e0 = e1;
   }
+  return PPO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Edge files, Sec. IV.A-C: one edge per line, "u<TAB>v<LF>", decimal.        */
+/* ------------------------------------------------------------------------ */
+int ppo_tsv_format(int64_t m, const int64_t *u, const int64_t *v, char *text, int64_t cap,
+                   int64_t *nbytes) {
+  if (m < 0 || cap < 0 || !nbytes || (m > 0 && (!u || !v || !text))) return PPO_EINVAL;
+  int64_t pos = 0;
+  char line[64];
+  for (int64_t e = 0; e < m; ++e) {
+    if (u[e] < 0 || v[e] < 0) return PPO_EINVAL;
+    int len = snprintf(line, sizeof line, "%lld\t%lld\n", (long long)u[e], (long long)v[e]);
+    if (len < 0 || pos + len > cap) return PPO_EINVAL;
+    memcpy(text + pos, line, (size_t)len);
+    pos += len;
+  }
+  *nbytes = pos;
+  return PPO_OK;
+}
+
+/* Accepted text: lines of one or more decimal digits, a tab, one or more
+ * decimal digits, each line ended by a newline except that the last line
+ * may end at the end of the text.  Labels must lie in [0, 2^scale).
+ * Anything else (empty lines, signs, spaces, other characters, more than
+ * cap lines) is an error. */
+int ppo_tsv_parse(int32_t scale, const char *text, int64_t nbytes, int64_t cap, int64_t *u,
+                  int64_t *v, int64_t *m) {
+  if (scale < 1 || scale > 30 || nbytes < 0 || cap < 0 || !m || (nbytes > 0 && !text))
+    return PPO_EINVAL;
+  int64_t n = (int64_t)1 << scale, count = 0, pos = 0;
+  while (pos < nbytes) {
+    int64_t val[2];
+    for (int f = 0; f < 2; ++f) {
+      int64_t x = 0;
+      int digits = 0;
+      while (pos < nbytes && text[pos] >= '0' && text[pos] <= '9') {
+        x = x * 10 + (text[pos] - '0');
+        if (x >= n) return PPO_EINVAL;
+        ++digits;
+        ++pos;
+      }
+      if (digits == 0) return PPO_EINVAL;
+      char want = f == 0 ? '\t' : '\n';
+      if (pos < nbytes) {
+        if (text[pos] != want) return PPO_EINVAL;
+        ++pos;
+      } else if (f == 0) {
+        return PPO_EINVAL;
+      }
+      val[f] = x;
+    }
+    if (count >= cap || !u || !v) return PPO_EINVAL;
+    u[count] = val[0];
+    v[count] = val[1];
+    ++count;
+  }
+  *m = count;
   return PPO_OK;
 }
 

@@ -74,6 +74,16 @@ int ppo_filter_rows(int32_t scale, int64_t m, const int64_t *u, const int64_t *v
                     int64_t *out_rp, int32_t *out_col, double *out_val, int64_t out_cap,
                     int64_t *out_din, int64_t *out_dout, int64_t *mx, int64_t *nnz);
 
+/* Edge files (Sec. IV.A-C): text with one edge per line, the two labels in
+ * decimal separated by a tab, each line ended by a newline.  format writes
+ * the m edges into text (cap bytes) and sets *nbytes; parse reads them back
+ * (the last newline may be missing), checking every label against
+ * [0, 2^scale), and sets *m (at most cap edges). */
+int ppo_tsv_format(int64_t m, const int64_t *u, const int64_t *v, char *text, int64_t cap,
+                   int64_t *nbytes);
+int ppo_tsv_parse(int32_t scale, const char *text, int64_t nbytes, int64_t cap, int64_t *u,
+                  int64_t *v, int64_t *m);
+
 /* K3 init (Sec. IV.D): r_i = k_i / sum(k) with k_i the top 24 bits of a
  * Philox draw; rhs selects an independent vector. */
 int ppo_init_r(int64_t n, uint64_t seed, int32_t rhs, double *r);
