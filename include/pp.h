@@ -53,7 +53,9 @@ typedef enum {
   PP_K2 = 2,
   PP_K3 = 3,
   PP_K3_GRAPHS = 4, /* pp_pagerank_graphs; the m argument is the number of graphs */
-  PP_K2_ROWFORM = 5 /* pp_transpose; the m argument is the number of stored entries */
+  PP_K2_ROWFORM = 5, /* pp_transpose; the m argument is the number of stored entries */
+  PP_TSV_FORMAT = 6, /* pp_tsv_format; m = edges, nrhs = number of parts (files) */
+  PP_TSV_PARSE = 7   /* pp_tsv_parse; m = bytes of text */
 } pp_kernel;
 
 /* Kronecker generator parameters [host] (Sec. IV.A): N = 2^scale vertices,
@@ -158,6 +160,45 @@ pp_status pp_filter(int32_t scale, int64_t m, const int64_t *u, const int64_t *v
  * pp_workspace_bytes(PP_K2_ROWFORM, n, AT->nnz, dt, 1). */
 pp_status pp_transpose(const pp_csr *AT, pp_dtype dt, pp_csr *A, void *ws, size_t ws_bytes,
                        void *stream);
+
+/* Edge files (Sec. IV.A-C): text with one edge per line, the two labels as
+ * decimal strings separated by a tab, a newline after each edge; the number
+ * of files is free.  K0 writes such files, K1 reads them and writes the
+ * sorted edges the same way, K2 reads those.
+ *
+ * pp_tsv_format: the m edges (u, v: device int64, labels in [0, 2^scale))
+ * as text into `text` (device, cap bytes; at most 22 bytes per edge).  The
+ * lines are cut into nsplit parts of nearly equal edge counts (part k =
+ * lines [m*k/nsplit, m*(k+1)/nsplit)); split (host, nsplit + 1 entries)
+ * receives the byte offset of each part, split[nsplit] = total bytes.
+ * PP_EINVAL for a label out of range or text longer than cap.  Synchronizes
+ * the stream.  Workspace: pp_workspace_bytes(PP_TSV_FORMAT, 0, m, dt,
+ * nsplit).
+ *
+ * pp_tsv_parse: the edges of `text` (device, nbytes, 16-byte aligned) into
+ * u, v (device, cap entries); *m (host) = edges read.  Every line must be
+ * digits, a tab, digits (the last newline may be missing), labels in
+ * [0, 2^scale); anything else, or more than cap lines, is PP_EINVAL (u and v
+ * then hold partial results).  Synchronizes the stream.  Workspace:
+ * pp_workspace_bytes(PP_TSV_PARSE, 0, nbytes, dt, 1).
+ *
+ * pp_write_text_files: writes text[split[k], split[k+1]) (device) to file
+ * "<prefix>.<k>" (k with five digits) for k < nfiles, through pinned host
+ * staging buffers (allocated and freed by the call, 128 MiB); with sync
+ * the files are flushed to storage (fsync) before the call returns.
+ * pp_read_text_files: reads files "<prefix>.0" .. ".<nfiles-1>" back to
+ * back into text (device, cap bytes); *nbytes (host) = total.  Both return
+ * PP_EINVAL with the system's message for a file that cannot be opened,
+ * read or written, and leave the stream idle. */
+pp_status pp_tsv_format(int32_t scale, int64_t m, const int64_t *u, const int64_t *v, char *text,
+                        int64_t cap, int32_t nsplit, int64_t *split, void *ws, size_t ws_bytes,
+                        void *stream);
+pp_status pp_tsv_parse(int32_t scale, const char *text, int64_t nbytes, int64_t cap, int64_t *u,
+                       int64_t *v, int64_t *m, void *ws, size_t ws_bytes, void *stream);
+pp_status pp_write_text_files(const char *prefix, int32_t nfiles, const char *text,
+                              const int64_t *split, int32_t sync, void *stream);
+pp_status pp_read_text_files(const char *prefix, int32_t nfiles, char *text, int64_t cap,
+                             int64_t *nbytes, void *stream);
 
 /* K3 initial vector (Sec. IV.D, r = rand(1,N); r = r./norm(r,1)): for each
  * right-hand side j < nrhs, k_ij = top 24 bits of word 0 of Philox4x32-10

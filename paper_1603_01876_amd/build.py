@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpp.so")
 SOURCES = ["pp_api.hip", "pp_util.hip", "k0_generate.hip", "k1_radix.hip", "k2_filter.hip",
-           "k2_transpose.hip", "k3_pagerank.hip", "k3_graphs.hip"]
+           "k2_transpose.hip", "k3_pagerank.hip", "k3_graphs.hip", "pp_files.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

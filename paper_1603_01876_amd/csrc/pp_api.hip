@@ -61,6 +61,12 @@ const char *pp_strerror(pp_status st) {
 const char *pp_last_error(void) { return g_last_error; }
 
 size_t pp_workspace_bytes(pp_kernel k, int64_t n, int64_t m, pp_dtype dt, int32_t nrhs) {
+  // The edge-file codec sizes by edges or bytes only (n and dt unused).
+  if (k == PP_TSV_FORMAT) {
+    if (m < 0 || m > kI32Max || nrhs < 1 || nrhs > (1 << 20)) return size_t(-1);
+    return tsv_format_ws_bytes(m, nrhs);
+  }
+  if (k == PP_TSV_PARSE) return m < 0 ? size_t(-1) : tsv_parse_ws_bytes(m);
   if (n < 1 || n > (int64_t(1) << 30) || m < 0 || m > kI32Max) return size_t(-1);
   if (dt != PP_F64 && dt != PP_F32) return size_t(-1);
   switch (k) {
@@ -75,6 +81,8 @@ size_t pp_workspace_bytes(pp_kernel k, int64_t n, int64_t m, pp_dtype dt, int32_
       return graphs_ws_bytes(int32_t(m));
     case PP_K2_ROWFORM:
       return transpose_ws_bytes(n, m);
+    default:
+      break;
   }
   return size_t(-1);
 }
@@ -135,6 +143,49 @@ pp_status pp_sort_uv(int32_t scale, int64_t m, const int64_t *u, const int64_t *
   if (st != PP_OK) return st;
   return radix_sort(RadixIn{nullptr, u_out, v_out}, RadixOut{nullptr, u_out, v_out}, m,
                     scale < 9 ? 9 : scale, rest, rest_bytes, 0, false, flag, s, false);
+}
+
+pp_status pp_tsv_format(int32_t scale, int64_t m, const int64_t *u, const int64_t *v, char *text,
+                        int64_t cap, int32_t nsplit, int64_t *split, void *ws, size_t ws_bytes,
+                        void *stream) {
+  if (scale < 1 || scale > 30) return fail(PP_ERANGE, "pp_tsv_format: scale %d", scale);
+  if (m < 0 || m > kI32Max) return fail(PP_ERANGE, "pp_tsv_format: m = %lld", (long long)m);
+  if (nsplit < 1 || nsplit > (1 << 20)) return fail(PP_EINVAL, "pp_tsv_format: nsplit %d", nsplit);
+  if (!split || cap < 0 || (m > 0 && (!u || !v || !text)))
+    return fail(PP_EINVAL, "pp_tsv_format: null argument");
+  const size_t need = tsv_format_ws_bytes(m, nsplit);
+  if (!ws || ws_bytes < need) return fail(PP_EWORKSPACE, "pp_tsv_format: workspace needs %zu bytes", need);
+  return launch_tsv_format(scale, m, u, v, text, cap, nsplit, split, ws, ws_bytes, as_stream(stream));
+}
+
+pp_status pp_tsv_parse(int32_t scale, const char *text, int64_t nbytes, int64_t cap, int64_t *u,
+                       int64_t *v, int64_t *m, void *ws, size_t ws_bytes, void *stream) {
+  if (!m) return fail(PP_EINVAL, "pp_tsv_parse: null m");
+  *m = 0;
+  if (scale < 1 || scale > 30) return fail(PP_ERANGE, "pp_tsv_parse: scale %d", scale);
+  if (nbytes < 0 || cap < 0) return fail(PP_EINVAL, "pp_tsv_parse: negative size");
+  if (nbytes > 0 && !text) return fail(PP_EINVAL, "pp_tsv_parse: null text");
+  if (reinterpret_cast<uintptr_t>(text) % 16 != 0)
+    return fail(PP_EINVAL, "pp_tsv_parse: text must be 16-byte aligned");
+  const size_t need = tsv_parse_ws_bytes(nbytes);
+  if (!ws || ws_bytes < need) return fail(PP_EWORKSPACE, "pp_tsv_parse: workspace needs %zu bytes", need);
+  return launch_tsv_parse(scale, text, nbytes, cap, u, v, m, ws, ws_bytes, as_stream(stream));
+}
+
+pp_status pp_write_text_files(const char *prefix, int32_t nfiles, const char *text,
+                              const int64_t *split, int32_t sync, void *stream) {
+  if (!prefix || !split) return fail(PP_EINVAL, "pp_write_text_files: null argument");
+  if (nfiles < 1 || nfiles > 99999) return fail(PP_EINVAL, "pp_write_text_files: nfiles %d", nfiles);
+  if (split[nfiles] > split[0] && !text) return fail(PP_EINVAL, "pp_write_text_files: null text");
+  return write_text_files(prefix, nfiles, text, split, sync, as_stream(stream));
+}
+
+pp_status pp_read_text_files(const char *prefix, int32_t nfiles, char *text, int64_t cap,
+                             int64_t *nbytes, void *stream) {
+  if (!prefix || !nbytes) return fail(PP_EINVAL, "pp_read_text_files: null argument");
+  if (nfiles < 1 || nfiles > 99999) return fail(PP_EINVAL, "pp_read_text_files: nfiles %d", nfiles);
+  if (cap > 0 && !text) return fail(PP_EINVAL, "pp_read_text_files: null text");
+  return read_text_files(prefix, nfiles, text, cap, nbytes, as_stream(stream));
 }
 
 pp_status pp_filter(int32_t scale, int64_t m, const int64_t *u, const int64_t *v, pp_dtype dt,

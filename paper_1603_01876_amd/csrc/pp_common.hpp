@@ -232,6 +232,19 @@ pp_status launch_pagerank_converge(const pp_csr &AT, pp_dtype dt, int32_t max_it
                                    double tol, int32_t mode, const int32_t *d_out,
                                    const int32_t *weights, void *r, double *sums, double *deltas,
                                    int32_t *iters_done, void *ws, size_t ws_bytes, hipStream_t s);
+// Edge files (pp_files.hip)
+size_t tsv_format_ws_bytes(int64_t m, int32_t nsplit);
+size_t tsv_parse_ws_bytes(int64_t nbytes);
+pp_status launch_tsv_format(int32_t scale, int64_t m, const int64_t *u, const int64_t *v,
+                            char *text, int64_t cap, int32_t nsplit, int64_t *split_host,
+                            void *ws, size_t ws_bytes, hipStream_t s);
+pp_status launch_tsv_parse(int32_t scale, const char *text, int64_t nbytes, int64_t cap,
+                           int64_t *u, int64_t *v, int64_t *m_out, void *ws, size_t ws_bytes,
+                           hipStream_t s);
+pp_status write_text_files(const char *prefix, int32_t nfiles, const char *text,
+                           const int64_t *split, int32_t sync, hipStream_t s);
+pp_status read_text_files(const char *prefix, int32_t nfiles, char *text, int64_t cap,
+                          int64_t *nbytes, hipStream_t s);
 // K3 batch of small graphs (k3_graphs.hip)
 size_t graphs_ws_bytes(int32_t ngraphs);
 int64_t graphs_max_n(pp_dtype dt);

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libpp.so")
 
 PP_OK, PP_EINVAL, PP_ERANGE, PP_EWORKSPACE, PP_EHIP = range(5)
 F64, F32 = 0, 1
-K0, K1, K2, K3, K3_GRAPHS, K2_ROWFORM = range(6)
+K0, K1, K2, K3, K3_GRAPHS, K2_ROWFORM, TSV_FORMAT, TSV_PARSE = range(8)
 
 _TORCH = {F64: torch.float64, F32: torch.float32}
 _NAMES = {"f64": F64, "f32": F32, F64: F64, F32: F32,
@@ -68,6 +68,13 @@ SIGNATURES = {
     "pp_generate": (ctypes.c_int, [ctypes.POINTER(_Kron), _VP, _VP, _VP]),
     "pp_sort": (ctypes.c_int, [_I32, _I64, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "pp_sort_uv": (ctypes.c_int, [_I32, _I64, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    "pp_tsv_format": (ctypes.c_int, [_I32, _I64, _VP, _VP, _VP, _I64, _I32, _VP, _VP, _SZ,
+                                     _VP]),
+    "pp_tsv_parse": (ctypes.c_int, [_I32, _VP, _I64, _I64, _VP, _VP, ctypes.POINTER(_I64), _VP,
+                                    _SZ, _VP]),
+    "pp_write_text_files": (ctypes.c_int, [ctypes.c_char_p, _I32, _VP, _VP, _I32, _VP]),
+    "pp_read_text_files": (ctypes.c_int, [ctypes.c_char_p, _I32, _VP, _I64,
+                                          ctypes.POINTER(_I64), _VP]),
     "pp_filter": (ctypes.c_int, [_I32, _I64, _VP, _VP, ctypes.c_int, ctypes.POINTER(_Csr),
                                  _VP, _VP, _VP, _SZ, _VP]),
     "pp_transpose": (ctypes.c_int, [ctypes.POINTER(_Csr), ctypes.c_int, ctypes.POINTER(_Csr),
@@ -176,6 +183,57 @@ def sort_uv(scale: int, u, v, u_out=None, v_out=None, ws=None):
     _check(lib().pp_sort_uv(scale, m, _ptr(u), _ptr(v), _ptr(u_out), _ptr(v_out), _ptr(ws),
                             ws.numel(), _stream()), "pp_sort_uv")
     return u_out, v_out
+
+
+# ------------------------------------------------------------- edge files
+def tsv_format(scale: int, u, v, nsplit: int = 1, text=None, ws=None):
+    """Edges as text lines "u<TAB>v<LF>" on the GPU.  Returns (text, split):
+    a uint8 device tensor (capacity 22 bytes per edge unless given) and the
+    nsplit + 1 byte offsets of nsplit parts of nearly equal edge counts
+    (split[-1] = bytes of text)."""
+    m = u.numel()
+    if text is None:
+        text = torch.empty(max(22 * m, 16), dtype=torch.uint8, device=u.device)
+    split = (ctypes.c_int64 * (nsplit + 1))()
+    ws = _ws(workspace_bytes(TSV_FORMAT, 0, m, F64, nsplit), ws, u.device)
+    _check(lib().pp_tsv_format(scale, m, _ptr(u), _ptr(v), _ptr(text), text.numel(), nsplit,
+                               ctypes.cast(split, ctypes.c_void_p), _ptr(ws), ws.numel(),
+                               _stream()), "pp_tsv_format")
+    return text, [int(x) for x in split]
+
+
+def tsv_parse(scale: int, text, nbytes: int, cap: int | None = None, u=None, v=None, ws=None):
+    """Edges back from text (a uint8 device tensor, first nbytes bytes).
+    Returns (u, v) cut to the edges read."""
+    dev = text.device
+    if cap is None:
+        cap = u.numel() if u is not None else nbytes // 4 + 1
+    if u is None:
+        u = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
+    if v is None:
+        v = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
+    m = ctypes.c_int64(0)
+    ws = _ws(workspace_bytes(TSV_PARSE, 0, nbytes, F64), ws, dev)
+    _check(lib().pp_tsv_parse(scale, _ptr(text), nbytes, cap, _ptr(u), _ptr(v), ctypes.byref(m),
+                              _ptr(ws), ws.numel(), _stream()), "pp_tsv_parse")
+    return u[:m.value], v[:m.value]
+
+
+def write_text_files(prefix: str, text, split, sync: bool = True) -> None:
+    """File k = text[split[k]:split[k+1]] for k < len(split) - 1."""
+    arr = (ctypes.c_int64 * len(split))(*split)
+    _check(lib().pp_write_text_files(prefix.encode(), len(split) - 1, _ptr(text),
+                                     ctypes.cast(arr, ctypes.c_void_p), int(sync), _stream()),
+           "pp_write_text_files")
+
+
+def read_text_files(prefix: str, nfiles: int, text) -> int:
+    """Reads the files back to back into text (uint8 device tensor); returns
+    the number of bytes."""
+    nb = ctypes.c_int64(0)
+    _check(lib().pp_read_text_files(prefix.encode(), nfiles, _ptr(text), text.numel(),
+                                    ctypes.byref(nb), _stream()), "pp_read_text_files")
+    return int(nb.value)
 
 
 # ---------------------------------------------------------------------- K2

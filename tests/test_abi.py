@@ -155,6 +155,36 @@ def test_pagerank_converge_rejects_bad_args():
     assert call(csr=native._Csr(1 << 30, (1 << 31) - 10, 1 << 31, 8, 16, 24)) == native.PP_ERANGE
 
 
+def test_edge_file_calls_reject_bad_args(tmp_path):
+    L = native.lib()
+    assert native.workspace_bytes(native.TSV_FORMAT, 0, 32, "f64", 3) > 0
+    assert native.workspace_bytes(native.TSV_PARSE, 0, 1 << 35, "f64") > 1 << 21  # > 2^31 bytes ok
+    assert native.workspace_bytes(native.TSV_PARSE, 0, 0, "f64") > 0
+    assert L.pp_workspace_bytes(native.TSV_FORMAT, 0, 32, 0, 0) == ctypes.c_size_t(-1).value
+    split = (ctypes.c_int64 * 3)()
+    sp = ctypes.cast(split, ctypes.c_void_p)
+    m = ctypes.c_int64(-1)
+    assert L.pp_tsv_format(31, 10, 8, 16, 24, 1000, 1, sp, 64, 1 << 20, None) == native.PP_ERANGE
+    assert L.pp_tsv_format(10, 10, 8, 16, 24, 1000, 0, sp, 64, 1 << 20, None) == native.PP_EINVAL
+    assert L.pp_tsv_format(10, 10, 8, 16, 24, 1000, 1, None, 64, 1 << 20, None) == native.PP_EINVAL
+    assert L.pp_tsv_format(10, 10, None, 16, 24, 1000, 1, sp, 64, 1 << 20, None) == native.PP_EINVAL
+    assert L.pp_tsv_format(10, 10, 8, 16, 24, 1000, 1, sp, 64, 4, None) == native.PP_EWORKSPACE
+    assert L.pp_tsv_parse(10, 8, 100, 10, 16, 24, ctypes.byref(m), 64, 1 << 20,
+                          None) == native.PP_EINVAL          # text not 16-byte aligned
+    assert m.value == 0
+    assert L.pp_tsv_parse(10, 16, -1, 10, 16, 24, ctypes.byref(m), 64, 1 << 20,
+                          None) == native.PP_EINVAL
+    assert L.pp_tsv_parse(31, 16, 100, 10, 16, 24, ctypes.byref(m), 64, 1 << 20,
+                          None) == native.PP_ERANGE
+    assert L.pp_tsv_parse(10, 16, 100, 10, 16, 24, None, 64, 1 << 20, None) == native.PP_EINVAL
+    assert L.pp_write_text_files(b"x", 0, 16, sp, 0, None) == native.PP_EINVAL
+    assert L.pp_write_text_files(None, 2, 16, sp, 0, None) == native.PP_EINVAL
+    nb = ctypes.c_int64(-1)
+    missing = str(tmp_path / "absent").encode()
+    assert L.pp_read_text_files(missing, 1, 16, 100, ctypes.byref(nb), None) == native.PP_EINVAL
+    assert b"absent" in L.pp_last_error()
+
+
 def test_init_r_rejects_bad_args():
     L = native.lib()
     assert L.pp_init_r(0, 1, 1, 0, 8, 64, 1 << 20, None) == native.PP_ERANGE
