@@ -1580,14 +1580,15 @@ __global__ __launch_bounds__(kWinThreads) void k_spmv_win(
 //   mode SELF adds c * x_j to y_j for every dangling j (the entry A(j,j) = 1
 //   of an empty row), so the new sum is S_y + c * D_x, D_x the mass of x on
 //   dangling vertices (from the previous pass);
-//   block sums of |y_j / S_y - x_j / S_x| and of y over dangling vertices.
+//   block sums of |y_j / S_y - x_j / S_x| (as products with the sums'
+//   reciprocals) and of y over dangling vertices.
 // A one-workgroup finish adds them in a fixed order: delta (infinite unless
 // both sums are positive), the stop flag delta <= tol, sum(r) of the new
 // iterate, and the next teleport (1-c)/N * S_y, plus c/N * D_y in mode
 // UNIFORM (a dangling vertex's damped mass spread evenly).  r_0's S and D
 // come from a pass of their own.
 enum : int32_t { kDangNone = 0, kDangUniform = 1, kDangSelf = 2 };
-constexpr int kConvBlocks = 1024;
+constexpr int kConvBlocks = 8192;
 
 struct ConvState {
   double sx, sy, dx, delta, stop;
@@ -1629,6 +1630,7 @@ __global__ __launch_bounds__(kThreads) void k_conv_step(const V *__restrict__ x,
   __shared__ double sh[4];
   const double sx = st->sx, sy = st->sy + self_c * st->dx;
   const bool ok = sx > 0.0 && sy > 0.0;
+  const double ix = ok ? 1.0 / sx : 0.0, iy = ok ? 1.0 / sy : 0.0;
   double a = 0.0, d = 0.0;
   for (int64_t j = blockIdx.x * int64_t(kThreads) + threadIdx.x; j < n;
        j += int64_t(gridDim.x) * kThreads) {
@@ -1639,7 +1641,7 @@ __global__ __launch_bounds__(kThreads) void k_conv_step(const V *__restrict__ x,
       y[j] = nv;
       v = double(nv);
     }
-    if (ok) a += fabs(v / sy - double(x[j]) / sx);
+    if (ok) a += fabs(v * iy - double(x[j]) * ix);
     if (dang) d += v;
   }
   const double ba = block_sum256(a, sh);
@@ -2142,7 +2144,7 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
     hipLaunchKernelGGL(k_sum0_mm<V>, dim3(G0), dim3(kThreads), 0, s, x0, n, k, lanes, kSumChunk,
                        L.part, L.counter, w, sums, L.tele);
   PP_LAUNCHED("k_sum0");
-  const int cblk = grid_for(n, kThreads * 16, kConvBlocks);
+  const int cblk = grid_for(n, kThreads * 4, kConvBlocks);
   const uint8_t *dflag = nullptr;
   if (cv) {
     if (cv->mode != kDangNone) {
