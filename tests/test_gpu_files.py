@@ -165,3 +165,24 @@ def test_files_many_chunks_per_worker(tmp_path):
         assert torch.equal(back[:nb], text[:nb])
         gu, gv = pp.tsv_parse(scale, back, nb, cap=u.numel())
         assert torch.equal(gu, u) and torch.equal(gv, v)
+
+
+def test_codec_round_trip_beyond_4gib():
+    # S = 24: 2^28 edges, about 4.4 GB of text, so byte offsets pass 2^32
+    # (64-bit block offsets in both directions).
+    scale = 24
+    s = spec(scale)
+    u, v = pp.generate(s)
+    text, split = pp.tsv_format(scale, u, v, nsplit=7)
+    nb = split[-1]
+    assert nb > (1 << 32)
+    # each part starts with the oracle's line of its first edge
+    m = u.numel()
+    for k in range(7):
+        e = m * k // 7
+        line = oracle.tsv_format(host(u[e:e + 1]), host(v[e:e + 1]))
+        assert bytes(host(text[split[k]:split[k] + len(line)])) == line
+    last = oracle.tsv_format(host(u[-1:]), host(v[-1:]))
+    assert bytes(host(text[nb - len(last):nb])) == last
+    gu, gv = pp.tsv_parse(scale, text, nb, cap=u.numel())
+    assert torch.equal(gu, u) and torch.equal(gv, v)
