@@ -296,8 +296,8 @@ __global__ __launch_bounds__(kThreads) void k_spmv(
 // but each item is processed by a group of G = nextpow2(k) lanes, lane l
 // owning right-hand side l: a non-zero gathers the k consecutive values of
 // row col of X (one 128 B line at k = 32), so the gather moves only useful
-// bytes.  Each group walks its items in order and keeps U gathers in
-// flight.  Carries between groups and workgroups, the per-column FP64
+// bytes.  Each group walks its items in order, gathering the next U
+// non-zeros' rows while it adds up the current U.  Carries between groups and workgroups, the per-column FP64
 // sum(y) and the per-column teleport scalar work as in the SpMV.
 template <typename V, int G>
 __global__ __launch_bounds__(kThreads) void k_spmm(
@@ -348,13 +348,21 @@ __global__ __launch_bounds__(kThreads) void k_spmm(
   Acc acc{}, first{};
   int32_t first_row = -1;
   double ysum = 0.0;
-  while (d < dend) {
-    V buf[U];
+  // Gathers of U non-zeros from tj on (indices clamped into the tile).
+  auto gather = [&](V *dst, int32_t from) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int32_t q = tj + u < nz ? tj + u : nz - 1;
-      buf[u] = (active && q >= 0) ? x[int64_t(s_col[q]) * k + l] : V(0);
+      const int32_t q = from + u < nz ? from + u : nz - 1;
+      dst[u] = (active && q >= 0) ? x[int64_t(s_col[q]) * k + l] : V(0);
     }
+  };
+  // A batch that does not end the group's items consumes exactly U
+  // non-zeros, so the next batch starts U further: its gathers are issued
+  // before the current batch is added up.
+  V buf[U], nxt[U];
+  gather(buf, tj);
+  while (d < dend) {
+    gather(nxt, tj + U);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       while (d < dend && ti < na && s_end[ti] <= tj) {
@@ -376,6 +384,8 @@ __global__ __launch_bounds__(kThreads) void k_spmm(
         ++d;
       }
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u) buf[u] = nxt[u];
   }
   s_carry[tid] = acc;
   if (l == 0) s_key[g] = i0 + ti;
