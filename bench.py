@@ -83,17 +83,18 @@ def calibrate_copy():
 
 
 def measured_traffic(scale: int, dtype: str, cfg, relabel: bool):
-    """HBM bytes per K3 iteration from the committed rocprofv3 counter summary
-    for this workload, or None when there is none, when it was taken with
-    another launch configuration, or when the kernel source has changed
-    since."""
+    """From the committed rocprofv3 counter summary for this workload: HBM
+    bytes per K3 iteration ("traffic", GB) and the raw SpMV's L1-to-L2 read
+    requests per launch with its traced duration ("l2"); None when there is
+    no summary, when it was taken with another launch configuration, or when
+    the kernel source has changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"k3_spmv_kron_s{scale}_{dtype}_counters.md")
     src = os.path.join(ROOT, "paper_1603_01876_amd", "csrc", "k3_pagerank.hip")
     if not os.path.exists(path):
         return None
     keys = ("kernel_source_sha256", "fetch_bytes_per_launch", "write_bytes_per_launch",
-            "k3_config", "relabel")
+            "k3_config", "relabel", "spmv_l2_read_requests_per_launch", "spmv_launch_us")
     fields = {}
     for line in open(path):
         if ":" in line and line.split(":", 1)[0].strip() in keys:
@@ -105,7 +106,16 @@ def measured_traffic(scale: int, dtype: str, cfg, relabel: bool):
     if fields.get("k3_config") != ",".join(str(x) for x in cfg) or \
             fields.get("relabel") != str(int(relabel)):
         return None
-    return (float(fields["fetch_bytes_per_launch"]) + float(fields["write_bytes_per_launch"])) / 1e9
+    out = {"traffic": (float(fields["fetch_bytes_per_launch"]) +
+                       float(fields["write_bytes_per_launch"])) / 1e9}
+    if "spmv_l2_read_requests_per_launch" in fields and "spmv_launch_us" in fields:
+        req = float(fields["spmv_l2_read_requests_per_launch"])
+        us = float(fields["spmv_launch_us"])
+        out["l2"] = {"kernel": "k_spmv raw (column-segmented)",
+                     "read_requests_per_launch": req, "launch_us": us,
+                     "requests_per_s": req / (us * 1e-6),
+                     "source": os.path.basename(path)}
+    return out
 
 
 def copy_ceiling(torch, nbytes=1 << 31, reps=5):
@@ -538,6 +548,7 @@ def main():
     sums_h = sums.cpu().numpy()
 
     copy_bw = copy_ceiling(torch)
+    mt = measured_traffic(S, dt, pp.get_k3_config(), state["relabel"])
     log(f"device copy ceiling {copy_bw:.0f} GB/s")
     out = {
         "metric": "K3 PageRank edges/s (20*M/t_K3)",
@@ -566,10 +577,11 @@ def main():
         "roofline": {"bound": "hbm", "kernel": spmv_label(pp.get_k3_config(), dt),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(S, dt, pp.get_k3_config(), state["relabel"]),
+                     "traffic": (mt or {}).get("traffic"),
                      "traffic_unit": "GB per iteration (rocprofv3 FETCH_SIZE + WRITE_SIZE over the iteration's launches, copy-calibrated)",
                      "algorithmic_bytes_per_launch": nbytes,
-                     "copy_GBps": copy_bw, "frac_of_copy": achieved / copy_bw},
+                     "copy_GBps": copy_bw, "frac_of_copy": achieved / copy_bw,
+                     "l2_requests": (mt or {}).get("l2")},
         "sum_r": {"first": float(sums_h[0]), "last": float(sums_h[-1])},
         "k3_config": {"items_per_thread": pp.get_k3_config()[0],
                       "slab_log2": pp.get_k3_config()[2],
