@@ -12,11 +12,15 @@
 //   2. vstart[w]  = first position of column w in the sorted list
 //   3. d_in[w]    = vstart[w+1] - vstart[w];  mx = max d_in (atomicMax)
 //   4. keep bitmap: d_in != mx and d_in != 1 (both on the same d_in)
-//   5. d_out[u]   = kept edges per u, on the u-ordered input: per-wave
-//                   segmented popcounts, one integer atomic per run
-//   6. compaction: per-tile counts of kept distinct pairs, scan, emit
-//                   col = u, val = count / d_out[u] (IEEE FP64 division,
-//                   FP32 stores the rounded quotient) and row_ptr.
+//   5. d_out[u]   = all edges per u, on the u-ordered input: per-wave
+//                   run lengths, one integer atomic per run
+//   6. compaction: per-tile counts of kept distinct pairs; every edge into
+//                   a removed column takes one from d_out[u] (d_out is then
+//                   the kept edges per u); scan, emit col = u, val = count /
+//                   d_out[u] (IEEE FP64 division, FP32 stores the rounded
+//                   quotient) and row_ptr.
+// Step 5 reads only u; the keep bitmap is read in v order in step 6, where
+// consecutive entries share its words, instead of once per edge at random.
 #include "pp_common.hpp"
 
 namespace pp {
@@ -79,12 +83,10 @@ __global__ __launch_bounds__(256) void k_keepbits(const int32_t *__restrict__ d_
   }
 }
 
-// d_out[u] += number of kept edges of u, over the u-ordered input.  A wave
-// covers 64 consecutive edges; each run of equal u inside it is summed with
-// one popcount and one atomic add by the run's first lane.
-__global__ __launch_bounds__(256) void k_dout(const int64_t *__restrict__ u,
-                                              const int64_t *__restrict__ v, int64_t m,
-                                              const uint64_t *__restrict__ keepw,
+// d_out[u] += number of edges of u, over the u-ordered input.  A wave
+// covers 64 consecutive edges; each run of equal u inside it is counted by
+// the run's first lane with one popcount and one atomic add.
+__global__ __launch_bounds__(256) void k_dout(const int64_t *__restrict__ u, int64_t m,
                                               int32_t *__restrict__ d_out) {
   const int64_t stride = int64_t(gridDim.x) * 256;
   const int lane = lane_id();
@@ -92,26 +94,26 @@ __global__ __launch_bounds__(256) void k_dout(const int64_t *__restrict__ u,
     const int64_t p = p0 + lane;
     const bool valid = p < m;
     const int32_t uu = valid ? int32_t(u[p]) : -1;
-    const bool f = valid && kept(keepw, int32_t(v[p]));
     const int32_t up = __shfl_up(uu, 1, kWave);
     const bool head = valid && (lane == 0 || up != uu);
     const uint64_t heads = __ballot(head);
-    const uint64_t flags = __ballot(f);
+    const uint64_t flags = __ballot(valid);
     if (head) {
       const uint64_t after = heads & ~((2ull << lane) - 1ull);   // heads above this lane
       const uint64_t upto = after ? (after & (~after + 1ull)) - 1ull : ~0ull;
       const uint64_t seg = upto & ~((1ull << lane) - 1ull);
-      const int cnt = __popcll(flags & seg);
-      if (cnt) atomicAdd(&d_out[uu], cnt);
+      atomicAdd(&d_out[uu], __popcll(flags & seg));
     }
   }
 }
 
-// Per tile: number of kept distinct (v,u) pairs.
+// Per tile: number of kept distinct (v,u) pairs.  Every edge into a removed
+// column (counted with its multiplicity) takes one from d_out[u].
 __global__ __launch_bounds__(kThreads) void k_compact_count(const uint64_t *__restrict__ P,
                                                             int64_t m,
                                                             const uint64_t *__restrict__ keepw,
-                                                            uint32_t *__restrict__ tile_cnt) {
+                                                            uint32_t *__restrict__ tile_cnt,
+                                                            int32_t *__restrict__ d_out) {
   __shared__ uint32_t sh[4];
   const int w = threadIdx.x / kWave;
   const int64_t base = int64_t(blockIdx.x) * kTile + int64_t(w) * kWaveKeys;
@@ -121,7 +123,10 @@ __global__ __launch_bounds__(kThreads) void k_compact_count(const uint64_t *__re
     if (p < m) {
       const uint64_t key = P[p];
       const bool distinct = p == 0 || P[p - 1] != key;
-      c += (distinct && kept(keepw, vof(key))) ? 1u : 0u;
+      if (kept(keepw, vof(key)))
+        c += distinct ? 1u : 0u;
+      else
+        atomicSub(&d_out[uof(key)], 1);
     }
   }
   const uint32_t tot = block_sum256(c, sh);
@@ -131,7 +136,7 @@ __global__ __launch_bounds__(kThreads) void k_compact_count(const uint64_t *__re
 template <typename V>
 __global__ __launch_bounds__(kThreads) void k_compact_emit(
     const uint64_t *__restrict__ P, int64_t m, int32_t n, const uint64_t *__restrict__ keepw,
-    const int32_t *__restrict__ d_out, const uint32_t *__restrict__ tile_off,
+    const int32_t *__restrict__ d_out, HotTab hot, const uint32_t *__restrict__ tile_off,
     int32_t *__restrict__ row_ptr, int32_t *__restrict__ col, V *__restrict__ val) {
   __shared__ uint32_t wave_tot[kWaves];
   const int w = threadIdx.x / kWave;
@@ -170,7 +175,7 @@ __global__ __launch_bounds__(kThreads) void k_compact_emit(
         const int32_t u = uof(key);
         int64_t q = p + 1;
         while (q < m && P[q] == key) ++q;
-        const double quot = double(q - p) / double(d_out[u]);
+        const double quot = double(q - p) / double(hot_get(hot, d_out, u));
         col[excl] = u;
         val[excl] = V(quot);
       }
@@ -193,6 +198,7 @@ struct Layout {
   int32_t *vstart, *d_in, *d_out;
   uint64_t *keepw;
   uint32_t *tile_cnt, *scan_ws;
+  uint64_t *hot;
   int32_t *mx;
   int64_t *z;
   uint32_t *flag;
@@ -211,6 +217,7 @@ Layout carve(void *ws, int64_t n, int64_t m) {
   L.keepw = c.take<uint64_t>(size_t((n + 63) / 64));
   L.tile_cnt = c.take<uint32_t>(size_t(ntiles + 1));
   L.scan_ws = c.take<uint32_t>(size_t(scan_ws_elems(ntiles + 1)));
+  L.hot = c.take<uint64_t>(hot_bytes(n) / 8);
   L.mx = c.take<int32_t>(1);
   L.z = c.take<int64_t>(1);
   L.flag = c.take<uint32_t>(1);
@@ -230,6 +237,7 @@ size_t filter_ws_bytes(int64_t n, int64_t m) {
   c.take<uint64_t>(size_t((n + 63) / 64));
   c.take<uint32_t>(size_t(ntiles + 1));
   c.take<uint32_t>(size_t(scan_ws_elems(ntiles + 1)));
+  c.take<uint64_t>(hot_bytes(n) / 8);
   c.take<int32_t>(1);
   c.take<int64_t>(1);
   c.take<uint32_t>(1);
@@ -272,25 +280,28 @@ pp_status launch_filter(int32_t scale, int64_t m, const int64_t *u, const int64_
                      s, din, n32, L.mx, L.keepw);
   PP_LAUNCHED("k_vstart/k_din/k_keepbits");
 
-  // 5. out-degrees from the u-ordered input.
+  // 5. edges per u from the u-ordered input.
   if ((st = fill_i32(dout, n, 0, s)) != PP_OK) return st;
-  hipLaunchKernelGGL(k_dout, dim3(grid_for(m, 256, 256 * 32)), dim3(256), 0, s, u, v, m, L.keepw,
-                     dout);
+  hipLaunchKernelGGL(k_dout, dim3(grid_for(m, 256, 256 * 32)), dim3(256), 0, s, u, m, dout);
   PP_LAUNCHED("k_dout");
 
-  // 6. compaction into CSR(A^T).
+  // 6. compaction into CSR(A^T); removed edges leave d_out here.
   const int64_t ntiles = (m + kTile - 1) / kTile;
   hipLaunchKernelGGL(k_compact_count, dim3(unsigned(ntiles)), dim3(kThreads), 0, s, L.P, m,
-                     L.keepw, L.tile_cnt);
+                     L.keepw, L.tile_cnt, dout);
   PP_LAUNCHED("k_compact_count");
   if ((st = exscan_u32(L.tile_cnt, L.tile_cnt, ntiles, L.scan_ws, L.z, s)) != PP_OK) return st;
+  // d_out is read once per kept pair at random u: the hottest vertices'
+  // out-degrees are cached in an L2-sized table in front of it.
+  HotTab hot;
+  if ((st = hot_build(dout, dout, n32, L.hot, &hot, s)) != PP_OK) return st;
   if (dt == PP_F64)
     hipLaunchKernelGGL(k_compact_emit<double>, dim3(unsigned(ntiles)), dim3(kThreads), 0, s, L.P,
-                       m, n32, L.keepw, dout, L.tile_cnt, AT->row_ptr, AT->col,
+                       m, n32, L.keepw, dout, hot, L.tile_cnt, AT->row_ptr, AT->col,
                        static_cast<double *>(AT->val));
   else
     hipLaunchKernelGGL(k_compact_emit<float>, dim3(unsigned(ntiles)), dim3(kThreads), 0, s, L.P,
-                       m, n32, L.keepw, dout, L.tile_cnt, AT->row_ptr, AT->col,
+                       m, n32, L.keepw, dout, hot, L.tile_cnt, AT->row_ptr, AT->col,
                        static_cast<float *>(AT->val));
   PP_LAUNCHED("k_compact_emit");
 

@@ -679,7 +679,7 @@ __global__ void k_set_total(int32_t *rp2, int32_t n, const int64_t *total) {
 template <typename V>
 __global__ __launch_bounds__(kThreads) void k_relabel_copy(
     const int32_t *__restrict__ rp, const int32_t *__restrict__ col, const V *__restrict__ val,
-    const int32_t *__restrict__ order, const int32_t *__restrict__ newlabel,
+    const int32_t *__restrict__ order, const int32_t *__restrict__ newlabel, HotTab hot,
     const int32_t *__restrict__ rp2, int32_t n, const int2 *__restrict__ coord,
     int32_t *__restrict__ col2, V *__restrict__ val2) {
   __shared__ int32_t s_end[kItemsMax];
@@ -707,7 +707,7 @@ __global__ __launch_bounds__(kThreads) void k_relabel_copy(
         hi = m;
     }
     const int32_t src = s_old[lo] + (q - s_new[lo]);
-    col2[q] = newlabel[col[src]];
+    col2[q] = hot_get(hot, newlabel, col[src]);
     val2[q] = val[src];
   }
 }
@@ -785,6 +785,7 @@ constexpr int kMaskWords = kMaxSlabs / 32;
 struct RelabelSrc {
   const int32_t *rp0, *col0, *order, *newlabel;
   const void *val0;
+  HotTab hot;   // cache of newlabel for the heaviest vertices
 };
 
 template <typename V, bool kScatter, bool kRelabel>
@@ -838,7 +839,8 @@ __global__ __launch_bounds__(kThreads) void k_seg_tile(
   if constexpr (kRelabel) {
 #pragma unroll
     for (int r = 0; r < kSegPer; ++r)
-      if (w * (kSegTile / kWaves) + r * kWave + lane < nz) cc[r] = rs.newlabel[cc[r]];
+      if (w * (kSegTile / kWaves) + r * kWave + lane < nz)
+        cc[r] = hot_get(rs.hot, rs.newlabel, cc[r]);
 #pragma unroll
     for (int r = 0; r < kSegPer; ++r) {
       const int32_t e = w * (kSegTile / kWaves) + r * kWave + lane;
@@ -1731,6 +1733,7 @@ struct Layout {
   void *radix_ws;
   size_t radix_bytes;
   int32_t *order, *newlabel, *rp2, *col2;
+  uint64_t *hot;
   V *val2, *x2;
   int64_t *total;
   // column segmenting
@@ -1780,6 +1783,7 @@ Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs, size_t *byte
   L.radix_ws = c.take<uint8_t>(L.radix_bytes);
   L.order = c.take<int32_t>(size_t(n));
   L.newlabel = c.take<int32_t>(size_t(n));
+  L.hot = c.take<uint64_t>(hot_bytes(n) / 8);
   L.rp2 = c.take<int32_t>(size_t(n + 1));
   {
     // One region for the relabelled entries; when the columns are
@@ -2078,6 +2082,7 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
   const int32_t *rp = AT0.row_ptr, *col = AT0.col;
   const V *val = static_cast<const V *>(AT0.val);
   V *x0 = r;
+  HotTab hot{nullptr, 0};
   if (weights) {
     hipLaunchKernelGGL(k_order_keys, dim3(gN), dim3(256), 0, s, weights, n32, L.keys_in);
     PP_LAUNCHED("k_order_keys");
@@ -2091,6 +2096,9 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
                     reinterpret_cast<uint32_t *>(L.keys_in), L.total, s);
     if (st != PP_OK) return st;
     hipLaunchKernelGGL(k_set_total, dim3(1), dim3(64), 0, s, L.rp2, n32, L.total);
+    // Every entry's column goes through newlabel at random; the heaviest
+    // sources' new labels are cached in an L2-sized table in front of it.
+    if ((st = hot_build(weights, L.newlabel, n32, L.hot, &hot, s)) != PP_OK) return st;
     rp = L.rp2;
     col = L.col2;
     val = L.val2;
@@ -2119,15 +2127,15 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
   int32_t nbp = 0, ncomb = 0;
   int64_t Pr = 0;   // pairs (and their entries) left to the raw SpMV
   if (segment) {
-    const RelabelSrc rl{AT0.row_ptr, AT0.col, L.order, L.newlabel, AT0.val};
+    const RelabelSrc rl{AT0.row_ptr, AT0.col, L.order, L.newlabel, AT0.val, hot};
     st = build_segments<V>(L, rp, const_cast<int32_t *>(col), const_cast<V *>(val), n, nnz,
                            slab_log2, g_cfg.hot_windows, weights ? &rl : nullptr, &si, s);
     if (st != PP_OK) return st;
   }
   if (weights && !si.relabelled) {
     hipLaunchKernelGGL(k_relabel_copy<V>, dim3(nb), dim3(kThreads), 0, s, AT0.row_ptr, AT0.col,
-                       static_cast<const V *>(AT0.val), L.order, L.newlabel, L.rp2, n32, L.coord,
-                       L.col2, L.val2);
+                       static_cast<const V *>(AT0.val), L.order, L.newlabel, hot, L.rp2, n32,
+                       L.coord, L.col2, L.val2);
     PP_LAUNCHED("k_relabel_copy");
   }
   if (segment) {

@@ -165,6 +165,34 @@ __device__ __forceinline__ T load_acquire(const T *p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Hot-vertex cache: a small direct-mapped table in front of a per-vertex
+// int32 table that a kernel reads at random once per matrix entry.  Random
+// reads that miss L2 run about five times slower than ones that hit it,
+// whether or not the big table fits the Infinity Cache; the cache is sized
+// to stay in one XCD's L2.  Slot hot_mix(u) & mask holds the vertex of
+// highest degree hashed there as (value << 32 | u), or a key no vertex has.
+// A lookup that finds another vertex reads the big table, so results never
+// depend on what the cache holds.  hot_mix is the "lowbias32" integer
+// finaliser (C. Wellons, 2018).
+struct HotTab {
+  const uint64_t *tab;
+  uint32_t mask;
+};
+
+__device__ __forceinline__ uint32_t hot_mix(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352dU;
+  x ^= x >> 15;
+  x *= 0x846ca68bU;
+  x ^= x >> 16;
+  return x;
+}
+
+__device__ __forceinline__ int32_t hot_get(HotTab h, const int32_t *__restrict__ full, int32_t u) {
+  const uint64_t e = h.tab[hot_mix(uint32_t(u)) & h.mask];
+  return uint32_t(e) == uint32_t(u) ? int32_t(uint32_t(e >> 32)) : full[u];
+}
+
 // ------------------------------------------------------ host launchers
 // Each .hip file exposes plain host functions that enqueue its kernels.
 
@@ -172,6 +200,14 @@ __device__ __forceinline__ T load_acquire(const T *p) {
 pp_status fill_i32(int32_t *p, int64_t n, int32_t value, hipStream_t s);
 pp_status fill_u64(uint64_t *p, int64_t n, uint64_t value, hipStream_t s);
 pp_status copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t s);
+
+// Hot-vertex cache (pp_util.hip): 2^hot_log2(n) slots (at most 2^17,
+// 1 MiB), filled from degrees deg[0..n) (vertices of degree < 8 are left
+// out) with values full[u]; hot_bytes(n) is the table's size.
+int hot_log2(int64_t n);
+size_t hot_bytes(int64_t n);
+pp_status hot_build(const int32_t *deg, const int32_t *full, int32_t n, uint64_t *tab,
+                    HotTab *h, hipStream_t s);
 
 // Exclusive scan of n uint32 values (in place allowed).  `total` (device,
 // may be null) receives the sum as int64.  Workspace from scan_ws_elems().

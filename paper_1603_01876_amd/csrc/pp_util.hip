@@ -25,6 +25,54 @@ pp_status fill_u64(uint64_t *p, int64_t n, uint64_t value, hipStream_t s) {
   return PP_OK;
 }
 
+// ------------------------------------------------------ hot-vertex cache
+int hot_log2(int64_t n) {
+  int lg = 4;
+  while (lg < 17 && (int64_t(4) << lg) < n) ++lg;   // about n / 4 slots
+  return lg;
+}
+
+size_t hot_bytes(int64_t n) { return sizeof(uint64_t) << hot_log2(n); }
+
+__global__ __launch_bounds__(256) void k_hot_max(const int32_t *__restrict__ deg, int32_t n,
+                                                 unsigned long long *__restrict__ tab,
+                                                 uint32_t mask) {
+  for (int32_t u = blockIdx.x * 256 + threadIdx.x; u < n; u += gridDim.x * 256) {
+    const int32_t d = deg[u];
+    if (d >= 8)
+      atomicMax(&tab[hot_mix(uint32_t(u)) & mask],
+                (static_cast<unsigned long long>(uint32_t(d)) << 32) | uint32_t(u));
+  }
+}
+
+// Winner (degree << 32 | u) -> (full[u] << 32 | u); empty slots get key
+// 0xFFFFFFFF, which no vertex label (< 2^31) equals.
+__global__ __launch_bounds__(256) void k_hot_fill(const int32_t *__restrict__ full,
+                                                  uint64_t *__restrict__ tab, uint32_t slots) {
+  for (uint32_t k = blockIdx.x * 256 + threadIdx.x; k < slots; k += gridDim.x * 256) {
+    const uint64_t e = tab[k];
+    const uint32_t u = uint32_t(e);
+    tab[k] = e ? (uint64_t(uint32_t(full[u])) << 32) | u : 0xFFFFFFFFull;
+  }
+}
+
+pp_status hot_build(const int32_t *deg, const int32_t *full, int32_t n, uint64_t *tab, HotTab *h,
+                    hipStream_t s) {
+  const int lg = hot_log2(n);
+  const uint32_t slots = 1u << lg;
+  pp_status st;
+  if ((st = fill_u64(tab, slots, 0, s)) != PP_OK) return st;
+  if (n > 0)
+    hipLaunchKernelGGL(k_hot_max, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, deg, n,
+                       reinterpret_cast<unsigned long long *>(tab), slots - 1u);
+  hipLaunchKernelGGL(k_hot_fill, dim3(grid_for(slots, 256, 1024)), dim3(256), 0, s, full, tab,
+                     slots);
+  PP_LAUNCHED("k_hot_max/k_hot_fill");
+  h->tab = tab;
+  h->mask = slots - 1u;
+  return PP_OK;
+}
+
 __global__ __launch_bounds__(256) void k_copy16(uint4 *dst, const uint4 *src, int64_t n) {
   for (int64_t i = blockIdx.x * int64_t(256) + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
     dst[i] = src[i];
