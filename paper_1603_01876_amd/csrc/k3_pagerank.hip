@@ -78,17 +78,26 @@ __device__ __forceinline__ AccF merge(AccF a, AccF b) {
 
 template <typename V>
 struct Form;
+// Part: what the segmented iteration stores per (slab, row) pair for the
+// combine -- FP64 its sum, FP32 the compensated pair rounded once to float
+// (half the bytes; the combine merges the partials with TwoSum again).
 template <>
 struct Form<double> {
   using Acc = AccD;
+  using Part = double;
   __device__ static double finish(AccD a, double c, double t) { return c * a.value() + t; }
+  __device__ static Part part(AccD a) { return a.s; }
+  __device__ static AccD acc(Part p) { return AccD{p}; }
 };
 template <>
 struct Form<float> {
   using Acc = AccF;
+  using Part = float;
   __device__ static float finish(AccF a, double c, double t) {
     return float(c * double(a.value()) + t);
   }
+  __device__ static Part part(AccF a) { return a.value(); }
+  __device__ static AccF acc(Part p) { return AccF{p, 0.0f}; }
 };
 
 // ------------------------------------------------------------- partition
@@ -141,7 +150,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv(
     const V *__restrict__ x, V *__restrict__ y, int32_t n, const int2 *__restrict__ coord,
     double c, const double *__restrict__ tele, double *__restrict__ blk_ysum,
     typename Form<V>::Acc *__restrict__ blk_carry, typename Form<V>::Acc *__restrict__ blk_head,
-    typename Form<V>::Acc *__restrict__ part) {
+    typename Form<V>::Part *__restrict__ part) {
   using Acc = typename Form<V>::Acc;
   constexpr int kD = kThreads * IPT;
   constexpr int kWaves = kThreads / kWave;
@@ -224,7 +233,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv(
         first_row = ti;
         first = acc;
       } else if constexpr (kRaw) {
-        part[i0 + ti] = acc;
+        part[i0 + ti] = Form<V>::part(acc);
       } else {
         const V yv = Form<V>::finish(acc, c, tk);
         y[i0 + ti] = yv;
@@ -275,7 +284,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv(
     if (R == i0 && mid_row) {
       blk_head[b] = sum;  // row began in an earlier workgroup: completed later
     } else if constexpr (kRaw) {
-      part[R] = sum;
+      part[R] = Form<V>::part(sum);
     } else {
       const V yv = Form<V>::finish(sum, c, tk);
       y[R] = yv;
@@ -1056,7 +1065,7 @@ __global__ __launch_bounds__(256) void k_pair_index(const uint64_t *__restrict__
 
 // Completes pairs that span SpMV workgroups (raw accumulators, no sum).
 template <typename V>
-__global__ __launch_bounds__(256) void k_fix_raw(typename Form<V>::Acc *__restrict__ part,
+__global__ __launch_bounds__(256) void k_fix_raw(typename Form<V>::Part *__restrict__ part,
                                                  int32_t nb, const int2 *__restrict__ coord,
                                                  const uint8_t *__restrict__ closes,
                                                  const int32_t *__restrict__ carry_row,
@@ -1070,7 +1079,7 @@ __global__ __launch_bounds__(256) void k_fix_raw(typename Form<V>::Acc *__restri
     while (q >= 0 && carry_row[q] == R) --q;
     Acc sum{};
     for (int32_t k = q + 1; k < b; ++k) sum = merge(sum, blk_carry[k]);
-    part[R] = merge(sum, blk_head[b]);
+    part[R] = Form<V>::part(merge(sum, blk_head[b]));
   }
 }
 
@@ -1104,13 +1113,14 @@ __global__ __launch_bounds__(256) void k_comb_bounds(const int32_t *__restrict__
 // queue on a shared arrival counter).
 template <typename V>
 __global__ __launch_bounds__(kThreads) void k_seg_combine(
-    const typename Form<V>::Acc *__restrict__ part, const int32_t *__restrict__ rpp,
+    const typename Form<V>::Part *__restrict__ part, const int32_t *__restrict__ rpp,
     const int32_t *__restrict__ pidx, const int2 *__restrict__ cstart, double c,
     const double *__restrict__ tele_in, V *__restrict__ y, double *__restrict__ blk_ysum) {
   using Acc = typename Form<V>::Acc;
+  using Part = typename Form<V>::Part;
   constexpr int kCap = kCombItems + kMaxSlabs;
   constexpr int kPer = kCap / kThreads;
-  __shared__ Acc s_part[kCap];
+  __shared__ Part s_part[kCap];
   __shared__ uint16_t s_off[kCap + 1];   // rpp[R0 + i] - rpp[R0]
   __shared__ double sh[4];
   const int b = blockIdx.x, tid = threadIdx.x;
@@ -1133,7 +1143,7 @@ __global__ __launch_bounds__(kThreads) void k_seg_combine(
       const int32_t q = k * kThreads + tid;
       if (q <= nr) s_off[q] = uint16_t(ro[k] - j0);
     }
-    Acc pa[kPer];
+    Part pa[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int32_t q = k * kThreads + tid;
@@ -1151,7 +1161,7 @@ __global__ __launch_bounds__(kThreads) void k_seg_combine(
   for (int32_t i = tid; i < nr; i += kThreads) {
     const int32_t e = s_off[i + 1];
     Acc acc{};
-    for (int32_t j = s_off[i]; j < e; ++j) acc = merge(acc, s_part[j]);
+    for (int32_t j = s_off[i]; j < e; ++j) acc = merge(acc, Form<V>::acc(s_part[j]));
     const V yv = Form<V>::finish(acc, c, tk);
     y[R0 + i] = yv;
     ysum += double(yv);
@@ -1410,7 +1420,7 @@ template <typename V>
 __global__ __launch_bounds__(kWinThreads) void k_spmv_win(
     const uint32_t *__restrict__ pk, const V *__restrict__ val, const V *__restrict__ x,
     int32_t n, const int2 *__restrict__ wb, const int32_t *__restrict__ chunk, int32_t nwin,
-    typename Form<V>::Acc *__restrict__ part) {
+    typename Form<V>::Part *__restrict__ part) {
   using Acc = typename Form<V>::Acc;
   constexpr int kWinBits = win_bits<V>();
   constexpr int kWinSize = 1 << kWinBits;
@@ -1580,7 +1590,7 @@ __global__ __launch_bounds__(kWinThreads) void k_spmv_win(
     wcur = wnext;
   }
   __syncthreads();
-  for (int i = tid; i < rows; i += kWinThreads) part[w0.x + i] = s_acc[i];
+  for (int i = tid; i < rows; i += kWinThreads) part[w0.x + i] = Form<V>::part(s_acc[i]);
 }
 
 // ------------------------------------------------ run to a convergence test
@@ -1745,7 +1755,7 @@ struct Layout {
   int32_t *wchunk;
   int64_t *info;
   V *seg_val;
-  typename Form<V>::Acc *seg_part;
+  typename Form<V>::Part *seg_part;
   // run to a convergence test
   uint8_t *dflag;
   double *conv_part;
@@ -1809,8 +1819,9 @@ Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs, size_t *byte
     L.prp = c.take<int32_t>(size_t(z + 1));
     L.pair_row = c.take<int32_t>(size_t(z));
     // The partials are written only by the iterations; during the build
-    // the same bytes hold the keys of the pairs' row-major sort.
-    L.seg_part = c.take<typename Form<V>::Acc>(size_t(z));
+    // the same bytes hold the keys of the pairs' row-major sort (8 B per
+    // pair, so the region keeps 8 B per entry for FP32 too).
+    L.seg_part = reinterpret_cast<typename Form<V>::Part *>(c.take<uint64_t>(size_t(z)));
     const int64_t wcnt = int64_t(kMaxWins) * (z / kWinTile + z * (kWinRowCost + 1) / kWinBlock + 4);
     const int64_t cnt_n = kMaxSlabs * ntiles > wcnt ? kMaxSlabs * ntiles : wcnt;
     L.seg_cnt = c.take<uint32_t>(size_t(cnt_n));
@@ -1870,7 +1881,7 @@ template <typename V, bool kRaw>
 void launch_spmv(int ipt, int32_t nb, hipStream_t s, const int32_t *rp, const int32_t *col,
                  const V *val, const V *x, V *y, int32_t n, const int2 *coord, double c,
                  const double *tele, double *blk_ysum, typename Form<V>::Acc *blk_carry,
-                 typename Form<V>::Acc *blk_head, typename Form<V>::Acc *part) {
+                 typename Form<V>::Acc *blk_head, typename Form<V>::Part *part) {
   if (ipt == 4)
     hipLaunchKernelGGL((k_spmv<V, 4, kRaw>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x, y,
                        n, coord, c, tele, blk_ysum, blk_carry, blk_head, part);
