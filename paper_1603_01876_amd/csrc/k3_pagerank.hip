@@ -1045,22 +1045,28 @@ __global__ __launch_bounds__(256) void k_seg_cont(const int32_t *__restrict__ rp
   }
 }
 
-// Row-major order of the pairs: key = row << 32 | pair, sorted stably by
-// row (so a row's pairs stay in slab order); pcount[row] counts its pairs.
-__global__ __launch_bounds__(256) void k_pair_keys(const int32_t *__restrict__ pair_row, int64_t P,
-                                                   uint64_t *__restrict__ keys,
-                                                   uint32_t *__restrict__ pcount) {
-  for (int64_t p = blockIdx.x * int64_t(256) + threadIdx.x; p < P; p += int64_t(gridDim.x) * 256) {
-    const int32_t v = pair_row[p];
-    keys[p] = (uint64_t(uint32_t(v)) << 32) | uint64_t(uint32_t(p));
-    atomicAdd(pcount + v, 1u);
-  }
+// Row-major order of the pairs (pidx) for the combine.  pcount[row] counts
+// a row's pairs.  The pairs are stored slab by slab, rows ascending inside
+// a slab, and a row has at most one pair per slab; so appending each
+// slab's pairs to their rows' runs, one launch per slab in slab order,
+// lists every row's pairs in slab order, and inside a launch every row's
+// cursor has one writer.
+__global__ __launch_bounds__(256) void k_pair_count(const int32_t *__restrict__ pair_row, int64_t P,
+                                                    uint32_t *__restrict__ pcount) {
+  for (int64_t p = blockIdx.x * int64_t(256) + threadIdx.x; p < P; p += int64_t(gridDim.x) * 256)
+    atomicAdd(pcount + pair_row[p], 1u);
 }
 
-__global__ __launch_bounds__(256) void k_pair_index(const uint64_t *__restrict__ keys, int64_t P,
+__global__ __launch_bounds__(256) void k_pair_place(const int32_t *__restrict__ pair_row, int64_t p0,
+                                                    int64_t p1, int32_t *__restrict__ cursor,
                                                     int32_t *__restrict__ pidx) {
-  for (int64_t j = blockIdx.x * int64_t(256) + threadIdx.x; j < P; j += int64_t(gridDim.x) * 256)
-    pidx[j] = int32_t(uint32_t(keys[j]));
+  for (int64_t p = p0 + blockIdx.x * int64_t(256) + threadIdx.x; p < p1;
+       p += int64_t(gridDim.x) * 256) {
+    const int32_t r = pair_row[p];
+    const int32_t q = cursor[r];
+    pidx[q] = int32_t(p);
+    cursor[r] = q + 1;
+  }
 }
 
 // Completes pairs that span SpMV workgroups (raw accumulators, no sum).
@@ -1838,7 +1844,7 @@ Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs, size_t *byte
     L.wb = c.take<int2>(size_t(nblk_w + 1));
     L.wtb = c.take<uint32_t>(size_t(nblk_w + 2));
     L.wchunk = c.take<int32_t>(size_t(nblk_w) * (kMaxWins + 1));
-    L.info = c.take<int64_t>(4);
+    L.info = c.take<int64_t>(4 + kMaxSlabs);
     L.cstart = c.take<int2>(size_t((n + z + kCombItems - 1) / kCombItems + 2));
     L.pidx = L.col2;
   }
@@ -1893,14 +1899,16 @@ void launch_spmv(int ipt, int32_t nb, hipStream_t s, const int32_t *rp, const in
                        n, coord, c, tele, blk_ysum, blk_carry, blk_head, part);
 }
 
-// info[0] = P, info[1] = E0 (entries of slab 0), info[2] = P0 (its pairs);
+// info[0] = P, info[1] = E0 (entries of slab 0), info[2] = P0 (its pairs),
+// info[3 + d] = first pair of slab d (d <= ns; slab ns = the end, P);
 // prp[P] = nnz.  eoff / poff are the per-(tile, slab) offsets, so their
-// entry for (tile 0, slab 1) is slab 0's total.
+// entry for (tile 0, slab d) is the start of slab d.
 __global__ void k_seg_info(const uint32_t *__restrict__ eoff, const uint32_t *__restrict__ poff,
-                           int64_t nnz, const int64_t *__restrict__ total,
+                           int32_t ns, int64_t nnz, const int64_t *__restrict__ total,
                            int32_t *__restrict__ prp, int64_t *__restrict__ info) {
+  const int64_t P = *total;
+  for (int d = threadIdx.x; d <= ns; d += blockDim.x) info[3 + d] = d < ns ? int64_t(poff[d]) : P;
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    const int64_t P = *total;
     info[0] = P;
     info[1] = eoff[1];
     info[2] = poff[1];
@@ -1973,11 +1981,11 @@ pp_status build_segments(const Layout<V> &L, const int32_t *rp, int32_t *col, V 
   hipLaunchKernelGGL((k_seg_tile<V, true, false>), dim3(ntiles), dim3(kThreads), 0, s, rp, col,
                      val, n32, RelabelSrc{}, L.seg_coord, sbits, ns, dbits, ntiles, L.seg_cnt,
                      L.seg_pcnt, L.seg_fmask, nullptr, L.seg_col, L.seg_val, L.prp, L.pair_row);
-  hipLaunchKernelGGL(k_seg_info, dim3(1), dim3(64), 0, s, L.seg_cnt, L.seg_pcnt, nnz, L.total,
-                     L.prp, L.info);
+  hipLaunchKernelGGL(k_seg_info, dim3(1), dim3(256), 0, s, L.seg_cnt, L.seg_pcnt, ns, nnz,
+                     L.total, L.prp, L.info);
   PP_LAUNCHED("k_seg_tile (scatter)/k_seg_info");
-  int64_t info[3] = {0, 0, 0};
-  PP_HIP(hipMemcpyAsync(info, L.info, sizeof(info), hipMemcpyDeviceToHost, s));
+  int64_t info[4 + kMaxSlabs] = {};
+  PP_HIP(hipMemcpyAsync(info, L.info, sizeof(int64_t) * size_t(4 + ns), hipMemcpyDeviceToHost, s));
   PP_HIP(hipStreamSynchronize(s));
   const int64_t P = info[0], E0 = info[1], P0 = info[2];
   if (P <= 0 || P > nnz || P + nnz > int64_t(INT32_MAX)) return PP_OK;
@@ -2029,28 +2037,29 @@ pp_status build_segments(const Layout<V> &L, const int32_t *rp, int32_t *col, V 
     si.nwin = nwin;
   }
 
-  // Row-major index of the pairs for the combine: the keys sort in the
-  // partials' region (free until the first iteration) against the
-  // relabelled-entry region (free once the slab-major copy exists).
-  uint64_t *keys = reinterpret_cast<uint64_t *>(L.seg_part);
-  uint64_t *keys_b = reinterpret_cast<uint64_t *>(L.col2);
+  // Row-major index of the pairs for the combine (see k_pair_place): the
+  // row cursors live in the relabelling's key buffer, free by now.
   st = fill_i32(L.rpp, n + 1, 0, s);
   if (st != PP_OK) return st;
-  hipLaunchKernelGGL(k_pair_keys, dim3(grid_for(P, 256, 16384)), dim3(256), 0, s, L.pair_row, P,
-                     keys, reinterpret_cast<uint32_t *>(L.rpp));
-  PP_LAUNCHED("k_pair_keys");
+  hipLaunchKernelGGL(k_pair_count, dim3(grid_for(P, 256, 16384)), dim3(256), 0, s, L.pair_row, P,
+                     reinterpret_cast<uint32_t *>(L.rpp));
+  PP_LAUNCHED("k_pair_count");
   st = exscan_u32(reinterpret_cast<uint32_t *>(L.rpp), reinterpret_cast<uint32_t *>(L.rpp), n + 1,
                   L.seg_scan, nullptr, s);
   if (st != PP_OK) return st;
-  const int32_t rbits = 32 - __builtin_clz(uint32_t(n - 1));
-  st = radix_sort_pingpong(keys, keys_b, P, rbits, L.seg_cnt, L.seg_scan, s);
-  if (st != PP_OK) return st;
-  hipLaunchKernelGGL(k_pair_index, dim3(grid_for(P, 256, 16384)), dim3(256), 0, s, keys, P,
-                     L.pidx);
+  int32_t *cursor = reinterpret_cast<int32_t *>(L.keys_out);
+  if ((st = copy_bytes(cursor, L.rpp, size_t(n + 1) * 4, s)) != PP_OK) return st;
+  for (int32_t d = 0; d < ns; ++d) {
+    const int64_t p0 = info[3 + d], p1 = info[4 + d];
+    if (p1 > p0)
+      hipLaunchKernelGGL(k_pair_place, dim3(grid_for(p1 - p0, 256, 8192)), dim3(256), 0, s,
+                         L.pair_row, p0, p1, cursor, L.pidx);
+  }
+  PP_LAUNCHED("k_pair_place");
   const int32_t ncomb = int32_t((n + P + kCombItems - 1) / kCombItems);
   hipLaunchKernelGGL(k_comb_bounds, dim3(grid_for(int64_t(ncomb) + 1, 256, 4096)), dim3(256), 0, s,
                      L.rpp, n32, ncomb, L.cstart);
-  PP_LAUNCHED("k_pair_index/k_comb_bounds");
+  PP_LAUNCHED("k_comb_bounds");
   *out = si;
   return PP_OK;
 }
