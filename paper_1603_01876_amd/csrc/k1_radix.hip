@@ -51,39 +51,29 @@ __device__ __forceinline__ void store_key(const RadixOut &out, int64_t pos, uint
   }
 }
 
-// Per-tile digit counts -> counts[d * ntiles + tile].  With kCheck, also
-// validates the raw int64 input (range and, optionally, lo non-decreasing).
-template <bool kSep, bool kCheck>
+// Per-tile digit counts -> counts[d * ntiles + tile].  The digit comes from
+// hi alone, so from two int64 arrays only hi is read.
+template <bool kSep>
 __global__ __launch_bounds__(kThreads) void k_radix_count(RadixIn in, int64_t m, int shift,
                                                           int bits, int64_t ntiles,
-                                                          uint32_t *__restrict__ counts,
-                                                          int64_t check_n, int check_sorted,
-                                                          uint32_t *flag) {
+                                                          uint32_t *__restrict__ counts) {
   __shared__ uint32_t wh[kWaves][256];
   for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&wh[0][0])[i] = 0u;
   __syncthreads();
   const int w = threadIdx.x / kWave;
   const int64_t base = int64_t(blockIdx.x) * kTile + int64_t(w) * kWaveKeys;
   const uint32_t dmask = (1u << bits) - 1u;
-  uint32_t bad = 0;
   for (int r = 0; r < kPerThread; ++r) {
     const int64_t i = base + r * kWave + lane_id();
     const bool valid = i < m;
     uint64_t key = 0;
     if (valid) {
-      if constexpr (kSep && kCheck) {
-        const int64_t hi = in.hi[i], lo = in.lo[i];
-        if (hi < 0 || hi >= check_n || lo < 0 || lo >= check_n) bad |= 1u;
-        if (check_sorted && i > 0 && in.lo[i - 1] > lo) bad |= 2u;
-        key = (uint64_t(hi) << 32) | (uint64_t(lo) & 0xFFFFFFFFull);
-      } else {
-        key = load_key<kSep>(in, i);
-      }
+      if constexpr (kSep)
+        key = uint64_t(in.hi[i]) << 32;
+      else
+        key = in.packed[i];
     }
     wave_digit_rank(digit_of(key, shift, dmask), valid, bits, wh[w]);
-  }
-  if constexpr (kCheck) {
-    if (bad) atomicOr(flag, bad);
   }
   __syncthreads();
   for (int d = threadIdx.x; d <= int(dmask); d += kThreads)
@@ -94,11 +84,17 @@ __global__ __launch_bounds__(kThreads) void k_radix_count(RadixIn in, int64_t m,
 // (keys of that digit in earlier waves) + (its rank in its wave).  The tile
 // is first written to LDS in digit order, then read back in that order and
 // stored, so consecutive lanes store consecutive addresses of one digit's
-// run instead of 64 different buckets per instruction.
+// run instead of 64 different buckets per instruction.  With check_n > 0
+// (first pass over two int64 arrays) it also validates the raw input: both
+// labels in [0, check_n), and with check_sorted lo non-decreasing; flag
+// bits 1 / 2 report failures.  Positions depend only on the masked digits
+// the count pass saw, so every store stays in range whatever the input.
 template <bool kSrcSep, bool kDstSep>
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(RadixIn in, RadixOut out, int64_t m,
                                                             int shift, int bits, int64_t ntiles,
-                                                            const uint32_t *__restrict__ offsets) {
+                                                            const uint32_t *__restrict__ offsets,
+                                                            int64_t check_n, int check_sorted,
+                                                            uint32_t *flag) {
   __shared__ uint32_t wh[kWaves][256];
   __shared__ uint32_t s_tile_off[256];   // first slot of each digit in the tile
   __shared__ uint32_t s_glob[256];       // global position of that slot
@@ -112,13 +108,26 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(RadixIn in, RadixOut
   const int64_t base = tile0 + int64_t(w) * kWaveKeys;
   uint64_t keys[kPerThread];
   uint32_t rank[kPerThread];
+  uint32_t bad = 0;
 #pragma unroll
   for (int r = 0; r < kPerThread; ++r) {
     const int64_t i = base + r * kWave + lane_id();
     const bool valid = i < m;
-    keys[r] = valid ? load_key<kSrcSep>(in, i) : 0ull;
+    if constexpr (kSrcSep) {
+      if (valid && check_n > 0) {
+        const int64_t hi = in.hi[i], lo = in.lo[i];
+        if (hi < 0 || hi >= check_n || lo < 0 || lo >= check_n) bad |= 1u;
+        if (check_sorted && i > 0 && in.lo[i - 1] > lo) bad |= 2u;
+        keys[r] = (uint64_t(hi) << 32) | (uint64_t(lo) & 0xFFFFFFFFull);
+      } else {
+        keys[r] = valid ? load_key<kSrcSep>(in, i) : 0ull;
+      }
+    } else {
+      keys[r] = valid ? load_key<kSrcSep>(in, i) : 0ull;
+    }
     rank[r] = wave_digit_rank(digit_of(keys[r], shift, dmask), valid, bits, wh[w]);
   }
+  if (bad && flag) atomicOr(flag, bad);
   __syncthreads();
   // Per digit: prefix over waves (in place), tile total, then an exclusive
   // scan over digits gives each digit's first slot in the tile.
@@ -210,13 +219,13 @@ pp_status radix_sort_pingpong(uint64_t *a, uint64_t *b, int64_t m, int32_t key_b
     const int bits = base_bits + (p < extra ? 1 : 0);
     const RadixIn in{src, nullptr, nullptr};
     const RadixOut out{dst, nullptr, nullptr};
-    hipLaunchKernelGGL((k_radix_count<false, false>), grid, block, 0, s, in, m, shift, bits,
-                       ntiles, counts, int64_t(0), 0, nullptr);
+    hipLaunchKernelGGL((k_radix_count<false>), grid, block, 0, s, in, m, shift, bits, ntiles,
+                       counts);
     PP_LAUNCHED("k_radix_count (pingpong)");
     pp_status st = exscan_u32(counts, counts, (int64_t(1) << bits) * ntiles, scan_ws, nullptr, s);
     if (st != PP_OK) return st;
     hipLaunchKernelGGL((k_radix_scatter<false, false>), grid, block, 0, s, in, out, m, shift,
-                       bits, ntiles, counts);
+                       bits, ntiles, counts, int64_t(0), 0, nullptr);
     PP_LAUNCHED("k_radix_scatter (pingpong)");
     shift += bits;
     uint64_t *t = src;
@@ -247,18 +256,32 @@ pp_status radix_sort(RadixIn in, RadixOut out, int64_t m, int32_t key_bits, void
     const bool src_sep = src.packed == nullptr;
     const bool dst_sep = dst.packed == nullptr;
     const dim3 grid = dim3(static_cast<unsigned>(ntiles)), block = dim3(kThreads);
-    if (src_sep) {
-      if (first && check)
-        hipLaunchKernelGGL((k_radix_count<true, true>), grid, block, 0, s, src, m, shift, bits,
-                           ntiles, L.counts, check_n, int(check_sorted_lo), flag);
-      else
-        hipLaunchKernelGGL((k_radix_count<true, false>), grid, block, 0, s, src, m, shift, bits,
-                           ntiles, L.counts, int64_t(0), 0, flag);
-    } else {
-      hipLaunchKernelGGL((k_radix_count<false, false>), grid, block, 0, s, src, m, shift, bits,
-                         ntiles, L.counts, int64_t(0), 0, flag);
-    }
+    if (src_sep)
+      hipLaunchKernelGGL((k_radix_count<true>), grid, block, 0, s, src, m, shift, bits, ntiles,
+                         L.counts);
+    else
+      hipLaunchKernelGGL((k_radix_count<false>), grid, block, 0, s, src, m, shift, bits, ntiles,
+                         L.counts);
     PP_LAUNCHED("k_radix_count");
+    // Digit-major table: only the 2^bits rows this pass wrote are scanned.
+    pp_status st = exscan_u32(L.counts, L.counts, (int64_t(1) << bits) * ntiles, L.scan_ws, nullptr, s);
+    if (st != PP_OK) return st;
+    // The first pass validates the input while it moves it.
+    const int64_t cn = first && check ? check_n : 0;
+    const int cs = int(check_sorted_lo);
+    if (src_sep && dst_sep)
+      hipLaunchKernelGGL((k_radix_scatter<true, true>), grid, block, 0, s, src, dst, m, shift,
+                         bits, ntiles, L.counts, cn, cs, flag);
+    else if (src_sep)
+      hipLaunchKernelGGL((k_radix_scatter<true, false>), grid, block, 0, s, src, dst, m, shift,
+                         bits, ntiles, L.counts, cn, cs, flag);
+    else if (dst_sep)
+      hipLaunchKernelGGL((k_radix_scatter<false, true>), grid, block, 0, s, src, dst, m, shift,
+                         bits, ntiles, L.counts, int64_t(0), 0, flag);
+    else
+      hipLaunchKernelGGL((k_radix_scatter<false, false>), grid, block, 0, s, src, dst, m, shift,
+                         bits, ntiles, L.counts, int64_t(0), 0, flag);
+    PP_LAUNCHED("k_radix_scatter");
     if (first && check && sync_after_first_pass) {
       uint32_t h = 0;
       PP_HIP(hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, s));
@@ -266,22 +289,6 @@ pp_status radix_sort(RadixIn in, RadixOut out, int64_t m, int32_t key_bits, void
       if (h & 1u) return fail(PP_EINVAL, "input label outside [0, %lld)", (long long)check_n);
       if (h & 2u) return fail(PP_EINVAL, "input not sorted by start vertex");
     }
-    // Digit-major table: only the 2^bits rows this pass wrote are scanned.
-    pp_status st = exscan_u32(L.counts, L.counts, (int64_t(1) << bits) * ntiles, L.scan_ws, nullptr, s);
-    if (st != PP_OK) return st;
-    if (src_sep && dst_sep)
-      hipLaunchKernelGGL((k_radix_scatter<true, true>), grid, block, 0, s, src, dst, m, shift,
-                         bits, ntiles, L.counts);
-    else if (src_sep)
-      hipLaunchKernelGGL((k_radix_scatter<true, false>), grid, block, 0, s, src, dst, m, shift,
-                         bits, ntiles, L.counts);
-    else if (dst_sep)
-      hipLaunchKernelGGL((k_radix_scatter<false, true>), grid, block, 0, s, src, dst, m, shift,
-                         bits, ntiles, L.counts);
-    else
-      hipLaunchKernelGGL((k_radix_scatter<false, false>), grid, block, 0, s, src, dst, m, shift,
-                         bits, ntiles, L.counts);
-    PP_LAUNCHED("k_radix_scatter");
     shift += bits;
   }
   return PP_OK;
