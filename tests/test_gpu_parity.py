@@ -115,6 +115,30 @@ def test_sort_rejects_out_of_range():
     assert e.value.status == pp.PP_EINVAL
 
 
+@pytest.mark.parametrize("where", [0, 4095, 4096, 3 * 4096 + 16])
+@pytest.mark.parametrize("which", ["u", "v", "negative"])
+def test_sort_rejects_bad_label_in_any_tile(where, which):
+    # One bad label anywhere in four 4096-key tiles (the last one ragged) is
+    # caught, and the check does not stick: a valid call right after works.
+    m = 3 * 4096 + 17
+    rng = np.random.default_rng(where)
+    u = rng.integers(0, 1 << 12, m)
+    v = rng.integers(0, 1 << 12, m)
+    if which == "u":
+        u[where] = 1 << 12
+    elif which == "v":
+        v[where] = 1 << 12
+    else:
+        u[where] = -1
+    with pytest.raises(pp.PPError) as e:
+        pp.sort(12, dev(u), dev(v))
+    assert e.value.status == pp.PP_EINVAL
+    u[where] = v[where] = 7
+    us, vs = pp.sort(12, dev(u), dev(v))
+    ous, ovs = oracle.sort(12, u, v)
+    assert np.array_equal(host(us), ous) and np.array_equal(host(vs), ovs)
+
+
 # ----------------------------------------------------- K1 ordered by (u, v)
 @pytest.mark.parametrize("scale", [1, 3, 8, 9, 10, 16, 20])
 def test_sort_uv_pipeline_matches_oracle(scale):
@@ -229,6 +253,24 @@ def test_filter_rejects_unsorted_input():
     with pytest.raises(pp.PPError) as e:
         pp.filter(4, u, v)
     assert e.value.status == pp.PP_EINVAL
+
+
+@pytest.mark.parametrize("where", [1, 64, 4095, 4096, 2 * 4096 + 5])
+def test_filter_rejects_one_descent_at_any_position(where):
+    # u sorted except u[where-1] > u[where] (inside a wave, across waves and
+    # across 4096-key tiles); the sorted input right after is filtered as the
+    # oracle filters it.
+    m = 3 * 4096 + 17
+    rng = np.random.default_rng(where)
+    u = np.sort(rng.integers(0, 4000, m))
+    v = rng.integers(0, 1 << 12, m)
+    bad = u.copy()
+    bad[where - 1] = u[where] + 1
+    with pytest.raises(pp.PPError) as e:
+        pp.filter(12, dev(bad), dev(v))
+    assert e.value.status == pp.PP_EINVAL
+    us, vs = oracle.sort(12, u, v)
+    check_filter(12, us, vs, "f32")
 
 
 # ---------------------------------------------------------------- K3 init
