@@ -155,6 +155,30 @@ def test_pagerank_converge_rejects_bad_args():
     assert call(csr=native._Csr(1 << 30, (1 << 31) - 10, 1 << 31, 8, 16, 24)) == native.PP_ERANGE
 
 
+def test_pagerank_graphs_rejects_bad_args():
+    # Every call below fails a host-side check before anything is enqueued,
+    # so the descriptor and workspace addresses are never dereferenced.
+    L = native.lib()
+    mx = native.graphs_max_n("f32")
+    assert mx > 0 and mx % 64 == 0
+    assert 0 < native.graphs_max_n("f64") <= mx      # two n-vectors of 8 B instead of 4 B
+
+    def call(ng=4, g=16, max_n=64, dt=1, iters=20, damp=0.85, use_graph=0, ws=64, wsb=1 << 20,
+             stream=None):
+        return L.pp_pagerank_graphs(ng, g, max_n, dt, iters, damp, use_graph, ws, wsb, stream)
+
+    assert call(ng=0) == native.PP_EINVAL
+    assert call(g=None) == native.PP_EINVAL
+    assert call(dt=5) == native.PP_EINVAL
+    assert call(iters=-1) == native.PP_EINVAL
+    assert call(damp=1.5) == native.PP_EINVAL
+    assert call(max_n=0) == native.PP_ERANGE
+    assert call(max_n=mx + 64) == native.PP_ERANGE
+    assert call(use_graph=1) == native.PP_EINVAL      # capture needs a stream
+    assert call(ws=None) == native.PP_EWORKSPACE
+    assert call(wsb=1) == native.PP_EWORKSPACE
+
+
 def test_edge_file_calls_reject_bad_args(tmp_path):
     L = native.lib()
     assert native.workspace_bytes(native.TSV_FORMAT, 0, 32, "f64", 3) > 0
