@@ -1824,10 +1824,9 @@ Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs, size_t *byte
     L.seg_val = c.take<V>(size_t(z));
     L.prp = c.take<int32_t>(size_t(z + 1));
     L.pair_row = c.take<int32_t>(size_t(z));
-    // The partials are written only by the iterations; during the build
-    // the same bytes hold the keys of the pairs' row-major sort (8 B per
-    // pair, so the region keeps 8 B per entry for FP32 too).
-    L.seg_part = reinterpret_cast<typename Form<V>::Part *>(c.take<uint64_t>(size_t(z)));
+    // One partial per pair (at most one pair per entry), written by the
+    // iterations.
+    L.seg_part = c.take<typename Form<V>::Part>(size_t(z));
     const int64_t wcnt = int64_t(kMaxWins) * (z / kWinTile + z * (kWinRowCost + 1) / kWinBlock + 4);
     const int64_t cnt_n = kMaxSlabs * ntiles > wcnt ? kMaxSlabs * ntiles : wcnt;
     L.seg_cnt = c.take<uint32_t>(size_t(cnt_n));
