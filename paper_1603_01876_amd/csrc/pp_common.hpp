@@ -63,15 +63,19 @@ __device__ __forceinline__ uint64_t lanes_below() {
 // Rank of this lane's digit d among the earlier lanes of the wave holding
 // the same digit, plus the wave's running count wh[d] of that digit from
 // earlier calls; advances wh[d] by the digit's lanes in this call.  Digits
-// have `bits` bits and are matched with one ballot per bit.  Stable: lanes
-// and calls are ranked in order.
+// have `bits` (<= 8) bits and are matched with one ballot per bit (the loop
+// is unrolled to 8 steps with a uniform guard).  Stable: lanes and calls
+// are ranked in order.
 __device__ __forceinline__ uint32_t wave_digit_rank(uint32_t d, bool valid, int bits,
                                                     uint32_t *wh) {
   uint64_t match = __ballot(valid);
-  for (int b = 0; b < bits; ++b) {
-    const bool bit = (d >> b) & 1u;
-    const uint64_t bal = __ballot(bit);
-    match &= bit ? bal : ~bal;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    if (b < bits) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bal = __ballot(bit);
+      match &= bit ? bal : ~bal;
+    }
   }
   const uint64_t below = match & lanes_below();
   uint32_t before = 0;
