@@ -73,7 +73,8 @@ __global__ __launch_bounds__(kThreads) void k_radix_count(RadixIn in, int64_t m,
       else
         key = in.packed[i];
     }
-    wave_digit_rank(digit_of(key, shift, dmask), valid, bits, wh[w]);
+    // Counts need no order: one LDS add per key into the wave's own bins.
+    if (valid) atomicAdd(&wh[w][digit_of(key, shift, dmask)], 1u);
   }
   __syncthreads();
   for (int d = threadIdx.x; d <= int(dmask); d += kThreads)
