@@ -40,13 +40,30 @@ __device__ __forceinline__ bool kept(const uint64_t *keepw, int32_t w) {
   return (keepw[w >> 6] >> (w & 63)) & 1ull;
 }
 
+// The previous lane's 64-bit value, and lane 63's: a wave reads 64
+// consecutive sorted positions per round, so the key at p - 1 is the
+// previous lane's, or for lane 0 the previous round's lane 63.
+__device__ __forceinline__ uint64_t from_lane_below(uint64_t x) {
+  const uint32_t lo = uint32_t(__shfl_up(int(uint32_t(x)), 1, kWave));
+  const uint32_t hi = uint32_t(__shfl_up(int(uint32_t(x >> 32)), 1, kWave));
+  return (uint64_t(hi) << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t from_lane63(uint64_t x) {
+  const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(x)), 63));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(x >> 32)), 63));
+  return (uint64_t(hi) << 32) | lo;
+}
+
 // vstart[w] = first sorted position with v >= w, for w = 0..n.
 __global__ __launch_bounds__(256) void k_vstart(const uint64_t *__restrict__ P, int64_t m,
                                                 int32_t n, int32_t *__restrict__ vstart) {
   const int64_t stride = int64_t(gridDim.x) * 256;
   for (int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x; p < m; p += stride) {
     const int32_t v = vof(P[p]);
-    const int32_t vp = p > 0 ? vof(P[p - 1]) : -1;
+    // Lanes holding p are active down to lane 0, so lane - 1 holds p - 1.
+    const int32_t up = __shfl_up(v, 1, kWave);
+    const int32_t vp = lane_id() > 0 ? up : (p > 0 ? vof(P[p - 1]) : -1);
     for (int32_t w = vp + 1; w <= v; ++w) vstart[w] = int32_t(p);
     if (p == m - 1)
       for (int32_t w = v + 1; w <= n; ++w) vstart[w] = int32_t(m);
@@ -118,11 +135,15 @@ __global__ __launch_bounds__(kThreads) void k_compact_count(const uint64_t *__re
   const int w = threadIdx.x / kWave;
   const int64_t base = int64_t(blockIdx.x) * kTile + int64_t(w) * kWaveKeys;
   uint32_t c = 0;
+  uint64_t carry = 0;   // key of the previous round's lane 63
   for (int r = 0; r < kPerThread; ++r) {
     const int64_t p = base + r * kWave + lane_id();
+    const uint64_t key = p < m ? P[p] : 0ull;
+    const uint64_t below = from_lane_below(key);
+    const uint64_t prev = lane_id() > 0 ? below : r > 0 ? carry : p > 0 && p <= m ? P[p - 1] : ~0ull;
+    carry = from_lane63(key);
     if (p < m) {
-      const uint64_t key = P[p];
-      const bool distinct = p == 0 || P[p - 1] != key;
+      const bool distinct = p == 0 || prev != key;
       if (kept(keepw, vof(key)))
         c += distinct ? 1u : 0u;
       else
@@ -145,14 +166,17 @@ __global__ __launch_bounds__(kThreads) void k_compact_emit(
   uint64_t keys[kPerThread];
   uint64_t ball[kPerThread];
   uint32_t run = 0;
+  uint64_t first_prev = ~0ull;   // key at base - 1 (lane 0 only)
+  if (lane == 0 && base > 0 && base <= m) first_prev = P[base - 1];
 #pragma unroll
   for (int r = 0; r < kPerThread; ++r) {
     const int64_t p = base + r * kWave + lane;
+    const uint64_t key = p < m ? P[p] : 0ull;
+    const uint64_t below = from_lane_below(key);
+    const uint64_t prev = lane > 0 ? below : r > 0 ? from_lane63(keys[r - 1]) : first_prev;
     bool f = false;
-    uint64_t key = 0;
     if (p < m) {
-      key = P[p];
-      const bool distinct = p == 0 || P[p - 1] != key;
+      const bool distinct = p == 0 || prev != key;
       f = distinct && kept(keepw, vof(key));
     }
     keys[r] = key;
@@ -166,6 +190,8 @@ __global__ __launch_bounds__(kThreads) void k_compact_emit(
 #pragma unroll
   for (int r = 0; r < kPerThread; ++r) {
     const int64_t p = base + r * kWave + lane;
+    const uint64_t below = from_lane_below(keys[r]);
+    const uint64_t prevk = lane > 0 ? below : r > 0 ? from_lane63(keys[r - 1]) : first_prev;
     if (p < m) {
       const uint64_t key = keys[r];
       const bool f = (ball[r] >> lane) & 1ull;
@@ -180,7 +206,7 @@ __global__ __launch_bounds__(kThreads) void k_compact_emit(
         val[excl] = V(quot);
       }
       // Row pointers of every column that starts here (empty ones too).
-      const int32_t vp = p > 0 ? vof(P[p - 1]) : -1;
+      const int32_t vp = p > 0 ? vof(prevk) : -1;
       for (int32_t j = vp + 1; j <= v; ++j) row_ptr[j] = int32_t(excl);
       if (p == m - 1) {
         const int32_t z = int32_t(excl + (f ? 1u : 0u));
