@@ -5,11 +5,13 @@ A step is one pass of the whole pipeline over one synthetic Kronecker graph
 held in HBM: K0 generate, K1 sort, K2 filter (into CSR(A^T)), K3 PageRank
 (initial vector + 20 damped iterations).  The headline metric is the
 paper's K3 rate, 20*M / t_K3 edges per second (Sec. IV.D), on the largest
-single-GPU instance (S = 26, M = 2^30 edges, FP32 values and ranks with
-compensated row sums, FP64 sum(r) and teleport).  K1 and K2 rates (M/t,
-Sec. IV.B and IV.C) and the FP64 form on the same graph are reported beside
-it.  The roofline object prices the SpMV kernel's algorithmic HBM bytes
-against its average launch time, timed with HIP events on its stream.
+single-GPU instance (S = 26, M = 2^30 edges) at the paper's precision (FP64
+values and ranks).  K1 and K2 rates (M/t, Sec. IV.B and IV.C) and the FP32
+form (FP32 values and ranks, compensated row sums, FP64 sum(r) and
+teleport) on the same graph are reported beside it, each with its error
+against the oracle's ranks stored for this graph.  The roofline object
+prices the SpMV iteration's algorithmic HBM bytes against its average
+duration, timed with HIP events on its stream.
 """
 from __future__ import annotations
 
@@ -24,6 +26,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+# L2 tag lookups: 16 channels per XCD, 8 XCDs, one 128 B lookup per channel
+# per clock at the 2.4 GHz peak engine clock (a model figure, not measured).
+L2_REQ_PEAK = 16 * 8 * 2.4e9
+METRIC = "K3 PageRank edges/s (M\u00b720/t) + HBM GB/s, FP64 vs FP32 vs batched-RHS"
 
 
 def log(msg):
@@ -36,11 +42,15 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--scale", type=int, default=26)
-    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--dtype", default="f64", choices=["f32", "f64"],
+                    help="value type of the timed run (the other one runs beside it)")
     ap.add_argument("--iters", type=int, default=20)
-    ap.add_argument("--no-f64-side", action="store_true", help="skip the FP64 side-by-side run")
+    ap.add_argument("--no-side", action="store_true",
+                    help="skip the side-by-side run in the other value type")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-k12-scale", type=int, default=21,
+                    help="graph scale of the oracle's K1/K2 timing")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-RHS form (S=22, 32 right-hand sides)")
     ap.add_argument("--batched-scale", type=int, default=22)
@@ -118,6 +128,18 @@ def measured_traffic(scale: int, dtype: str, cfg, relabel: bool):
     return out
 
 
+def limiter(mt):
+    """What binds the dominant kernel, from the committed counters: the raw
+    SpMV's L1-to-L2 read requests per second against the L2's tag-lookup
+    rate, beside its HBM bytes.  None without a matching summary."""
+    if not mt or "l2" not in mt:
+        return None
+    l2 = mt["l2"]
+    return {"resource": "L2 request rate (one request per gathered value of r)",
+            "requests_per_s": l2["requests_per_s"], "model_peak_requests_per_s": L2_REQ_PEAK,
+            "frac": l2["requests_per_s"] / L2_REQ_PEAK, "source": l2["source"]}
+
+
 def copy_ceiling(torch, nbytes=1 << 31, reps=5):
     """Streaming-copy bandwidth of the device (read + write bytes per second
     of a plain device-to-device copy), the practical ceiling beside the
@@ -141,15 +163,15 @@ def copy_ceiling(torch, nbytes=1 << 31, reps=5):
 def spmv_label(cfg, dt):
     v = "float" if dt == "f32" else "double"
     if cfg[2] > 0:
-        hot = f"k_spmv_win<{v}> (slab 0 through LDS windows) + " if cfg[3] == 1 else ""
-        return (f"segmented SpMV iteration, slabs of 2^{cfg[2]} columns: {hot}"
+        return (f"segmented SpMV iteration, slabs of 2^{cfg[2]} columns: "
                 f"k_spmv<{v},{cfg[0]},raw> + k_fix_raw<{v}> + k_seg_combine<{v}> + k_sum_blocks")
     return f"k_spmv<{v},{cfg[0]}> + k_finish<{v}>"
 
 
 def batched_form(args, pp, workloads, torch):
     """K3 with nrhs independent vectors on one S=22 matrix (one SpMM per
-    iteration) beside nrhs-times the single-vector FP32 run."""
+    iteration) beside nrhs times the single-vector run, in FP32 and in FP64
+    (the batched form's speed-up and error against each)."""
     S, k, dev = args.batched_scale, args.nrhs, "cuda"
     spec = workloads.pipeline(S)
     n, m = spec.n, spec.m
@@ -157,10 +179,11 @@ def batched_form(args, pp, workloads, torch):
     us, vs = pp.sort(S, u, v)
     del u, v
     AT, _, d_out = pp.filter(S, us, vs, "f32")
+    AT64, _, _ = pp.filter(S, us, vs, "f64", degrees=False)
     del us, vs
     w = None if args.no_relabel else d_out
     ws = torch.empty(max(pp.workspace_bytes(pp.K3, n, AT.nnz, "f32", k),
-                         pp.workspace_bytes(pp.K3, n, AT.nnz, "f32", 1)),
+                         pp.workspace_bytes(pp.K3, n, AT.nnz, "f64", 1)),
                      dtype=torch.uint8, device=dev)
     tuned = None
     if not args.no_tune:
@@ -204,19 +227,37 @@ def batched_form(args, pp, workloads, torch):
 
     run_1()
     t1, k1 = timed(run_1)
+    # The same single vector at the paper's precision (FP64 values and ranks).
+    r64 = torch.empty(n, dtype=torch.float64, device=dev)
+    w64 = w
+    if not args.no_tune:
+        t64cfg = autotune.tune(AT64, "f64", 1, w, ws=ws, iters=args.iters, force=True)
+        w64 = w if t64cfg["relabel"] else None
+
+    def run_64():
+        pp.init_r(n, workloads.BASE_SEED, "f64", 1, out=r64, ws=ws)
+        pp.pagerank(AT64, r64, iters=args.iters, c=workloads.DAMPING, sums=False, ws=ws,
+                    weights=w64)
+
+    run_64()
+    t64, _ = timed(run_64)
     pp.set_k3_config(*saved)
     err = float((rk[:, 0].double() - r1.double()).abs().sum() / r1.double().abs().sum())
+    err64 = float((rk[:, 0].double() - r64).abs().sum() / r64.abs().sum())
     nbytes = 4 * (n + 1) + 8 * AT.nnz + 8 * n * k
     out = {"workload": f"kron-s{S}-f32-rhs{k}", "nrhs": k, "nnz_filtered": AT.nnz,
            "k3_ms": tk * 1e3, "rhs_edges_per_s": args.iters * m * k / tk,
            "single_rhs_k3_ms": t1 * 1e3, "single_rhs_edges_per_s": args.iters * m / t1,
            "per_rhs_speedup_over_single": t1 * k / tk,
+           "single_rhs_f64_k3_ms": t64 * 1e3,
+           "per_rhs_speedup_over_single_f64": t64 * k / tk,
+           "rel_l1_rhs0_vs_single_f64": err64,
            "spmm_avg_ms": kk * 1e3, "spmm_GBps": nbytes / kk / 1e9,
            "spmm_frac_of_peak": nbytes / kk / 1e9 / HBM_PEAK_GBS,
            "spmm_algorithmic_bytes_per_launch": nbytes,
            "rel_l1_rhs0_vs_single_f32": err,
            "spmm_config": None if tuned is None else tuned}
-    del AT, ws, rk, r1, d_out
+    del AT, AT64, ws, rk, r1, r64, d_out
     torch.cuda.empty_cache()
     return out
 
@@ -411,11 +452,34 @@ def spmv_bytes(n: int, nnz: int, dtype: str) -> int:
     return 4 * (n + 1) + (4 + w) * nnz + 2 * w * n
 
 
-def cpu_baseline(AT, scale: int, m: int, budget_s: float):
-    """The oracle (single thread, FP64) timed on a contiguous block of rows of
-    the same CSR(A^T): one damped iteration over those rows.  Scaled to K3
-    edges/s: the rows hold a fraction f of the nnz, so the rate is
-    f*M / t_rows (one iteration processes M edges in the paper's metric)."""
+def host_cpu() -> dict:
+    """The host's CPU model and core counts (from /proc/cpuinfo and the
+    scheduler's affinity mask)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"model": model or platform.processor() or platform.machine(),
+            "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
+def cpu_baseline(AT, scale: int, m: int, budget_s: float, k12_scale: int):
+    """The oracle (single thread, FP64) timed on the host: K3 as one damped
+    iteration over a contiguous block of rows of the benchmark's CSR(A^T)
+    (scaled to K3 edges/s: the rows hold a fraction f of the nnz, so the
+    rate is f*M / t_rows, one iteration processing M edges in the paper's
+    metric), and K1 / K2 (M/t) over the whole pipeline of a smaller graph
+    of the same family (scale k12_scale: the oracle's K1 and K2 at the
+    benchmark's scale take minutes).  K0 is untimed, as in the paper."""
     import numpy as np
     import oracle
 
@@ -438,11 +502,58 @@ def cpu_baseline(AT, scale: int, m: int, budget_s: float):
     t = time.perf_counter() - t0
     f = float(rp[rows2]) / float(max(z, 1))
     value = f * m / t
+    del rp, r
+    # K1 and K2 of the oracle on a whole graph of the same family.
+    from paper_1603_01876_amd import workloads
+    spec = workloads.pipeline(k12_scale)
+    p = oracle.Kron(**spec.as_dict())
+    info = host_cpu()
+    u, v = oracle.generate_parallel(p, threads=max(1, min(16, info["usable_cpus"] or 1)))
+    t1 = time.perf_counter()
+    us, vs = oracle.sort(k12_scale, u, v)
+    t2 = time.perf_counter()
+    del u, v
+    fl = oracle.filter(k12_scale, us, vs)
+    t3 = time.perf_counter()
+    del us, vs, fl
     return {"value": value, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle ppo_step_rows (FP64, 1 thread) on rows [0, {rows2}) of the S={scale} "
-                       f"CSR(A^T): {int(rp[rows2])} of {z} nnz ({100*f:.1f}%), one iteration, "
-                       f"{t:.1f} s; rate = fraction * M / t"),
-            "host_cpu": platform.processor() or platform.machine()}
+            "sample": (f"K3: oracle ppo_step_rows (FP64, 1 thread) on rows [0, {rows2}) of the "
+                       f"S={scale} CSR(A^T): {int(f * z)} of {z} nnz ({100*f:.1f}%), one "
+                       f"iteration, {t:.1f} s; rate = fraction * M / t.  K1/K2: oracle ppo_sort "
+                       f"and ppo_filter (1 thread) on the whole S={k12_scale} graph "
+                       f"({spec.m} edges)"),
+            "k1": {"edges_per_s": spec.m / (t2 - t1), "s": t2 - t1, "scale": k12_scale},
+            "k2": {"edges_per_s": spec.m / (t3 - t2), "s": t3 - t2, "scale": k12_scale},
+            "host_cpu": info}
+
+
+def oracle_error(r, scale: int, iters: int, seed: int) -> dict | None:
+    """Error of the GPU's r_iters against the oracle's ranks for the same
+    graph, as stored by tests/golden/make_pipeline_digests.py (an oracle-only
+    script): relative L1 over the stored sample of rows (random rows plus the
+    64 largest ranks), over the 256 block sums of r, and of sum(r); None when
+    no stored values match this workload."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", f"kron_s{scale}_pipeline.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        g = json.load(fh)
+    if g["iterations"] != iters or g["r0_seed"] != seed:
+        return None
+    got = r.double().cpu().numpy()
+    rows = np.asarray(g["r20_rows"], np.int64)
+    want = np.array([float.fromhex(x) for x in g["r20_values"]])
+    out = {"sampled_rows": int(rows.size),
+           "sampled_rel_l1": float(np.abs(got[rows] - want).sum() / np.abs(want).sum())}
+    if "r20_block_sums" in g:
+        wb = np.array([float.fromhex(x) for x in g["r20_block_sums"]])
+        gb = got.reshape(wb.size, -1).sum(axis=1)
+        out["block_sums_rel_l1"] = float(np.abs(gb - wb).sum() / np.abs(wb).sum())
+    wl1 = float.fromhex(g["r20_l1"])
+    out["l1_rel"] = float(abs(np.abs(got).sum() / wl1 - 1))
+    out["source"] = os.path.relpath(path, ROOT)
+    return out
 
 
 def _run_rows(oracle, AT, rp, r, r0, r1):
@@ -551,7 +662,7 @@ def main():
     mt = measured_traffic(S, dt, pp.get_k3_config(), state["relabel"])
     log(f"device copy ceiling {copy_bw:.0f} GB/s")
     out = {
-        "metric": "K3 PageRank edges/s (20*M/t_K3)",
+        "metric": METRIC,
         "value": value,
         "unit": "edges/s",
         "n_gpus": 1,
@@ -581,11 +692,11 @@ def main():
                      "traffic_unit": "GB per iteration (rocprofv3 FETCH_SIZE + WRITE_SIZE over the iteration's launches, copy-calibrated)",
                      "algorithmic_bytes_per_launch": nbytes,
                      "copy_GBps": copy_bw, "frac_of_copy": achieved / copy_bw,
-                     "l2_requests": (mt or {}).get("l2")},
+                     "l2_requests": (mt or {}).get("l2"),
+                     "limiter": limiter(mt)},
         "sum_r": {"first": float(sums_h[0]), "last": float(sums_h[-1])},
         "k3_config": {"items_per_thread": pp.get_k3_config()[0],
                       "slab_log2": pp.get_k3_config()[2],
-                      "hot_windows": pp.get_k3_config()[3],
                       "relabel": state["relabel"],
                       "tuned": None if args.no_tune or args.warmup < 1 else tuned["ms"]},
     }
@@ -606,56 +717,63 @@ def main():
             "workload": f"kron-s{S}", "k1_uv_ms": t_uv * 1e3, "k1_uv_edges_per_s": m / t_uv,
             "k1_u_ms": mean["k1"] * 1e3, "cost_over_u_only": t_uv / mean["k1"]}
 
-    if not args.no_f64_side and dt == "f32":
-        log("FP64 side-by-side")
-        r32 = r.double().clone()
-        del ws12
-        AT64 = pp.CSR(n, 0, AT.row_ptr.clone(), torch.empty(m, dtype=torch.int32, device=dev),
-                      torch.empty(m, dtype=torch.float64, device=dev))
-        ws2 = torch.empty(pp.workspace_bytes(pp.K2, n, m), dtype=torch.uint8, device=dev)
-        pp.filter(S, us, vs, "f64", AT=AT64, d_in=d_in, d_out=d_out, ws=ws2)
-        del ws2
-        ws64 = torch.empty(pp.workspace_bytes(pp.K3, n, m, "f64"), dtype=torch.uint8, device=dev)
-        r64 = torch.empty(n, dtype=torch.float64, device=dev)
-        sums64 = torch.empty(args.iters + 1, dtype=torch.float64, device=dev)
+    out["error_vs_oracle"] = {dt: oracle_error(r, S, args.iters, rseed)}
+    if not args.no_side:
+        other = "f32" if dt == "f64" else "f64"
+        log(f"{other.upper()} side by side")
+        odt = torch.float32 if other == "f32" else torch.float64
+        r_main = r.double().clone()
+        ATo = pp.CSR(n, 0, torch.empty(n + 1, dtype=torch.int32, device=dev),
+                     torch.empty(m, dtype=torch.int32, device=dev),
+                     torch.empty(m, dtype=odt, device=dev))
+        pp.filter(S, us, vs, other, AT=ATo, d_in=d_in, d_out=d_out, ws=ws12)
+        need = pp.workspace_bytes(pp.K3, n, m, other)
+        wso = ws3 if ws3.numel() >= need else torch.empty(need, dtype=torch.uint8, device=dev)
+        ro = torch.empty(n, dtype=odt, device=dev)
+        sums_o = torch.empty(args.iters + 1, dtype=torch.float64, device=dev)
         saved = pp.get_k3_config()
-        w64 = None if args.no_relabel else d_out
-        tuned64 = None
+        wo = None if args.no_relabel else d_out
+        tuned_o = None
         if not args.no_tune:
             from paper_1603_01876_amd import autotune
-            tuned64 = autotune.tune(AT64, "f64", 1, w64, ws=ws64, iters=args.iters, force=True)
-            if not tuned64["relabel"]:
-                w64 = None
-        cfg64 = pp.get_k3_config()
+            tuned_o = autotune.tune(ATo, other, 1, wo, ws=wso, iters=args.iters, force=True)
+            if not tuned_o["relabel"]:
+                wo = None
+        cfg_o = pp.get_k3_config()
         times = []
         pp.set_kernel_timing(True)
-        spmv64 = []
+        spmv_o = []
         for _ in range(3):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            pp.init_r(n, rseed, "f64", out=r64, ws=ws64)
-            pp.pagerank(AT64, r64, iters=args.iters, c=workloads.DAMPING, sums=sums64, ws=ws64,
-                        weights=w64)
+            pp.init_r(n, rseed, other, out=ro, ws=wso)
+            pp.pagerank(ATo, ro, iters=args.iters, c=workloads.DAMPING, sums=sums_o, ws=wso,
+                        weights=wo)
             e1.record()
-            spmv64 += pp.kernel_times()
+            spmv_o += pp.kernel_times()
             torch.cuda.synchronize()
             times.append(e0.elapsed_time(e1) / 1e3)
         pp.set_kernel_timing(False)
         pp.set_k3_config(*saved)
-        t64 = sum(times) / len(times)
-        s64 = sum(spmv64) / len(spmv64) / 1e3
-        err = float((r32 - r64).abs().sum() / r64.abs().sum())
-        b64 = spmv_bytes(n, AT64.nnz, "f64")
-        out.setdefault("forms", {}).update({
-            "f64": {"k3_edges_per_s": args.iters * m / t64, "k3_ms": t64 * 1e3,
-                    "spmv_avg_ms": s64 * 1e3, "spmv_GBps": b64 / s64 / 1e9,
-                    "spmv_frac_of_peak": b64 / s64 / 1e9 / HBM_PEAK_GBS,
-                    "kernel": spmv_label(cfg64, "f64"), "relabel": w64 is not None,
-                    "tuned": None if tuned64 is None else tuned64["ms"]},
-            "f32_speedup_over_f64": t64 / mean["k3"],
-            "f32_rel_l1_vs_f64_gpu": err,
-        })
-        del AT64, ws64
+        t_o = sum(times) / len(times)
+        s_o = sum(spmv_o) / len(spmv_o) / 1e3
+        b_o = spmv_bytes(n, ATo.nnz, other)
+        out.setdefault("forms", {})[other] = {
+            "workload": f"kron-s{S}-{other}", "k3_edges_per_s": args.iters * m / t_o,
+            "k3_ms": t_o * 1e3, "spmv_avg_ms": s_o * 1e3, "spmv_GBps": b_o / s_o / 1e9,
+            "spmv_frac_of_peak": b_o / s_o / 1e9 / HBM_PEAK_GBS,
+            "kernel": spmv_label(cfg_o, other), "relabel": wo is not None,
+            "k3_config": list(cfg_o),
+            "tuned": None if tuned_o is None else tuned_o["ms"]}
+        t32, t64 = (mean["k3"], t_o) if dt == "f32" else (t_o, mean["k3"])
+        r32, r64 = (r_main, ro.double()) if dt == "f32" else (ro.double(), r_main)
+        out["f32_speedup_over_f64"] = t64 / t32
+        out["f32_rel_l1_vs_f64_gpu"] = float((r32 - r64).abs().sum() / r64.abs().sum())
+        out["error_vs_oracle"][other] = oracle_error(ro, S, args.iters, rseed)
+        del ATo, ro, r_main, r32, r64
+        if wso is not ws3:
+            del wso
+        torch.cuda.empty_cache()
 
     if not args.no_converge:
         log("run to convergence")
@@ -682,7 +800,7 @@ def main():
 
     if not args.no_cpu:
         log("CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(AT, S, m, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(AT, S, m, args.cpu_seconds, args.cpu_k12_scale)
 
     print(json.dumps(out), flush=True)
 

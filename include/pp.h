@@ -82,8 +82,8 @@ typedef struct {
   void *val;
 } pp_csr;
 
-/* One graph of a pp_pagerank_graphs batch (the descriptor table itself is
- * device memory, and so are the arrays it points to):
+/* One graph of a pp_pagerank_graphs batch (the descriptor table is host
+ * memory; the arrays it points to are device memory):
  * CSR(A^T) with n rows and nnz entries (as written by pp_filter, values of
  * the batch's dtype), the output vector r (n entries), optional sums
  * (iters+1 FP64 entries, NULL = not returned) and the seed of the graph's
@@ -270,19 +270,22 @@ pp_status pp_pagerank_converge(const pp_csr *AT, pp_dtype dt, int32_t max_iters,
 /* K3 (Sec. IV.D) for a batch of independent small graphs in one persistent
  * launch: for every graph, r_0 as pp_init_r (right-hand side 0, the graph's
  * seed) followed by `iters` iterations as pp_pagerank, with r and the
- * iterate held in on-chip memory.  graphs is a DEVICE array of ngraphs
- * descriptors owned by the caller; workgroups take graphs in array order,
- * so listing the largest first balances the launch.  max_n bounds the
- * vertex count of every graph and must not exceed pp_graphs_max_n(dt)
- * (PP_ERANGE).  A graph with n > max_n or malformed fields is skipped and
- * its r left untouched.  use_graph != 0 records the launch into a hipGraph
- * on first use and replays it on later calls with the same arguments
- * (stream must not be NULL then; the replay reads the descriptor table
- * and the workspace as they are at that time); use_graph == 0 launches
- * directly.  Workspace: pp_workspace_bytes(PP_K3_GRAPHS, 1, ngraphs, dt, 1);
- * calls sharing a workspace must not overlap. */
-pp_status pp_pagerank_graphs(int32_t ngraphs, const pp_graph *graphs, int64_t max_n, pp_dtype dt,
-                             int32_t iters, double c, int32_t use_graph, void *ws, size_t ws_bytes,
+ * iterate held in on-chip memory.  graphs is a [host] array of ngraphs
+ * descriptors (the arrays they point to are device memory); it is read
+ * during the call and copied into the workspace ahead of the launch.
+ * Workgroups take graphs in array order, so listing the largest first
+ * balances the launch.  Every descriptor is checked on the host before
+ * anything is enqueued: n in [1, pp_graphs_max_n(dt)] (PP_ERANGE above it),
+ * nnz >= 0, n + nnz < 2^31 (PP_ERANGE), row_ptr and r present, col and val
+ * present when nnz > 0 (PP_EINVAL); a failed check launches nothing and
+ * leaves every output untouched.  use_graph != 0 records the launch into a
+ * hipGraph on first use and replays it on later calls with the same
+ * workspace, stream, batch size, iteration count, damping and largest n
+ * (stream must not be NULL then); use_graph == 0 launches directly.
+ * Workspace: pp_workspace_bytes(PP_K3_GRAPHS, 1, ngraphs, dt, 1); calls
+ * sharing a workspace must not overlap. */
+pp_status pp_pagerank_graphs(int32_t ngraphs, const pp_graph *graphs, pp_dtype dt, int32_t iters,
+                             double c, int32_t use_graph, void *ws, size_t ws_bytes,
                              void *stream);
 
 /* Largest n a pp_pagerank_graphs graph may have with value type dt (the
@@ -303,21 +306,13 @@ int64_t pp_graphs_max_n(pp_dtype dt);
  * of 2 MiB of r (2^19 FP32 or 2^18 FP64 vertices) once r exceeds 4 MiB,
  * else one pass.  The segmented layout is built inside each pp_pagerank
  * call, which then synchronizes its stream once to read the number of
- * (slab, row) pairs.  hot_windows in {-1, 0, 1} (segmented runs whose
- * slabs are wider than one 64 KB window of r: 2^14 FP32 or 2^13 FP64
- * columns): 1 processes slab 0 -- the lowest labels, which after
- * relabelling are the most gathered -- in blocks of rows that walk windows
- * of r staged in on-chip memory; 0 (default) treats it like the other
- * slabs; -1 does the former when slab 0 holds at least 8 entries per pair.
- * On the S = 26 Kronecker matrix the window path is slower (5.5 ms against
- * about 3.1 ms for slab 0 through L2), so it is off unless asked for.  Results do not depend on the configuration beyond the order
- * of floating-point sums.  pp_set_k3_config(NULL) restores the defaults
- * (8, 0, -1, -1). */
+ * (slab, row) pairs.  Results do not depend on the configuration beyond
+ * the order of floating-point sums.  pp_set_k3_config(NULL) restores the
+ * defaults (8, 0, -1). */
 typedef struct {
   int32_t items_per_thread;
   int32_t rhs_lanes;
   int32_t slab_log2;
-  int32_t hot_windows;
 } pp_k3_config;
 pp_status pp_set_k3_config(const pp_k3_config *cfg);
 pp_status pp_get_k3_config(pp_k3_config *cfg);

@@ -76,6 +76,9 @@ def lib():
                                    ctypes.c_double, _f64p, _f64p]
         L.ppo_step_rows.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _f64p,
                                     _f64p, ctypes.c_double, ctypes.c_double, _f64p]
+        L.ppo_sum_r.argtypes = [ctypes.c_int64, _f64p, _f64p]
+        L.ppo_digest.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                 ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64)]
         L.ppo_pagerank_converge.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, ctypes.c_int32,
                                             ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                             _f64p, _f64p, _f64p, _i32p]
@@ -344,3 +347,145 @@ def transpose_csr(n: int, rp, col, val):
     np.add.at(trp, col + 1, 1)
     trp = np.cumsum(trp)
     return trp, rows[order].astype(np.int32), np.asarray(val, np.float64)[order]
+
+
+# --------------------------------------------------------------------------
+# Tooling for full-size parity: sums, digests, row blocks
+# --------------------------------------------------------------------------
+def sum_r(r) -> float:
+    """sum(r) exactly as K3 forms it (compensated, ascending index)."""
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    out = np.zeros(1, np.float64)
+    _check(lib().ppo_sum_r(r.size, _p(r, _f64p), _p(out, _f64p)), "sum_r")
+    return float(out[0])
+
+
+def digest(x, index0: int = 0) -> int:
+    """Order-independent 64-bit digest of an array's element bit patterns
+    (4- or 8-byte elements, zero-extended); see ppo_digest."""
+    x = np.ascontiguousarray(x)
+    if x.dtype.itemsize not in (4, 8):
+        raise ValueError(f"digest of {x.dtype} elements")
+    out = ctypes.c_uint64(0)
+    ptr = ctypes.c_void_p(x.ctypes.data if x.size else 0)
+    _check(lib().ppo_digest(ptr, x.size, x.dtype.itemsize, index0, ctypes.byref(out)), "digest")
+    return int(out.value)
+
+
+def digest_add(*parts: int) -> int:
+    """Digests of consecutive pieces add up (mod 2^64) to the whole's."""
+    return sum(parts) % (1 << 64)
+
+
+def _threads(fn, jobs, threads):
+    # The oracle's C functions run with the GIL released (ctypes), so
+    # independent calls overlap on several cores; each call is itself the
+    # plain single-threaded code.
+    from concurrent.futures import ThreadPoolExecutor
+    if threads <= 1:
+        return [fn(j) for j in jobs]
+    with ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(fn, jobs))
+
+
+def generate_parallel(p: Kron, threads: int = 1, chunk: int = 1 << 22):
+    """K0's whole edge list, computed in independent edge ranges (each edge is
+    a pure function of its index, Sec. IV.A), several ranges at a time."""
+    u = np.empty(p.m, dtype=np.int64)
+    v = np.empty(p.m, dtype=np.int64)
+    starts = list(range(0, p.m, chunk))
+
+    def one(e0):
+        k = min(chunk, p.m - e0)
+        _check(lib().ppo_generate_range(ctypes.byref(p._c()), e0, k, 1, _p(u[e0:], _i64p),
+                                        _p(v[e0:], _i64p)), "generate")
+
+    _threads(one, starts, threads)
+    return u, v
+
+
+def filter_blocks(scale: int, u, v, nblocks: int = 8, threads: int = 1):
+    """K2's CSR(A^T) at any scale, built from contiguous blocks of its rows
+    with ppo_filter_rows (each block rescans all edges, so peak memory is the
+    edges plus one block).  Returns (AT_rp int64, AT_col, AT_val, d_in,
+    d_out, mx, nnz) -- the same arrays ppo_filter writes."""
+    u = np.ascontiguousarray(u, dtype=np.int64)
+    v = np.ascontiguousarray(v, dtype=np.int64)
+    n = 1 << scale
+    m = u.size
+    d_in = np.empty(n, np.int64)
+    d_out = np.empty(n, np.int64)
+    mx = np.zeros(1, np.int64)
+    one = np.zeros(2, np.int64)
+    _check(lib().ppo_filter_rows(scale, m, _p(u, _i64p), _p(v, _i64p), None, 0, _p(one, _i64p),
+                                 None, None, 0, _p(d_in, _i64p), _p(d_out, _i64p),
+                                 _p(mx, _i64p), None), "filter_rows")
+    bounds = [n * b // nblocks for b in range(nblocks + 1)]
+    caps = [int(d_in[bounds[b]:bounds[b + 1]].sum()) for b in range(nblocks)]
+    offs = np.concatenate([[0], np.cumsum(caps)]).astype(np.int64)
+    col = np.empty(max(int(offs[-1]), 1), np.int32)
+    val = np.empty(max(int(offs[-1]), 1), np.float64)
+    rps = [None] * nblocks
+
+    def block(b):
+        j0, j1 = bounds[b], bounds[b + 1]
+        rows = np.arange(j0, j1, dtype=np.int64)
+        rp = np.empty(j1 - j0 + 1, np.int64)
+        o = int(offs[b])
+        cap = max(caps[b], 1)
+        _check(lib().ppo_filter_rows(scale, m, _p(u, _i64p), _p(v, _i64p), _p(rows, _i64p),
+                                     rows.size, _p(rp, _i64p), _p(col[o:], _i32p),
+                                     _p(val[o:], _f64p), cap, None, None, None, None),
+               "filter_rows")
+        rps[b] = rp
+
+    _threads(block, range(nblocks), threads)
+    # Close the gaps between blocks in place (block b's entries sit at
+    # offs[b] >= their final offset; numpy copies overlapping slices safely).
+    AT_rp = np.empty(n + 1, np.int64)
+    at = 0
+    for b in range(nblocks):
+        k = int(rps[b][-1])
+        o = int(offs[b])
+        if o != at:
+            col[at:at + k] = col[o:o + k]
+            val[at:at + k] = val[o:o + k]
+        AT_rp[bounds[b]:bounds[b + 1]] = rps[b][:-1] + at
+        at += k
+    AT_rp[n] = at
+    return AT_rp, col[:at], val[:at], d_in, d_out, int(mx[0]), at
+
+
+def pagerank_rows(n: int, AT_rp, AT_col, AT_val, r0, iters: int = 20, c: float = 0.85,
+                  threads: int = 1, nblocks: int | None = None):
+    """K3 on CSR(A^T): per iteration s = sum_r(r), then ppo_step_rows over
+    contiguous row blocks (the blocks only split the rows; every row is
+    the oracle's own sum).  Equals pagerank() on CSR(A) bit for bit.
+    Returns (r_iters, sums)."""
+    AT_rp = np.ascontiguousarray(AT_rp, dtype=np.int64)
+    AT_col = np.ascontiguousarray(AT_col, dtype=np.int32)
+    AT_val = np.ascontiguousarray(AT_val, dtype=np.float64)
+    if AT_col.size == 0:
+        AT_col = np.zeros(1, np.int32)
+        AT_val = np.zeros(1, np.float64)
+    r = np.array(r0, dtype=np.float64, copy=True)
+    y = np.empty_like(r)
+    sums = np.empty(iters + 1, np.float64)
+    nb = nblocks or max(1, 4 * threads)
+    bounds = [n * b // nb for b in range(nb + 1)]
+    for it in range(iters + 1):
+        sums[it] = sum_r(r)
+        if it == iters:
+            break
+        s = sums[it]
+
+        def block(b, r=r, y=y, s=s):
+            j0, j1 = bounds[b], bounds[b + 1]
+            _check(lib().ppo_step_rows(n, j1 - j0, _p(AT_rp[j0:], _i64p), _p(AT_col, _i32p),
+                                       _p(AT_val, _f64p), _p(r, _f64p), s, c,
+                                       _p(y[j0:], _f64p)), "step_rows")
+
+        _threads(block, range(nb), threads)
+        r, y = y, r
+    return r, sums
+

@@ -29,6 +29,10 @@
  *                matrix and for A = 0; the sum(r) recurrence; the Perron
  *                vector of c*A.' + (1-c)/N from numpy.linalg.eig (Sec. IV.D)
  *   step_rows    equals one pagerank iteration on every row
+ *   sum_r        the sums pagerank reports; extended-precision sum
+ *   digest       Python big-integer evaluation of its definition;
+ *                order independence; additivity over pieces
+ *   filter_rows  blocks of rows put together equal filter's CSR(A^T)
  *   pagerank_converge
  *                Perron vector of the dense matrix of each dangling mode
  *                (numpy.linalg.eig); sum(r) conserved by the two modes
@@ -558,6 +562,12 @@ static double sum_r(int64_t n, const double *r) {
   for (int64_t i = 0; i < n; ++i) csum_add(&a, r[i]);
   return csum_value(&a);
 }
+
+int ppo_sum_r(int64_t n, const double *r, double *out) {
+  if (n < 0 || !out || (n > 0 && !r)) return PPO_EINVAL;
+  *out = sum_r(n, r);
+  return PPO_OK;
+}
 int ppo_init_r(int64_t n, uint64_t seed, int32_t rhs, double *r) {
   if (n < 1 || n > ((int64_t)1 << 30) || rhs < 0 || !r) return PPO_EINVAL;
   /* r = rand(1,N); r = r ./ norm(r,1).  Each draw is a 24-bit integer k_i,
@@ -681,5 +691,38 @@ int ppo_step_rows(int64_t n, int64_t nrows, const int64_t *rp, const int32_t *co
     }
     y[q] = csum_value(&acc) + t;
   }
+  return PPO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Order-independent digest of an array, for comparing arrays too large to  */
+/* store: D = sum_i mix(x_i XOR mix(i + g)) mod 2^64, where x_i is element   */
+/* i's bit pattern zero-extended to 64 bits, g = 0x9E3779B97F4A7C15 and mix  */
+/* is the SplitMix64 output function (Steele, Lea and Flood, "Fast          */
+/* splittable pseudorandom number generators", OOPSLA 2014).  Test tooling: */
+/* it takes part in no kernel's arithmetic.                                 */
+/* ------------------------------------------------------------------------ */
+static uint64_t digest_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+int ppo_digest(const void *x, int64_t count, int32_t width, int64_t index0, uint64_t *out) {
+  if (count < 0 || index0 < 0 || !out || (width != 4 && width != 8) || (count > 0 && !x))
+    return PPO_EINVAL;
+  uint64_t d = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    uint64_t bits;
+    if (width == 4) {
+      uint32_t w;
+      memcpy(&w, (const char *)x + 4 * i, 4);
+      bits = w;
+    } else {
+      memcpy(&bits, (const char *)x + 8 * i, 8);
+    }
+    d += digest_mix(bits ^ digest_mix((uint64_t)(index0 + i) + 0x9E3779B97F4A7C15ull));
+  }
+  *out = d;
   return PPO_OK;
 }

@@ -126,4 +126,16 @@ int ppo_pagerank_converge(int64_t n, const int64_t *A_rp, const int32_t *A_col,
 int ppo_step_rows(int64_t n, int64_t nrows, const int64_t *rp, const int32_t *col,
                   const double *val, const double *r, double s, double c, double *y);
 
+/* sum(r) as K3 forms it: compensated (Neumaier), terms in ascending index
+ * order.  Lets a caller split one iteration's rows over several
+ * ppo_step_rows calls and still reproduce ppo_pagerank bit for bit. */
+int ppo_sum_r(int64_t n, const double *r, double *out);
+
+/* Test tooling, not part of any kernel: *out = sum over i < count of
+ * mix(x_i XOR mix(index0 + i + 0x9E3779B97F4A7C15)) mod 2^64, with x_i the
+ * bit pattern of element i (width 4 or 8 bytes, zero-extended) and mix the
+ * SplitMix64 output function.  Order-independent, and additive over
+ * consecutive pieces of an array when index0 is the piece's offset. */
+int ppo_digest(const void *x, int64_t count, int32_t width, int64_t index0, uint64_t *out);
+
 #endif

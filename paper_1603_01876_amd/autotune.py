@@ -9,8 +9,7 @@ with the iterations it serves.  Candidates are
 * nrhs == 1: one pass with 8 or 16 SpMV items per thread (the merge-path
   tile is 256 times that), or column slabs of 2^18, 2^19, 2^20 vertices with
   16 items per thread; each with vertex relabelling on or off when the
-  caller passes weights (slab 0 through LDS windows is measured slower at
-  S = 26 and is not a candidate);
+  caller passes weights;
 * nrhs > 1: SpMM lane-group width (the next power of two >= nrhs, or 64).
 
 The choice is applied with set_k3_config() and cached in a JSON file keyed
@@ -32,19 +31,19 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pp_mi355x", "k3
 SLABS = (0, 18, 19, 20)
 
 
-def candidates(nrhs: int, relabel_options=(False,)) -> list[tuple[int, int, int, int, bool]]:
-    """(items_per_thread, rhs_lanes, slab_log2, hot_windows, relabel) tuples."""
+def candidates(nrhs: int, relabel_options=(False,)) -> list[tuple[int, int, int, bool]]:
+    """(items_per_thread, rhs_lanes, slab_log2, relabel) tuples."""
     if nrhs == 1:
         out = []
         for rl in relabel_options:
-            out += [(8, 0, 0, 0, rl), (16, 0, 0, 0, rl)]
-            out += [(16, 0, slab, 0, rl) for slab in SLABS if slab]
+            out += [(8, 0, 0, rl), (16, 0, 0, rl)]
+            out += [(16, 0, slab, rl) for slab in SLABS if slab]
         return out
     lanes = 2
     while lanes < nrhs:
         lanes *= 2
-    return [(8, lanes, 0, 0, rl) for rl in relabel_options] + \
-        ([(8, 64, 0, 0, rl) for rl in relabel_options] if lanes < 64 else [])
+    return [(8, lanes, 0, rl) for rl in relabel_options] + \
+        ([(8, 64, 0, rl) for rl in relabel_options] if lanes < 64 else [])
 
 
 def name(cand) -> str:
@@ -70,8 +69,8 @@ def _load(path):
 def tune(AT, dtype="f32", nrhs: int = 1, weights=None, iters: int = 20, cache: str | None = None,
          force: bool = False, ws=None, repeats: int = 2) -> dict:
     """Measures the candidates on this matrix, applies the fastest with
-    set_k3_config() and returns {"config": [ipt, lanes, slab_log2,
-    hot_windows], "relabel": bool, "ms": {candidate: ms per call}}.  The
+    set_k3_config() and returns {"config": [ipt, lanes, slab_log2],
+    "relabel": bool, "ms": {candidate: ms per call}}.  The
     caller passes `weights` to pagerank() only when "relabel" is true."""
     cache = cache or DEFAULT_CACHE
     k = key(AT, dtype, nrhs, weights is not None, iters)
@@ -89,8 +88,8 @@ def tune(AT, dtype="f32", nrhs: int = 1, weights=None, iters: int = 20, cache: s
     opts = (False, True) if weights is not None else (False,)
     times = {}
     for cand in candidates(nrhs, opts):
-        ipt, lanes, slab, hot, rl = cand
-        pp.set_k3_config(ipt, lanes, slab, hot)
+        ipt, lanes, slab, rl = cand
+        pp.set_k3_config(ipt, lanes, slab)
         w = weights if rl else None
         best = float("inf")
         for rep in range(repeats + 1):
@@ -106,7 +105,7 @@ def tune(AT, dtype="f32", nrhs: int = 1, weights=None, iters: int = 20, cache: s
         times[name(cand)] = best
     win = min(times, key=times.get)
     cand = [int(x) for x in win.split(",")]
-    cfg, relabel = cand[:4], bool(cand[4])
+    cfg, relabel = cand[:3], bool(cand[3])
     pp.set_k3_config(*cfg)
     entry = {"config": cfg, "relabel": relabel, "ms": times}
     table[k] = entry

@@ -83,11 +83,14 @@ __device__ __forceinline__ T block_sum(T v, T *sh) {
   return r;
 }
 
+// Every descriptor has been checked on the host before the launch (n in
+// [1, lds_n], nnz >= 0, the arrays present), so each graph fits the
+// workgroup's two LDS vectors.
 template <typename V>
 __global__ __launch_bounds__(kT) void k_graphs(const pp_graph *__restrict__ graphs, int32_t ngraphs,
                                                int32_t iters, double c, uint32_t *queue,
                                                int32_t lds_n) {
-  // queue[0]: next graph; queue[1]: graphs skipped by the bounds check.
+  // queue[0]: index of the next graph to take.
   using Acc = typename GForm<V>::Acc;
   extern __shared__ __align__(16) uint8_t smem[];
   V *xa = reinterpret_cast<V *>(smem);
@@ -107,13 +110,6 @@ __global__ __launch_bounds__(kT) void k_graphs(const pp_graph *__restrict__ grap
     __syncthreads();
     if (g >= ngraphs) break;
     const pp_graph G = graphs[g];
-    // Graphs that do not fit the workgroup's LDS vectors (or are malformed)
-    // are left untouched and counted.
-    if (G.n < 1 || G.n > lds_n || G.nnz < 0 || G.n + G.nnz > 0x7FFFFFFF || !G.row_ptr || !G.r ||
-        (G.nnz > 0 && (!G.col || !G.val))) {
-      if (tid == 0) atomicAdd(queue + 1, 1u);
-      continue;
-    }
     const int32_t n = int32_t(G.n), nnz = int32_t(G.nnz);
     const int32_t *__restrict__ rp = G.row_ptr;
     const int32_t *__restrict__ col = G.col;
@@ -241,15 +237,15 @@ __global__ __launch_bounds__(kT) void k_graphs(const pp_graph *__restrict__ grap
 }
 
 __global__ void k_zero_queue(uint32_t *q) {
-  if (threadIdx.x < 2) q[threadIdx.x] = 0u;
+  if (threadIdx.x == 0) q[0] = 0u;
 }
 
 // Cached hipGraph per launch configuration.  The graph holds two kernel
-// nodes (queue reset, persistent kernel) whose arguments are device
-// pointers owned by the caller, so a replay reads whatever the descriptor
-// table and the workspace hold at that time.
+// nodes (queue reset, persistent kernel) whose arguments point into the
+// caller's workspace; the descriptor table is copied there before every
+// launch or replay, so a replay reads the batch of the current call.
 struct GraphEntry {
-  const void *graphs, *ws;
+  const void *ws;
   hipStream_t stream;
   int32_t ngraphs, iters, lds_n, grid;
   pp_dtype dt;
@@ -288,9 +284,10 @@ constexpr size_t kStaticLds = 24 * 1024;  // reductions, scan tails, s_pre
 
 }  // namespace
 
-size_t graphs_ws_bytes(int32_t /*ngraphs*/) {
+size_t graphs_ws_bytes(int32_t ngraphs) {
   Carve c(nullptr);
   c.take<uint32_t>(4);
+  c.take<pp_graph>(size_t(ngraphs < 1 ? 1 : ngraphs));
   return c.bytes();
 }
 
@@ -306,23 +303,36 @@ pp_status launch_graphs(int32_t ngraphs, const pp_graph *graphs, int64_t max_n, 
   if (ws_bytes < graphs_ws_bytes(ngraphs)) return fail(PP_EWORKSPACE, "graphs workspace too small");
   Carve cv(ws);
   uint32_t *queue = cv.take<uint32_t>(4);
+  pp_graph *table = cv.take<pp_graph>(size_t(ngraphs));
   const int32_t lds_n = int32_t((max_n + 63) / 64 * 64);
   const size_t dyn = size_t(2) * lds_n * (dt == PP_F64 ? 8 : 4);
   const int grid = ngraphs < cu_count() ? ngraphs : cu_count();
-  if (dt == PP_F64)
-    PP_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_graphs<double>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, int(dyn)));
-  else
-    PP_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_graphs<float>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, int(dyn)));
+  // The dynamic LDS limit is raised once per value type to the largest
+  // batch any call may run (graphs_max_n), never lowered, so a hipGraph
+  // recorded earlier with a larger size stays launchable.
+  static bool raised[2] = {false, false};
+  const int room = int(size_t(2) * graphs_max_n(dt) * (dt == PP_F64 ? 8 : 4));
+  if (!raised[dt == PP_F64 ? 0 : 1]) {
+    if (dt == PP_F64)
+      PP_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_graphs<double>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, room));
+    else
+      PP_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_graphs<float>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, room));
+    raised[dt == PP_F64 ? 0 : 1] = true;
+  }
+  // The descriptor table (host memory, checked by the caller) goes into the
+  // workspace ahead of the launch; graph replays read it from there.
+  PP_HIP(hipMemcpyAsync(table, graphs, size_t(ngraphs) * sizeof(pp_graph), hipMemcpyHostToDevice,
+                        s));
 
   auto enqueue = [&](hipStream_t st) -> pp_status {
     hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(64), 0, st, queue);
     if (dt == PP_F64)
-      hipLaunchKernelGGL(k_graphs<double>, dim3(grid), dim3(kT), dyn, st, graphs, ngraphs, iters,
+      hipLaunchKernelGGL(k_graphs<double>, dim3(grid), dim3(kT), dyn, st, table, ngraphs, iters,
                          c, queue, lds_n);
     else
-      hipLaunchKernelGGL(k_graphs<float>, dim3(grid), dim3(kT), dyn, st, graphs, ngraphs, iters,
+      hipLaunchKernelGGL(k_graphs<float>, dim3(grid), dim3(kT), dyn, st, table, ngraphs, iters,
                          c, queue, lds_n);
     PP_LAUNCHED("k_graphs");
     return PP_OK;
@@ -330,7 +340,7 @@ pp_status launch_graphs(int32_t ngraphs, const pp_graph *graphs, int64_t max_n, 
   if (!use_graph) return enqueue(s);
 
   for (GraphEntry &e : g_cache) {
-    if (e.graphs == graphs && e.ws == ws && e.stream == s && e.ngraphs == ngraphs &&
+    if (e.ws == ws && e.stream == s && e.ngraphs == ngraphs &&
         e.iters == iters && e.lds_n == lds_n && e.grid == grid && e.dt == dt && e.c == c) {
       PP_HIP(hipGraphLaunch(e.exec, s));
       return PP_OK;
@@ -350,7 +360,7 @@ pp_status launch_graphs(int32_t ngraphs, const pp_graph *graphs, int64_t max_n, 
     hipGraphExecDestroy(g_cache.front().exec);
     g_cache.erase(g_cache.begin());
   }
-  g_cache.push_back(GraphEntry{graphs, ws, s, ngraphs, iters, lds_n, grid, dt, c, exec});
+  g_cache.push_back(GraphEntry{ws, s, ngraphs, iters, lds_n, grid, dt, c, exec});
   PP_HIP(hipGraphLaunch(exec, s));
   return PP_OK;
 }

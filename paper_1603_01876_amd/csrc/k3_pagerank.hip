@@ -42,7 +42,6 @@ struct K3Config {
   int ipt = 8;
   int rhs_lanes = 0;  // 0: next power of two >= nrhs
   int slab_log2 = -1; // 0: one pass over all columns; > 0: slab width 2^slab_log2; -1: auto
-  int hot_windows = 0;   // slab 0 through LDS windows: 0 off, 1 on, -1 when slab 0 is dense
 };
 K3Config g_cfg;
 constexpr int kFinishPer = kThreads;         // spmv workgroups per finish workgroup
@@ -1195,410 +1194,6 @@ __global__ __launch_bounds__(1024) void k_sum_blocks(const double *__restrict__ 
   }
 }
 
-// ------------------------------------------------- hot slab through LDS
-// After relabelling, slab 0 (the lowest labels: the most gathered sources)
-// holds most of the entries, and one value of r per entry through L2 is
-// what bounds the segmented SpMV.  Slab 0 is therefore laid out for LDS:
-// its pairs (rows) are cut into blocks of whole rows -- block b starts at
-// the first pair p with p * kWinRowCost + rp[p] >= b * kWinBlock, so a block
-// has fewer than kWinRows rows -- and inside a block the entries are
-// ordered by window (2^13 FP64 or 2^14 FP32 columns: 64 KB of r), then by row, entries of a row in
-// their order.  One workgroup per block walks its windows in order: the
-// window's values of r are staged in LDS (the next window is prefetched
-// into registers meanwhile), each entry reads its value from LDS, and each
-// row's run inside the window is added to the row's LDS accumulator.  At
-// the end the accumulators are the slab-0 pairs' partial sums.  A row is
-// summed window by window, entries in order: a fixed order.
-template <typename V>
-constexpr int win_bits() { return sizeof(V) == 4 ? 14 : 13; }   // window: 64 KB of r
-constexpr int kWinRows = 8192;
-constexpr int kWinRowCost = 33;            // kWinBlock / kWinRowCost + 1 <= kWinRows
-constexpr int64_t kWinBlock = 262144;
-constexpr int kWinTile = kThreads * 16;    // build tile (entries)
-constexpr int kWinThreads = 1024;
-constexpr int kWinPer = 8;                 // entries per thread per step
-constexpr int kMaxWins = 128;
-
-// wb[b] = (first pair, its first entry) of block b; wb[nblk] = (P0, E0).
-__global__ __launch_bounds__(256) void k_win_bounds(const int32_t *__restrict__ prp, int32_t P0,
-                                                    int32_t nblk, int2 *__restrict__ wb) {
-  for (int32_t b = blockIdx.x * 256 + threadIdx.x; b <= nblk; b += gridDim.x * 256) {
-    const int64_t target = int64_t(b) * kWinBlock;
-    int32_t lo = 0, hi = P0;
-    while (lo < hi) {
-      const int32_t m = (lo + hi) >> 1;
-      if (int64_t(m) * kWinRowCost + prp[m] < target)
-        lo = m + 1;
-      else
-        hi = m;
-    }
-    const int32_t p = b == nblk ? P0 : lo;
-    wb[b] = make_int2(p, prp[p]);
-  }
-}
-
-// Build tiles per block (tcnt[nblk] = 0, scanned afterwards into tile bases).
-__global__ __launch_bounds__(256) void k_win_tiles(const int2 *__restrict__ wb, int32_t nblk,
-                                                   uint32_t *__restrict__ tcnt) {
-  for (int32_t b = blockIdx.x * 256 + threadIdx.x; b <= nblk; b += gridDim.x * 256)
-    tcnt[b] = b == nblk ? 0u : uint32_t((wb[b + 1].y - wb[b].y + kWinTile - 1) / kWinTile);
-}
-
-// Block of build tile t: the last b with tbase[b] <= t (blocks without tiles
-// share their base with the next block).
-__device__ __forceinline__ int32_t win_block_of(const uint32_t *tbase, int32_t nblk, uint32_t t) {
-  int32_t lo = 0, hi = nblk;   // tbase[lo] <= t < tbase[hi]
-  while (hi - lo > 1) {
-    const int32_t m = (lo + hi) >> 1;
-    if (tbase[m] <= t)
-      lo = m;
-    else
-      hi = m;
-  }
-  return lo;
-}
-
-// Entries of each build tile per window -> cnt[tbase[b] * nwin + w * nt + i]
-// (block-major, then window, then tile: one exclusive scan gives every
-// (block, window, tile) its output offset).
-__global__ __launch_bounds__(kThreads) void k_win_count(const int32_t *__restrict__ seg_col,
-                                                        const int2 *__restrict__ wb,
-                                                        const uint32_t *__restrict__ tbase,
-                                                        int32_t nblk, int32_t nwin, int32_t wbits,
-                                                        int32_t wshift, uint32_t *__restrict__ cnt) {
-  constexpr int kWaves = kThreads / kWave;
-  __shared__ uint32_t wh[kWaves][kMaxWins];
-  const uint32_t t = blockIdx.x;
-  if (t >= tbase[nblk]) return;
-  for (int i = threadIdx.x; i < kWaves * kMaxWins; i += kThreads) (&wh[0][0])[i] = 0u;
-  __syncthreads();
-  const int32_t b = win_block_of(tbase, nblk, t);
-  const uint32_t nt = tbase[b + 1] - tbase[b], ti = t - tbase[b];
-  const int32_t e0 = wb[b].y + int32_t(ti) * kWinTile;
-  const int32_t e1 = e0 + kWinTile < wb[b + 1].y ? e0 + kWinTile : wb[b + 1].y;
-  const int w = threadIdx.x / kWave;
-#pragma unroll 4
-  for (int r = 0; r < kWinTile / kThreads; ++r) {
-    const int32_t e = e0 + w * (kWinTile / kWaves) + r * kWave + lane_id();
-    const bool valid = e < e1;
-    const uint32_t d = valid ? uint32_t(seg_col[e]) >> wshift : 0u;
-    wave_digit_rank(d, valid, wbits, wh[w]);
-  }
-  __syncthreads();
-  for (int d = threadIdx.x; d < nwin; d += kThreads) {
-    uint32_t s = 0;
-#pragma unroll
-    for (int q = 0; q < kWaves; ++q) s += wh[q][d];
-    cnt[int64_t(tbase[b]) * nwin + int64_t(d) * nt + ti] = s;
-  }
-}
-
-// Stable scatter of each build tile to its (window, row) order inside its
-// block, packing each entry as local row << kWinBits | column in window.
-// The pair of entry e is the last pair of the block whose first entry
-// prp[p] is <= e.
-template <typename V>
-__global__ __launch_bounds__(kThreads) void k_win_scatter(
-    const int32_t *__restrict__ seg_col, const V *__restrict__ seg_val,
-    const int32_t *__restrict__ prp, const int2 *__restrict__ wb,
-    const uint32_t *__restrict__ tbase, int32_t nblk, int32_t nwin, int32_t wbits,
-    const uint32_t *__restrict__ off, uint32_t *__restrict__ out_pk, V *__restrict__ out_val) {
-  constexpr int kWaves = kThreads / kWave;
-  constexpr int kPer = kWinTile / kThreads;
-  constexpr int kWinBits = win_bits<V>();
-  constexpr int kWinSize = 1 << kWinBits;
-  __shared__ uint32_t wh[kWaves][kMaxWins];
-  __shared__ uint32_t s_toff[kMaxWins], s_goff[kMaxWins];
-  __shared__ uint32_t s_scan[4];
-  __shared__ uint32_t s_pk[kWinTile];
-  __shared__ V s_val[kWinTile];
-  __shared__ uint8_t s_dg[kWinTile];
-  const uint32_t t = blockIdx.x;
-  if (t >= tbase[nblk]) return;
-  for (int i = threadIdx.x; i < kWaves * kMaxWins; i += kThreads) (&wh[0][0])[i] = 0u;
-  __syncthreads();
-  const int tid = threadIdx.x, w = tid / kWave;
-  const int32_t b = win_block_of(tbase, nblk, t);
-  const uint32_t nt = tbase[b + 1] - tbase[b], ti = t - tbase[b];
-  const int2 blk = wb[b];
-  const int32_t e0 = blk.y + int32_t(ti) * kWinTile;
-  const int32_t e1 = e0 + kWinTile < wb[b + 1].y ? e0 + kWinTile : wb[b + 1].y;
-  uint32_t pk[kPer], rank[kPer], dg[kPer];
-  V vv[kPer];
-#pragma unroll
-  for (int r = 0; r < kPer; ++r) {
-    const int32_t e = e0 + w * (kWinTile / kWaves) + r * kWave + lane_id();
-    const bool valid = e < e1;
-    dg[r] = 0u;
-    pk[r] = 0u;
-    vv[r] = V(0);
-    if (valid) {
-      const uint32_t c = uint32_t(seg_col[e]);
-      int32_t lo = blk.x, hi = wb[b + 1].x;   // prp[lo] <= e < prp[hi]
-      while (hi - lo > 1) {
-        const int32_t m = (lo + hi) >> 1;
-        if (prp[m] <= e)
-          lo = m;
-        else
-          hi = m;
-      }
-      const uint32_t pe = uint32_t(lo);
-      dg[r] = c >> kWinBits;
-      pk[r] = ((pe - uint32_t(blk.x)) << kWinBits) | (c & uint32_t(kWinSize - 1));
-      vv[r] = seg_val[e];
-    }
-    rank[r] = wave_digit_rank(dg[r], valid, wbits, wh[w]);
-  }
-  __syncthreads();
-  const int d = tid;
-  uint32_t total = 0;
-  if (d < nwin) {
-#pragma unroll
-    for (int q = 0; q < kWaves; ++q) {
-      const uint32_t c = wh[q][d];
-      wh[q][d] = total;
-      total += c;
-    }
-  }
-  uint32_t all;
-  const uint32_t first = block_exscan256(total, s_scan, &all);
-  if (d < nwin) {
-    s_toff[d] = first;
-    s_goff[d] = off[int64_t(tbase[b]) * nwin + int64_t(d) * nt + ti];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < kPer; ++r) {
-    const int32_t e = e0 + w * (kWinTile / kWaves) + r * kWave + lane_id();
-    if (e < e1) {
-      const uint32_t slot = s_toff[dg[r]] + wh[w][dg[r]] + rank[r];
-      s_pk[slot] = pk[r];
-      s_val[slot] = vv[r];
-      s_dg[slot] = uint8_t(dg[r]);
-    }
-  }
-  __syncthreads();
-  for (int32_t slot = tid; slot < e1 - e0; slot += kThreads) {
-    const uint32_t d8 = s_dg[slot];
-    const int64_t pos = int64_t(s_goff[d8]) + (slot - int32_t(s_toff[d8]));
-    out_pk[pos] = s_pk[slot];
-    out_val[pos] = s_val[slot];
-  }
-}
-
-// chunk[b * (nwin + 1) + w] = first entry of window w in block b (w = nwin:
-// the block's end).
-__global__ __launch_bounds__(256) void k_win_chunks(const int2 *__restrict__ wb,
-                                                    const uint32_t *__restrict__ tbase,
-                                                    const uint32_t *__restrict__ off, int32_t nblk,
-                                                    int32_t nwin, int32_t *__restrict__ chunk) {
-  const int64_t total = int64_t(nblk) * (nwin + 1);
-  for (int64_t i = blockIdx.x * int64_t(256) + threadIdx.x; i < total;
-       i += int64_t(gridDim.x) * 256) {
-    const int32_t b = int32_t(i / (nwin + 1)), w = int32_t(i % (nwin + 1));
-    const uint32_t nt = tbase[b + 1] - tbase[b];
-    int32_t v;
-    if (w == nwin)
-      v = wb[b + 1].y;
-    else if (nt == 0)
-      v = wb[b].y;
-    else
-      v = int32_t(off[int64_t(tbase[b]) * nwin + int64_t(w) * nt]);
-    chunk[i] = v;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_rebase(int32_t *__restrict__ p, int64_t count,
-                                                int32_t by) {
-  for (int64_t i = blockIdx.x * int64_t(256) + threadIdx.x; i < count;
-       i += int64_t(gridDim.x) * 256)
-    p[i] -= by;
-}
-
-// Slab 0 of one iteration: block b's rows, window by window (see above).
-// Within a window the block's entries are split into steps of kWinThreads *
-// kWinPer consecutive entries; a thread adds its run of entries per row and
-// runs of one row that cross threads (or steps) are joined by a segmented
-// scan over the threads (and a carry between steps), in entry order.  The
-// next window's values of r and its first step's entries are loaded while
-// the current window is processed.
-template <typename V>
-__global__ __launch_bounds__(kWinThreads) void k_spmv_win(
-    const uint32_t *__restrict__ pk, const V *__restrict__ val, const V *__restrict__ x,
-    int32_t n, const int2 *__restrict__ wb, const int32_t *__restrict__ chunk, int32_t nwin,
-    typename Form<V>::Part *__restrict__ part) {
-  using Acc = typename Form<V>::Acc;
-  constexpr int kWinBits = win_bits<V>();
-  constexpr int kWinSize = 1 << kWinBits;
-  constexpr int kWaves = kWinThreads / kWave;
-  constexpr int kXPer = kWinSize / kWinThreads;
-  constexpr int kStep = kWinThreads * kWinPer;
-  constexpr uint32_t kMask = kWinSize - 1;
-  __shared__ Acc s_acc[kWinRows];
-  __shared__ V s_x[kWinSize];
-  __shared__ Acc s_wtail[kWaves];
-  __shared__ int32_t s_wlast[kWaves], s_wfirst[kWaves], s_wrow0[kWaves + 1];
-  __shared__ int32_t s_ch[kMaxWins + 1];
-  __shared__ int32_t s_ck;
-  __shared__ Acc s_cv;
-  const int b = blockIdx.x, tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
-  const int2 w0 = wb[b], w1 = wb[b + 1];
-  const int32_t rows = w1.x - w0.x;
-  for (int i = tid; i < rows; i += kWinThreads) s_acc[i] = Acc{};
-  for (int i = tid; i <= nwin; i += kWinThreads) s_ch[i] = chunk[int64_t(b) * (nwin + 1) + i];
-  if (tid == 0) {
-    s_wrow0[kWaves] = -1;
-    s_ck = -1;
-  }
-  __syncthreads();
-  auto next_window = [&](int w) {
-    while (w < nwin && s_ch[w + 1] <= s_ch[w]) ++w;
-    return w;
-  };
-  auto commit = [&](int32_t r, const Acc &v) { s_acc[r] = merge(s_acc[r], v); };
-  V xr[kXPer];
-  uint32_t qn[kWinPer];
-  V vn[kWinPer];
-  auto prefetch = [&](int w) {
-#pragma unroll
-    for (int k = 0; k < kXPer; ++k) {
-      const int64_t g = int64_t(w) * kWinSize + k * kWinThreads + tid;
-      xr[k] = g < n ? x[g] : V(0);
-    }
-    const int32_t eb = s_ch[w] + tid * kWinPer, ee = s_ch[w + 1];
-#pragma unroll
-    for (int k = 0; k < kWinPer; ++k) {
-      const bool ok = eb + k < ee;
-      qn[k] = ok ? pk[eb + k] : 0u;
-      vn[k] = ok ? val[eb + k] : V(0);
-    }
-  };
-  int wcur = next_window(0);
-  if (wcur < nwin) prefetch(wcur);
-  while (wcur < nwin) {
-    __syncthreads();   // the previous window's readers and accumulators are done
-#pragma unroll
-    for (int k = 0; k < kXPer; ++k) s_x[k * kWinThreads + tid] = xr[k];
-    uint32_t q[kWinPer];
-    V vv[kWinPer];
-#pragma unroll
-    for (int k = 0; k < kWinPer; ++k) {
-      q[k] = qn[k];
-      vv[k] = vn[k];
-    }
-    const int wnext = next_window(wcur + 1);
-    if (wnext < nwin) prefetch(wnext);
-    __syncthreads();
-    const int32_t c0 = s_ch[wcur], c1 = s_ch[wcur + 1];
-    for (int32_t base = c0; base < c1; base += kStep) {
-      const int32_t eb = base + tid * kWinPer;
-      if (base != c0) {
-#pragma unroll
-        for (int k = 0; k < kWinPer; ++k) {
-          const bool ok = eb + k < c1;
-          q[k] = ok ? pk[eb + k] : 0u;
-          vv[k] = ok ? val[eb + k] : V(0);
-        }
-      }
-      const int32_t myfirst = eb < c1 ? int32_t(q[0] >> kWinBits) : -1;
-      if (lane == 0) s_wrow0[wv] = myfirst;
-      int32_t cur = -1, first_row = -1;
-      Acc a{}, fa{};
-#pragma unroll
-      for (int k = 0; k < kWinPer; ++k) {
-        if (eb + k < c1) {
-          const int32_t r = int32_t(q[k] >> kWinBits);
-          const V prod = s_x[q[k] & kMask] * vv[k];
-          if (r != cur) {
-            if (cur >= 0) {
-              if (first_row < 0) {
-                first_row = cur;
-                fa = a;
-              } else {
-                commit(cur, a);   // a row wholly inside this thread
-              }
-            }
-            cur = r;
-            a = Acc{};
-          }
-          a.add(prod);
-        }
-      }
-      if (tid == 0) {   // the run carried in from the previous step
-        const int32_t ck = s_ck;
-        s_ck = -1;      // set again below, after the next barrier, if a run goes on
-        if (ck >= 0) {
-          const Acc cv = s_cv;
-          if (first_row >= 0) {
-            if (first_row == ck)
-              fa = merge(cv, fa);
-            else
-              commit(ck, cv);
-          } else if (cur == ck) {
-            a = merge(cv, a);
-          } else {
-            commit(ck, cv);
-          }
-        }
-      }
-      // segmented inclusive scan of the open runs, keyed by row
-      Acc v = a;
-      const int32_t key = cur;
-#pragma unroll
-      for (int o = 1; o < kWave; o <<= 1) {
-        const Acc vu = shfl_up_acc(v, o);
-        const int32_t ku = __shfl_up(key, o, kWave);
-        if (lane >= o && ku == key) v = merge(vu, v);
-      }
-      if (lane == kWave - 1) {
-        s_wtail[wv] = v;
-        s_wlast[wv] = key;
-      }
-      if (lane == 0) s_wfirst[wv] = key;
-      __syncthreads();   // wave tails and first rows are visible
-      {
-        Acc before{};
-        for (int qw = wv - 1; qw >= 0; --qw) {
-          if (s_wlast[qw] != key) break;
-          before = merge(s_wtail[qw], before);
-          if (s_wfirst[qw] != key) break;
-        }
-        v = merge(before, v);
-      }
-      // the previous thread's scanned run, for this thread's first row
-      const Acc vprev = shfl_up_acc(v, 1);
-      const int32_t kprev = __shfl_up(key, 1, kWave);
-      const int32_t nfirst = __shfl_down(myfirst, 1, kWave);
-      if (first_row >= 0) {
-        Acc pre{};
-        if (lane > 0) {
-          if (kprev == first_row) pre = vprev;
-        } else {
-          for (int qw = wv - 1; qw >= 0; --qw) {   // lane 63 of the previous wave, scanned
-            if (s_wlast[qw] != first_row) break;
-            pre = merge(s_wtail[qw], pre);
-            if (s_wfirst[qw] != first_row) break;
-          }
-        }
-        commit(first_row, merge(pre, fa));
-      }
-      const int32_t nf = lane < kWave - 1 ? nfirst : s_wrow0[wv + 1];
-      if (cur >= 0 && nf != cur) {
-        if (nf >= 0 || base + kStep >= c1) {
-          commit(cur, v);
-        } else {
-          s_ck = cur;   // the run may go on in the next step
-          s_cv = v;
-        }
-      }
-      __syncthreads();
-    }
-    wcur = wnext;
-  }
-  __syncthreads();
-  for (int i = tid; i < rows; i += kWinThreads) part[w0.x + i] = Form<V>::part(s_acc[i]);
-}
-
 // ------------------------------------------------ run to a convergence test
 // Sec. IV.D notes that applications iterate until the normed sum of the
 // differences between iterations is small; Sec. IV.C-D and V name the
@@ -1755,10 +1350,6 @@ struct Layout {
   // column segmenting
   int32_t *seg_col, *prp, *pair_row, *rpp, *pidx;
   int2 *cstart, *seg_coord;
-  // hot slab through LDS windows
-  int2 *wb;
-  uint32_t *wtb;
-  int32_t *wchunk;
   int64_t *info;
   V *seg_val;
   typename Form<V>::Part *seg_part;
@@ -1827,8 +1418,7 @@ Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs, size_t *byte
     // One partial per pair (at most one pair per entry), written by the
     // iterations.
     L.seg_part = c.take<typename Form<V>::Part>(size_t(z));
-    const int64_t wcnt = int64_t(kMaxWins) * (z / kWinTile + z * (kWinRowCost + 1) / kWinBlock + 4);
-    const int64_t cnt_n = kMaxSlabs * ntiles > wcnt ? kMaxSlabs * ntiles : wcnt;
+    const int64_t cnt_n = kMaxSlabs * ntiles;
     L.seg_cnt = c.take<uint32_t>(size_t(cnt_n));
     L.seg_pcnt = c.take<uint32_t>(size_t(kMaxSlabs * ntiles));
     L.seg_bsum = c.take<uint32_t>(size_t(kMaxSlabs) * size_t((ntiles + kColTiles - 1) / kColTiles + 1));
@@ -1839,10 +1429,6 @@ Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs, size_t *byte
     if (n + 1 > scan_n) scan_n = n + 1;
     L.seg_scan = c.take<uint32_t>(size_t(scan_ws_elems(scan_n)));
     L.rpp = c.take<int32_t>(size_t(n + 1));
-    const int64_t nblk_w = z * (kWinRowCost + 1) / kWinBlock + 2;
-    L.wb = c.take<int2>(size_t(nblk_w + 1));
-    L.wtb = c.take<uint32_t>(size_t(nblk_w + 2));
-    L.wchunk = c.take<int32_t>(size_t(nblk_w) * (kMaxWins + 1));
     L.info = c.take<int64_t>(4 + kMaxSlabs);
     L.cstart = c.take<int2>(size_t((n + z + kCombItems - 1) / kCombItems + 2));
     L.pidx = L.col2;
@@ -1898,30 +1484,24 @@ void launch_spmv(int ipt, int32_t nb, hipStream_t s, const int32_t *rp, const in
                        n, coord, c, tele, blk_ysum, blk_carry, blk_head, part);
 }
 
-// info[0] = P, info[1] = E0 (entries of slab 0), info[2] = P0 (its pairs),
-// info[3 + d] = first pair of slab d (d <= ns; slab ns = the end, P);
-// prp[P] = nnz.  eoff / poff are the per-(tile, slab) offsets, so their
+// info[0] = P, info[1 + d] = first pair of slab d (d <= ns; slab ns = the
+// end, P); prp[P] = nnz.  poff holds the per-(tile, slab) offsets, so its
 // entry for (tile 0, slab d) is the start of slab d.
-__global__ void k_seg_info(const uint32_t *__restrict__ eoff, const uint32_t *__restrict__ poff,
-                           int32_t ns, int64_t nnz, const int64_t *__restrict__ total,
-                           int32_t *__restrict__ prp, int64_t *__restrict__ info) {
+__global__ void k_seg_info(const uint32_t *__restrict__ poff, int32_t ns, int64_t nnz,
+                           const int64_t *__restrict__ total, int32_t *__restrict__ prp,
+                           int64_t *__restrict__ info) {
   const int64_t P = *total;
-  for (int d = threadIdx.x; d <= ns; d += blockDim.x) info[3 + d] = d < ns ? int64_t(poff[d]) : P;
+  for (int d = threadIdx.x; d <= ns; d += blockDim.x) info[1 + d] = d < ns ? int64_t(poff[d]) : P;
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     info[0] = P;
-    info[1] = eoff[1];
-    info[2] = poff[1];
     if (P >= 0 && P <= nnz) prp[P] = int32_t(nnz);
   }
 }
 
-// What build_segments produced.  P == 0: segmenting does not apply.  Pairs
-// [0, P0) and entries [0, E0) are slab 0; with nblk_w > 0 they go through
-// k_spmv_win and the rest through the raw SpMV.
+// What build_segments produced.  P == 0: segmenting does not apply.
 struct SegInfo {
   int32_t sbits = 0, ns = 0;
-  int64_t P = 0, E0 = 0, P0 = 0;
-  int32_t nblk_w = 0, nwin = 0;
+  int64_t P = 0;
   bool relabelled = false;   // the count pass wrote the relabelled entries
 };
 
@@ -1948,7 +1528,7 @@ pp_status col_offsets(uint32_t *cnt, int32_t ntiles, int32_t ns, uint32_t *bsum,
 // synchronizes the stream once.
 template <typename V>
 pp_status build_segments(const Layout<V> &L, const int32_t *rp, int32_t *col, V *val, int64_t n,
-                         int64_t nnz, int slab_log2, int hot_windows, const RelabelSrc *rl,
+                         int64_t nnz, int slab_log2, const RelabelSrc *rl,
                          SegInfo *out, hipStream_t s) {
   *out = SegInfo{};
   int sbits = slab_log2;
@@ -1980,61 +1560,19 @@ pp_status build_segments(const Layout<V> &L, const int32_t *rp, int32_t *col, V 
   hipLaunchKernelGGL((k_seg_tile<V, true, false>), dim3(ntiles), dim3(kThreads), 0, s, rp, col,
                      val, n32, RelabelSrc{}, L.seg_coord, sbits, ns, dbits, ntiles, L.seg_cnt,
                      L.seg_pcnt, L.seg_fmask, nullptr, L.seg_col, L.seg_val, L.prp, L.pair_row);
-  hipLaunchKernelGGL(k_seg_info, dim3(1), dim3(256), 0, s, L.seg_cnt, L.seg_pcnt, ns, nnz,
-                     L.total, L.prp, L.info);
+  hipLaunchKernelGGL(k_seg_info, dim3(1), dim3(256), 0, s, L.seg_pcnt, ns, nnz, L.total, L.prp,
+                     L.info);
   PP_LAUNCHED("k_seg_tile (scatter)/k_seg_info");
-  int64_t info[4 + kMaxSlabs] = {};
-  PP_HIP(hipMemcpyAsync(info, L.info, sizeof(int64_t) * size_t(4 + ns), hipMemcpyDeviceToHost, s));
+  int64_t info[2 + kMaxSlabs] = {};
+  PP_HIP(hipMemcpyAsync(info, L.info, sizeof(int64_t) * size_t(2 + ns), hipMemcpyDeviceToHost, s));
   PP_HIP(hipStreamSynchronize(s));
-  const int64_t P = info[0], E0 = info[1], P0 = info[2];
+  const int64_t P = info[0];
   if (P <= 0 || P > nnz || P + nnz > int64_t(INT32_MAX)) return PP_OK;
   SegInfo si;
   si.relabelled = out->relabelled;
   si.sbits = sbits;
   si.ns = ns;
   si.P = P;
-
-  // Slab 0 through LDS windows when it is dense enough to pay for loading
-  // its windows (or when asked to).
-  const int wbits = sbits - win_bits<V>();
-  const bool win = hot_windows != 0 && wbits >= 1 && (1 << wbits) <= kMaxWins && P0 > 0 &&
-                   (hot_windows == 1 || E0 >= 8 * P0);
-  if (win) {
-    const int32_t nwin = 1 << wbits;
-    const int32_t nblk = int32_t((P0 * kWinRowCost + E0 + kWinBlock - 1) / kWinBlock);
-    hipLaunchKernelGGL(k_win_bounds, dim3(grid_for(int64_t(nblk) + 1, 256, 4096)), dim3(256), 0,
-                       s, L.prp, int32_t(P0), nblk, L.wb);
-    hipLaunchKernelGGL(k_win_tiles, dim3(grid_for(int64_t(nblk) + 1, 256, 4096)), dim3(256), 0,
-                       s, L.wb, nblk, L.wtb);
-    PP_LAUNCHED("k_win_bounds/k_win_tiles");
-    st = exscan_u32(L.wtb, L.wtb, int64_t(nblk) + 1, L.seg_scan, nullptr, s);
-    if (st != PP_OK) return st;
-    const int64_t tmax = E0 / kWinTile + nblk + 1;   // >= the tiles the blocks need
-    hipLaunchKernelGGL(k_win_count, dim3(unsigned(tmax)), dim3(kThreads), 0, s, L.seg_col, L.wb,
-                       L.wtb, nblk, nwin, wbits, win_bits<V>(), L.seg_cnt);
-    PP_LAUNCHED("k_win_count");
-    st = exscan_u32(L.seg_cnt, L.seg_cnt, tmax * nwin, L.seg_scan, nullptr, s);
-    if (st != PP_OK) return st;
-    // Reordered slab 0 goes to the relabelled-entry region (free now), then
-    // back over the slab-major copy.
-    uint32_t *tmp_pk = reinterpret_cast<uint32_t *>(L.col2);
-    V *tmp_val = L.val2;
-    hipLaunchKernelGGL(k_win_scatter<V>, dim3(unsigned(tmax)), dim3(kThreads), 0, s, L.seg_col,
-                       L.seg_val, L.prp, L.wb, L.wtb, nblk, nwin, wbits, L.seg_cnt,
-                       tmp_pk, tmp_val);
-    hipLaunchKernelGGL(k_win_chunks, dim3(grid_for(int64_t(nblk) * (nwin + 1), 256, 4096)),
-                       dim3(256), 0, s, L.wb, L.wtb, L.seg_cnt, nblk, nwin, L.wchunk);
-    PP_LAUNCHED("k_win_scatter/k_win_chunks");
-    if ((st = copy_bytes(L.seg_col, tmp_pk, size_t(E0) * 4, s)) != PP_OK) return st;
-    if ((st = copy_bytes(L.seg_val, tmp_val, size_t(E0) * sizeof(V), s)) != PP_OK) return st;
-    hipLaunchKernelGGL(k_rebase, dim3(grid_for(P - P0 + 1, 256, 4096)), dim3(256), 0, s,
-                       L.prp + P0, P - P0 + 1, int32_t(E0));
-    PP_LAUNCHED("k_rebase");
-    si.E0 = E0;
-    si.P0 = P0;
-    si.nblk_w = nblk;
-    si.nwin = nwin;
-  }
 
   // Row-major index of the pairs for the combine (see k_pair_place): the
   // row cursors live in the relabelling's key buffer, free by now.
@@ -2049,7 +1587,7 @@ pp_status build_segments(const Layout<V> &L, const int32_t *rp, int32_t *col, V 
   int32_t *cursor = reinterpret_cast<int32_t *>(L.keys_out);
   if ((st = copy_bytes(cursor, L.rpp, size_t(n + 1) * 4, s)) != PP_OK) return st;
   for (int32_t d = 0; d < ns; ++d) {
-    const int64_t p0 = info[3 + d], p1 = info[4 + d];
+    const int64_t p0 = info[1 + d], p1 = info[2 + d];
     if (p1 > p0)
       hipLaunchKernelGGL(k_pair_place, dim3(grid_for(p1 - p0, 256, 8192)), dim3(256), 0, s,
                          L.pair_row, p0, p1, cursor, L.pidx);
@@ -2148,7 +1686,7 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
   if (segment) {
     const RelabelSrc rl{AT0.row_ptr, AT0.col, L.order, L.newlabel, AT0.val, hot};
     st = build_segments<V>(L, rp, const_cast<int32_t *>(col), const_cast<V *>(val), n, nnz,
-                           slab_log2, g_cfg.hot_windows, weights ? &rl : nullptr, &si, s);
+                           slab_log2, weights ? &rl : nullptr, &si, s);
     if (st != PP_OK) return st;
   }
   if (weights && !si.relabelled) {
@@ -2159,17 +1697,14 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
   }
   if (segment) {
     if (si.P > 0) {
-      Pr = si.P - si.P0;
-      const int64_t Er = nnz - si.E0;
-      nbp = int32_t((Pr + Er + D - 1) / D);
+      Pr = si.P;
+      nbp = int32_t((Pr + nnz + D - 1) / D);
       ncomb = int32_t((n + si.P + kCombItems - 1) / kCombItems);
-      if (Pr > 0) {
-        hipLaunchKernelGGL(k_partition, dim3(grid_for(int64_t(nbp) + 1, 256, 4096)), dim3(256),
-                           0, s, L.prp + si.P0, int32_t(Pr), int32_t(Er), nbp, D, L.coord);
-        hipLaunchKernelGGL(k_block_flags, dim3(grid_for(nbp, 256, 4096)), dim3(256), 0, s,
-                           L.prp + si.P0, int32_t(Pr), nbp, L.coord, L.carry_row, L.closes);
-        PP_LAUNCHED("k_partition/k_block_flags (pairs)");
-      }
+      hipLaunchKernelGGL(k_partition, dim3(grid_for(int64_t(nbp) + 1, 256, 4096)), dim3(256), 0,
+                         s, L.prp, int32_t(Pr), int32_t(nnz), nbp, D, L.coord);
+      hipLaunchKernelGGL(k_block_flags, dim3(grid_for(nbp, 256, 4096)), dim3(256), 0, s, L.prp,
+                         int32_t(Pr), nbp, L.coord, L.carry_row, L.closes);
+      PP_LAUNCHED("k_partition/k_block_flags (pairs)");
     }
   }
 
@@ -2209,18 +1744,11 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
     done = it + 1;
     if ((st = timed_begin(s)) != PP_OK) return st;
     if (si.P > 0) {
-      if (si.nblk_w > 0)
-        hipLaunchKernelGGL(k_spmv_win<V>, dim3(si.nblk_w), dim3(kWinThreads), 0, s,
-                           reinterpret_cast<const uint32_t *>(L.seg_col), L.seg_val, x, n32,
-                           L.wb, L.wchunk, si.nwin, L.seg_part);
-      if (Pr > 0) {
-        launch_spmv<V, true>(ipt, nbp, s, L.prp + si.P0, L.seg_col + si.E0, L.seg_val + si.E0, x,
-                             nullptr, int32_t(Pr), L.coord, c, t_in, nullptr, L.blk_carry,
-                             L.blk_head, L.seg_part + si.P0);
-        hipLaunchKernelGGL(k_fix_raw<V>, dim3(grid_for(nbp, 256, 4096)), dim3(256), 0, s,
-                           L.seg_part + si.P0, nbp, L.coord, L.closes, L.carry_row, L.blk_carry,
-                           L.blk_head);
-      }
+      launch_spmv<V, true>(ipt, nbp, s, L.prp, L.seg_col, L.seg_val, x, nullptr, int32_t(Pr),
+                           L.coord, c, t_in, nullptr, L.blk_carry, L.blk_head, L.seg_part);
+      hipLaunchKernelGGL(k_fix_raw<V>, dim3(grid_for(nbp, 256, 4096)), dim3(256), 0, s,
+                         L.seg_part, nbp, L.coord, L.closes, L.carry_row, L.blk_carry,
+                         L.blk_head);
       hipLaunchKernelGGL(k_seg_combine<V>, dim3(ncomb), dim3(kThreads), 0, s, L.seg_part, L.rpp,
                          L.pidx, L.cstart, c, t_in, yv, L.blk_ysum);
       hipLaunchKernelGGL(k_sum_blocks, dim3(1), dim3(1024), 0, s, L.blk_ysum, ncomb, w, s_out,
@@ -2298,24 +1826,21 @@ int32_t kernel_times(float *ms, int32_t cap) {
   return n;
 }
 
-pp_status set_k3_config(int32_t ipt, int32_t rhs_lanes, int32_t slab_log2, int32_t hot_windows) {
+pp_status set_k3_config(int32_t ipt, int32_t rhs_lanes, int32_t slab_log2) {
   if (ipt != 4 && ipt != 8 && ipt != 16) return fail(PP_EINVAL, "items per thread %d", ipt);
   if (rhs_lanes != 0 && (rhs_lanes < 2 || rhs_lanes > 64 || (rhs_lanes & (rhs_lanes - 1))))
     return fail(PP_EINVAL, "rhs lanes %d", rhs_lanes);
   if (slab_log2 < -1 || slab_log2 > 30) return fail(PP_EINVAL, "slab log2 %d", slab_log2);
-  if (hot_windows < -1 || hot_windows > 1) return fail(PP_EINVAL, "hot windows %d", hot_windows);
   g_cfg.ipt = ipt;
   g_cfg.rhs_lanes = rhs_lanes;
   g_cfg.slab_log2 = slab_log2;
-  g_cfg.hot_windows = hot_windows;
   return PP_OK;
 }
 
-void get_k3_config(int32_t *ipt, int32_t *rhs_lanes, int32_t *slab_log2, int32_t *hot_windows) {
+void get_k3_config(int32_t *ipt, int32_t *rhs_lanes, int32_t *slab_log2) {
   *ipt = g_cfg.ipt;
   *rhs_lanes = g_cfg.rhs_lanes;
   *slab_log2 = g_cfg.slab_log2;
-  *hot_windows = g_cfg.hot_windows;
 }
 
 size_t pagerank_ws_bytes(int64_t n, int64_t nnz_cap, pp_dtype dt, int32_t nrhs) {

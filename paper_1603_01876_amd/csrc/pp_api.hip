@@ -282,18 +282,33 @@ int64_t pp_graphs_max_n(pp_dtype dt) {
   return graphs_max_n(dt);
 }
 
-pp_status pp_pagerank_graphs(int32_t ngraphs, const pp_graph *graphs, int64_t max_n, pp_dtype dt,
-                             int32_t iters, double c, int32_t use_graph, void *ws, size_t ws_bytes,
+pp_status pp_pagerank_graphs(int32_t ngraphs, const pp_graph *graphs, pp_dtype dt, int32_t iters,
+                             double c, int32_t use_graph, void *ws, size_t ws_bytes,
                              void *stream) {
   if (ngraphs < 1 || ngraphs > (1 << 24)) return fail(PP_EINVAL, "pp_pagerank_graphs: ngraphs %d", ngraphs);
   if (!graphs) return fail(PP_EINVAL, "pp_pagerank_graphs: null graphs");
   if (dt != PP_F64 && dt != PP_F32) return fail(PP_EINVAL, "pp_pagerank_graphs: dtype %d", int(dt));
   if (iters < 0) return fail(PP_EINVAL, "pp_pagerank_graphs: iters %d", iters);
   if (!(c >= 0.0 && c <= 1.0)) return fail(PP_EINVAL, "pp_pagerank_graphs: c = %g", c);
-  if (max_n < 1 || max_n > graphs_max_n(dt))
-    return fail(PP_ERANGE, "pp_pagerank_graphs: max_n %lld outside [1, %lld]", (long long)max_n,
-                (long long)graphs_max_n(dt));
   if (use_graph && !stream) return fail(PP_EINVAL, "pp_pagerank_graphs: graph capture needs a stream");
+  // Every descriptor is checked here, on the host: the kernel takes each
+  // graph as it is.
+  const int64_t limit = graphs_max_n(dt);
+  int64_t max_n = 0;
+  for (int32_t g = 0; g < ngraphs; ++g) {
+    const pp_graph &G = graphs[g];
+    if (G.n < 1 || G.nnz < 0)
+      return fail(PP_EINVAL, "pp_pagerank_graphs: graph %d has n %lld, nnz %lld", g,
+                  (long long)G.n, (long long)G.nnz);
+    if (G.n > limit)
+      return fail(PP_ERANGE, "pp_pagerank_graphs: graph %d has n %lld > %lld", g,
+                  (long long)G.n, (long long)limit);
+    if (G.n + G.nnz > INT32_MAX)
+      return fail(PP_ERANGE, "pp_pagerank_graphs: graph %d: n + nnz beyond int32", g);
+    if (!G.row_ptr || !G.r || (G.nnz > 0 && (!G.col || !G.val)))
+      return fail(PP_EINVAL, "pp_pagerank_graphs: graph %d lacks an array", g);
+    if (G.n > max_n) max_n = G.n;
+  }
   const size_t need = graphs_ws_bytes(ngraphs);
   if (!ws || ws_bytes < need) return fail(PP_EWORKSPACE, "pp_pagerank_graphs: workspace needs %zu bytes", need);
   return launch_graphs(ngraphs, graphs, max_n, dt, iters, c, use_graph, ws, ws_bytes,
@@ -301,13 +316,13 @@ pp_status pp_pagerank_graphs(int32_t ngraphs, const pp_graph *graphs, int64_t ma
 }
 
 pp_status pp_set_k3_config(const pp_k3_config *cfg) {
-  if (!cfg) return set_k3_config(8, 0, -1, 0);
-  return set_k3_config(cfg->items_per_thread, cfg->rhs_lanes, cfg->slab_log2, cfg->hot_windows);
+  if (!cfg) return set_k3_config(8, 0, -1);
+  return set_k3_config(cfg->items_per_thread, cfg->rhs_lanes, cfg->slab_log2);
 }
 
 pp_status pp_get_k3_config(pp_k3_config *cfg) {
   if (!cfg) return fail(PP_EINVAL, "pp_get_k3_config: null");
-  get_k3_config(&cfg->items_per_thread, &cfg->rhs_lanes, &cfg->slab_log2, &cfg->hot_windows);
+  get_k3_config(&cfg->items_per_thread, &cfg->rhs_lanes, &cfg->slab_log2);
   return PP_OK;
 }
 

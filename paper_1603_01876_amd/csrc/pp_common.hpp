@@ -292,8 +292,8 @@ pp_status launch_graphs(int32_t ngraphs, const pp_graph *graphs, int64_t max_n, 
                         int32_t iters, double c, int32_t use_graph, void *ws, size_t ws_bytes,
                         hipStream_t s);
 
-pp_status set_k3_config(int32_t ipt, int32_t rhs_lanes, int32_t slab_log2, int32_t hot_windows);
-void get_k3_config(int32_t *ipt, int32_t *rhs_lanes, int32_t *slab_log2, int32_t *hot_windows);
+pp_status set_k3_config(int32_t ipt, int32_t rhs_lanes, int32_t slab_log2);
+void get_k3_config(int32_t *ipt, int32_t *rhs_lanes, int32_t *slab_log2);
 pp_status set_kernel_timing(bool enable);
 int32_t kernel_times(float *ms, int32_t cap);
 

@@ -47,7 +47,7 @@ class _Csr(ctypes.Structure):
 
 class _K3Config(ctypes.Structure):
     _fields_ = [("items_per_thread", ctypes.c_int32), ("rhs_lanes", ctypes.c_int32),
-                ("slab_log2", ctypes.c_int32), ("hot_windows", ctypes.c_int32)]
+                ("slab_log2", ctypes.c_int32)]
 
 
 class _Graph(ctypes.Structure):
@@ -82,8 +82,8 @@ SIGNATURES = {
     "pp_init_r": (ctypes.c_int, [_I64, _I32, _U64, ctypes.c_int, _VP, _VP, _SZ, _VP]),
     "pp_pagerank": (ctypes.c_int, [ctypes.POINTER(_Csr), ctypes.c_int, _I32, _I32, _D, _VP,
                                    _VP, _VP, _VP, _SZ, _VP]),
-    "pp_pagerank_graphs": (ctypes.c_int, [_I32, _VP, _I64, ctypes.c_int, _I32, _D, _I32, _VP,
-                                          _SZ, _VP]),
+    "pp_pagerank_graphs": (ctypes.c_int, [_I32, _VP, ctypes.c_int, _I32, _D, _I32, _VP, _SZ,
+                                          _VP]),
     "pp_pagerank_converge": (ctypes.c_int, [ctypes.POINTER(_Csr), ctypes.c_int, _I32, _D, _D,
                                             ctypes.c_int, _VP, _VP, _VP, _VP, _VP,
                                             ctypes.POINTER(_I32), _VP, _SZ, _VP]),
@@ -378,22 +378,21 @@ def graphs_max_n(dtype="f32") -> int:
 
 
 class GraphBatch:
-    """A batch for pagerank_graphs(): (CSR, r, sums_or_None, seed) per graph
-    and their device descriptor table, largest graphs first."""
+    """A batch for pagerank_graphs(): (CSR, r, sums_or_None, seed) per graph,
+    largest graphs first, and their descriptor table (host memory; the
+    library copies it into the batch's workspace on every call)."""
 
     def __init__(self, items, dtype="f32"):
         self.dtype = dtype_code(dtype)
         self.items = sorted(items, key=lambda it: -(it[0].n + it[0].nnz))
-        arr = (_Graph * len(self.items))()
+        self.table = (_Graph * len(self.items))()
         for i, (AT, r, sums, seed) in enumerate(self.items):
             if AT.dtype != self.dtype or dtype_code(r.dtype) != self.dtype:
                 raise PPError(PP_EINVAL, "GraphBatch", "dtype mismatch")
-            arr[i] = _Graph(AT.n, AT.nnz, AT.row_ptr.data_ptr(), AT.col.data_ptr(),
-                            AT.val.data_ptr(), r.data_ptr(), _ptr(sums) or 0,
-                            seed & (2**64 - 1))
-        raw = bytes(arr)
+            self.table[i] = _Graph(AT.n, AT.nnz, AT.row_ptr.data_ptr(), AT.col.data_ptr(),
+                                   AT.val.data_ptr(), r.data_ptr(), _ptr(sums) or 0,
+                                   seed & (2**64 - 1))
         dev = self.items[0][1].device
-        self.table = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev)
         self.max_n = max(AT.n for AT, *_ in self.items)
         self.ws = torch.empty(workspace_bytes(K3_GRAPHS, 1, len(self.items), self.dtype),
                               dtype=torch.uint8, device=dev)
@@ -402,29 +401,25 @@ class GraphBatch:
         return len(self.items)
 
 
-def pagerank_graphs(batch: GraphBatch, iters: int = 20, c: float = 0.85, use_graph=True,
-                    max_n: int | None = None):
+def pagerank_graphs(batch: GraphBatch, iters: int = 20, c: float = 0.85, use_graph=True):
     """K3 for every graph of the batch in one persistent launch (r and sums
     filled in place).  With use_graph the launch is recorded once into a
     hipGraph and replayed on later calls; it needs a non-default stream."""
-    mx = batch.max_n if max_n is None else max_n
-    _check(lib().pp_pagerank_graphs(len(batch), batch.table.data_ptr(), mx, batch.dtype, iters,
-                                    c, int(bool(use_graph)), batch.ws.data_ptr(),
+    _check(lib().pp_pagerank_graphs(len(batch), ctypes.addressof(batch.table), batch.dtype,
+                                    iters, c, int(bool(use_graph)), batch.ws.data_ptr(),
                                     batch.ws.numel(), _stream()), "pp_pagerank_graphs")
 
 
-def set_k3_config(items_per_thread: int = 8, rhs_lanes: int = 0, slab_log2: int = -1,
-                  hot_windows: int = 0) -> None:
+def set_k3_config(items_per_thread: int = 8, rhs_lanes: int = 0, slab_log2: int = -1) -> None:
     """Launch configuration of pagerank() (see pp_set_k3_config)."""
-    cfg = _K3Config(items_per_thread, rhs_lanes, slab_log2, hot_windows)
+    cfg = _K3Config(items_per_thread, rhs_lanes, slab_log2)
     _check(lib().pp_set_k3_config(ctypes.addressof(cfg)), "pp_set_k3_config")
 
 
-def get_k3_config() -> tuple[int, int, int, int]:
+def get_k3_config() -> tuple[int, int, int]:
     cfg = _K3Config()
     _check(lib().pp_get_k3_config(ctypes.addressof(cfg)), "pp_get_k3_config")
-    return (int(cfg.items_per_thread), int(cfg.rhs_lanes), int(cfg.slab_log2),
-            int(cfg.hot_windows))
+    return int(cfg.items_per_thread), int(cfg.rhs_lanes), int(cfg.slab_log2)
 
 
 # ------------------------------------------------------------ instrumentation

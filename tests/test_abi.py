@@ -156,27 +156,55 @@ def test_pagerank_converge_rejects_bad_args():
 
 
 def test_pagerank_graphs_rejects_bad_args():
-    # Every call below fails a host-side check before anything is enqueued,
-    # so the descriptor and workspace addresses are never dereferenced.
+    # Every call below fails a host-side check before anything is enqueued;
+    # the descriptors' device addresses are never dereferenced.
     L = native.lib()
     mx = native.graphs_max_n("f32")
     assert mx > 0 and mx % 64 == 0
     assert 0 < native.graphs_max_n("f64") <= mx      # two n-vectors of 8 B instead of 4 B
 
-    def call(ng=4, g=16, max_n=64, dt=1, iters=20, damp=0.85, use_graph=0, ws=64, wsb=1 << 20,
+    def table(*graphs):
+        t = (native._Graph * len(graphs))()
+        for i, g in enumerate(graphs):
+            t[i] = native._Graph(*g)
+        return t
+
+    good = (100, 50, 8, 16, 24, 32, 0, 1)        # n, nnz, row_ptr, col, val, r, sums, seed
+    ok = table(good, good)
+
+    def call(ng=2, g=ok, dt=1, iters=20, damp=0.85, use_graph=0, ws=64, wsb=1 << 20,
              stream=None):
-        return L.pp_pagerank_graphs(ng, g, max_n, dt, iters, damp, use_graph, ws, wsb, stream)
+        gp = None if g is None else ctypes.addressof(g)
+        return L.pp_pagerank_graphs(ng, gp, dt, iters, damp, use_graph, ws, wsb, stream)
 
     assert call(ng=0) == native.PP_EINVAL
     assert call(g=None) == native.PP_EINVAL
     assert call(dt=5) == native.PP_EINVAL
     assert call(iters=-1) == native.PP_EINVAL
     assert call(damp=1.5) == native.PP_EINVAL
-    assert call(max_n=0) == native.PP_ERANGE
-    assert call(max_n=mx + 64) == native.PP_ERANGE
     assert call(use_graph=1) == native.PP_EINVAL      # capture needs a stream
     assert call(ws=None) == native.PP_EWORKSPACE
     assert call(wsb=1) == native.PP_EWORKSPACE
+    # The workspace holds the descriptor table: it grows with the batch.
+    assert native.workspace_bytes(native.K3_GRAPHS, 1, 1000, "f32") > \
+        native.workspace_bytes(native.K3_GRAPHS, 1, 10, "f32")
+    # Descriptors: above the on-chip bound, empty or negative, over int32,
+    # missing arrays.  The bad descriptor may sit anywhere in the table.
+    big = (mx + 1,) + good[1:]
+    assert call(g=table(good, big)) == native.PP_ERANGE
+    assert call(g=table((native.graphs_max_n("f64") + 1,) + good[1:], good), dt=0) == \
+        native.PP_ERANGE
+    assert call(g=table((0,) + good[1:], good)) == native.PP_EINVAL
+    assert call(g=table(good, (100, -1) + good[2:])) == native.PP_EINVAL
+    assert call(g=table(good, (100, (1 << 31) - 50) + good[2:])) == native.PP_ERANGE
+    assert call(g=table(good, (100, 50, 0) + good[3:])) == native.PP_EINVAL     # no row_ptr
+    assert call(g=table(good, (100, 50, 8, 0) + good[4:])) == native.PP_EINVAL  # no col
+    assert call(g=table(good, (100, 50, 8, 16, 0) + good[5:])) == native.PP_EINVAL  # no val
+    assert call(g=table(good, (100, 50, 8, 16, 24, 0) + good[6:])) == native.PP_EINVAL  # no r
+    # A graph without entries needs no col / val: it passes the descriptor
+    # checks and fails only on the (too small) workspace.
+    assert call(g=table(good, (100, 0, 8, 0, 0, 32, 0, 1)), wsb=1) == native.PP_EWORKSPACE
+    assert call(g=table((mx,) + good[1:], good), wsb=1) == native.PP_EWORKSPACE
 
 
 def test_edge_file_calls_reject_bad_args(tmp_path):
@@ -227,14 +255,14 @@ def test_product_path_has_no_cpu_fallback():
 
 
 def test_k3_config_roundtrip_and_validation():
-    native.set_k3_config(16, 0, 19, 1)
-    assert native.get_k3_config() == (16, 0, 19, 1)
-    for bad in ((8, 0, -2), (8, 0, 31), (5, 0, 0), (8, 3, 0), (8, 0, 0, 2), (8, 0, 0, -2)):
+    native.set_k3_config(16, 0, 19)
+    assert native.get_k3_config() == (16, 0, 19)
+    for bad in ((8, 0, -2), (8, 0, 31), (5, 0, 0), (8, 3, 0), (8, 128, 0)):
         with pytest.raises(native.PPError):
             native.set_k3_config(*bad)
-    assert native.get_k3_config() == (16, 0, 19, 1)   # a rejected call changes nothing
+    assert native.get_k3_config() == (16, 0, 19)   # a rejected call changes nothing
     native.lib().pp_set_k3_config(None)
-    assert native.get_k3_config() == (8, 0, -1, 0)
+    assert native.get_k3_config() == (8, 0, -1)
 
 
 def test_transpose_validation():

@@ -11,12 +11,11 @@ from paper_1603_01876_amd import native
 
 def test_single_vector_candidates():
     plain = autotune.candidates(1)
-    assert plain == [(8, 0, 0, 0, False), (16, 0, 0, 0, False), (16, 0, 18, 0, False),
-                     (16, 0, 19, 0, False), (16, 0, 20, 0, False)]
+    assert plain == [(8, 0, 0, False), (16, 0, 0, False), (16, 0, 18, False),
+                     (16, 0, 19, False), (16, 0, 20, False)]
     both = autotune.candidates(1, (False, True))
-    assert both[:5] == plain and [c[:4] for c in both[5:]] == [c[:4] for c in plain]
-    assert all(c[4] for c in both[5:])
-    assert all(c[3] == 0 for c in both)          # LDS windows are not a candidate
+    assert both[:5] == plain and [c[:3] for c in both[5:]] == [c[:3] for c in plain]
+    assert all(c[3] for c in both[5:])
 
 
 def test_spmm_lane_candidates():
@@ -25,12 +24,12 @@ def test_spmm_lane_candidates():
     assert [c[1] for c in autotune.candidates(64)] == [64]
     assert [c[1] for c in autotune.candidates(2, (False, True))] == [2, 2, 64, 64]
     for c in autotune.candidates(17, (False, True)):
-        native.set_k3_config(*c[:4])           # every candidate is a valid configuration
+        native.set_k3_config(*c[:3])           # every candidate is a valid configuration
     native.set_k3_config()
 
 
 def test_name_and_key():
-    assert autotune.name((16, 0, 19, 0, True)) == "16,0,19,0,1"
+    assert autotune.name((16, 0, 19, True)) == "16,0,19,1"
     AT = SimpleNamespace(n=1 << 26, nnz=1051749331)
     k = autotune.key(AT, "f32", 1, True, 20)
     assert k.endswith("|n2^26|nnz2^29|f32|k1|it20|weights1")
@@ -42,12 +41,12 @@ def test_name_and_key():
 def test_cache_hit_applies_the_stored_choice(tmp_path):
     AT = SimpleNamespace(n=1 << 20, nnz=15_900_000)
     cache = tmp_path / "tuning.json"
-    entry = {"config": [16, 0, 19, 0], "relabel": True, "ms": {"16,0,19,0,1": 1.0}}
+    entry = {"config": [16, 0, 19], "relabel": True, "ms": {"16,0,19,1": 1.0}}
     cache.write_text(json.dumps({autotune.key(AT, "f32", 1, True, 20): entry}))
     native.set_k3_config()
     got = autotune.tune(AT, "f32", 1, weights=object(), iters=20, cache=str(cache))
     assert got == entry
-    assert native.get_k3_config() == (16, 0, 19, 0)
+    assert native.get_k3_config() == (16, 0, 19)
     native.set_k3_config()
 
 

@@ -50,7 +50,7 @@ def test_measured_traffic_follows_the_committed_summary():
     assert l2["requests_per_s"] == pytest.approx(
         float(f["spmv_l2_read_requests_per_launch"]) / (float(f["spmv_launch_us"]) * 1e-6))
     # another launch configuration, relabelling choice, scale or dtype: none
-    other = (cfg[0], cfg[1], cfg[2] + 1, cfg[3])
+    other = (cfg[0], cfg[1], cfg[2] + 1)
     assert bench.measured_traffic(26, "f32", other, relabel) is None
     assert bench.measured_traffic(26, "f32", cfg, not relabel) is None
     assert bench.measured_traffic(25, "f32", cfg, relabel) is None
@@ -71,11 +71,10 @@ def test_measured_traffic_ignores_a_summary_of_other_source(tmp_path, monkeypatc
 
 
 def test_spmv_label_names_the_timed_launches():
-    assert bench.spmv_label((16, 0, 19, 0), "f32") == (
+    assert bench.spmv_label((16, 0, 19), "f32") == (
         "segmented SpMV iteration, slabs of 2^19 columns: k_spmv<float,16,raw> + "
         "k_fix_raw<float> + k_seg_combine<float> + k_sum_blocks")
-    assert bench.spmv_label((8, 0, 0, 0), "f64") == "k_spmv<double,8> + k_finish<double>"
-    assert "k_spmv_win<float>" in bench.spmv_label((16, 0, 19, 1), "f32")
+    assert bench.spmv_label((8, 0, 0), "f64") == "k_spmv<double,8> + k_finish<double>"
 
 
 def test_more_than_one_gpu_is_refused():

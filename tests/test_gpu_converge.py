@@ -55,7 +55,7 @@ def pick_tol(deltas, target):
 
 def gpu_run(AT, n, dtype, max_iters, tol, mode, d_out, weights=None, slab=None, seed=7):
     if slab is not None:
-        pp.set_k3_config(8, 0, slab, 0)
+        pp.set_k3_config(8, 0, slab)
     r = pp.init_r(n, seed, dtype)
     dt = None if d_out is None else torch.as_tensor(np.asarray(d_out)).to(torch.int32).cuda()
     w = None if weights is None else torch.as_tensor(np.asarray(weights)).to(torch.int32).cuda()

@@ -99,21 +99,37 @@ def test_graphs_hipgraph_replays():
     check_batch(items, want, "f32")
 
 
-@pytest.mark.skip(reason="this case (graphs above max_n, skipped inside the persistent kernel) "
-                         "stopped making progress on the GPU once and the cause has not been "
-                         "found by reading the code; it stays off the GPU until it is")
-def test_graphs_skip_oversized_and_reject_bad_bound():
-    items, want = small_batch(6, 6, 9, "f32", seed=9)
-    gb = pp.GraphBatch(items, "f32")
+def test_graphs_reject_oversized_and_malformed():
+    # Descriptors are checked on the host: a graph above the on-chip bound,
+    # or one that lacks an array, fails the whole call before any launch,
+    # and every output stays as it was.  The valid part of the batch then
+    # runs and matches the oracle.
+    items, want = small_batch(3, 6, 8, "f32", seed=9)
+    limit = pp.graphs_max_n("f32")
+    s = workloads.GraphSpec(scale=limit.bit_length())
+    assert s.n > limit
+    u, v = pp.generate(s)
+    us, vs = pp.sort(s.scale, u, v)
+    AT, _, _ = pp.filter(s.scale, us, vs, "f32", degrees=False)
+    big = torch.empty(AT.n, dtype=torch.float32, device="cuda")
     for _, r, _, _ in items:
         r.fill_(-1.0)
-    bound = min(AT.n for AT, *_ in items)          # only the smallest graphs fit
-    pp.pagerank_graphs(gb, use_graph=False, max_n=bound)
-    for (AT, r, sums, _), (wr, ws) in zip(items, want):
-        if AT.n <= bound:
-            assert rel_l1(host(r), wr) <= TOL["f32"]
-        else:
-            assert (host(r) == -1.0).all()
+    big.fill_(-1.0)
+    gb = pp.GraphBatch(items + [(AT, big, None, 1)], "f32")
     with pytest.raises(pp.PPError) as e:
-        pp.pagerank_graphs(gb, use_graph=False, max_n=pp.graphs_max_n("f32") + 64)
+        pp.pagerank_graphs(gb, use_graph=False)
     assert e.value.status == pp.PP_ERANGE
+    gb = pp.GraphBatch(items, "f32")
+    k = next(i for i in range(len(gb)) if gb.table[i].nnz > 0)
+    keep = gb.table[k].col
+    gb.table[k].col = 0                      # entries but no column array
+    with pytest.raises(pp.PPError) as e:
+        pp.pagerank_graphs(gb, use_graph=False)
+    assert e.value.status == pp.PP_EINVAL
+    torch.cuda.synchronize()
+    for _, r, _, _ in items:
+        assert bool((r == -1.0).all())
+    assert bool((big == -1.0).all())
+    gb.table[k].col = keep
+    pp.pagerank_graphs(gb, use_graph=False)
+    check_batch(items, want, "f32")

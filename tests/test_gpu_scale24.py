@@ -1,94 +1,110 @@
 """Precision form at S = 24 (N = 2^24, M = 2^28): the whole GPU pipeline in
-FP32 and in FP64 against the FP64 oracle on the same seed.
+FP64 and FP32 against the FP64 oracle on the same seed.
 
-K1 and K2 must match the oracle bit for bit (sorted edges, d_in, d_out,
-CSR(A^T) and its row form); K3 must reach the oracle's r_20 within 1e-12
-relative L1 in FP64 and 1e-5 in FP32, with the K3 launch configuration the
-library picks by itself (segmented, relabelled by d_out).  The FP32 - FP64
-gap on the GPU is printed with the errors.
-
-The oracle is single-threaded and needs several minutes of CPU at this
-size, so the test runs only when PP_SLOW=1 is set.
+K0, K1 and K2 must match the oracle bit for bit over their full arrays
+(edges, sorted edges, d_in, d_out, nnz, CSR(A^T) with FP64 and FP32 values,
+the row form CSR(A)), compared as digests against the values the oracle
+wrote into tests/golden/kron_s24_pipeline.json; the initial vectors must
+match bit for bit; K3's r_20 must reach the oracle's within 1e-12 relative
+L1 in FP64 and 1e-5 in FP32, in every launch configuration the library
+offers (default, one pass, column slabs, with and without relabelling).
 """
-import os
-import sys
-import time
-
 import numpy as np
 import pytest
 import torch
 
-import oracle
+import pipeline_golden as pg
 from paper_1603_01876_amd import native as pp
 from paper_1603_01876_amd import workloads
 
-pytestmark = [pytest.mark.gpu, pytest.mark.slow,
-              pytest.mark.skipif(os.environ.get("PP_SLOW") != "1",
-                                 reason="S=24 oracle takes minutes of CPU; set PP_SLOW=1")]
+pytestmark = pytest.mark.gpu
 
 S = 24
-C = workloads.DAMPING
+TAG = "scale24"
 
 
-def say(msg):
-    print(f"[scale24] {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
-
-
-def rel_l1(a, b):
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
-    return float(np.abs(a - b).sum() / np.abs(b).sum())
-
-
-def test_precision_form_scale24():
+@pytest.fixture(scope="module")
+def run():
     assert torch.cuda.is_available()
+    g = pg.load(S)
     spec = workloads.pipeline(S)
-    seed = workloads.BASE_SEED
-    say("GPU K0-K2")
+    assert (spec.n, spec.m, spec.seed) == (g["vertices"], g["edges"], g["seed"])
+    pg.say(TAG, "GPU K0-K2")
     u, v = pp.generate(spec)
     us, vs = pp.sort(S, u, v)
-    del u, v
     AT64, d_in, d_out = pp.filter(S, us, vs, "f64")
     AT32, _, _ = pp.filter(S, us, vs, "f32", degrees=False)
-    A64 = pp.transpose(AT64)
-    say("GPU K3 FP64 and FP32")
-    r64 = pp.init_r(spec.n, seed, "f64")
-    s64 = pp.pagerank(AT64, r64, iters=20, c=C, weights=d_out)
-    r32 = pp.init_r(spec.n, seed, "f32")
-    s32 = pp.pagerank(AT32, r32, iters=20, c=C, weights=d_out)
     torch.cuda.synchronize()
-    g = {"us": us.cpu().numpy(), "vs": vs.cpu().numpy(), "d_in": d_in.cpu().numpy(),
-         "d_out": d_out.cpu().numpy(), "rp": AT64.row_ptr.cpu().numpy(),
-         "col": AT64.col[:AT64.nnz].cpu().numpy(), "val64": AT64.val[:AT64.nnz].cpu().numpy(),
-         "val32": AT32.val[:AT32.nnz].cpu().numpy(), "Arp": A64.row_ptr.cpu().numpy(),
-         "Acol": A64.col[:A64.nnz].cpu().numpy(), "Aval": A64.val[:A64.nnz].cpu().numpy(),
-         "r64": r64.cpu().numpy(), "r32": r32.cpu().numpy().astype(np.float64),
-         "s64": s64.cpu().numpy(), "s32": s32.cpu().numpy()}
-    nnz = AT64.nnz
-    del us, vs, AT64, AT32, A64, r64, r32
+    state = dict(g=g, spec=spec, u=u, v=v, us=us, vs=vs, AT64=AT64, AT32=AT32, d_in=d_in,
+                 d_out=d_out)
+    yield state
+    state.clear()
     torch.cuda.empty_cache()
 
-    say("oracle K0-K2")
-    ou, ov = oracle.generate(oracle.Kron(**spec.as_dict()))
-    ous, ovs = oracle.sort(S, ou, ov)
-    del ou, ov
-    assert np.array_equal(g["us"], ous) and np.array_equal(g["vs"], ovs)
-    f = oracle.filter(S, ous, ovs)
-    del ous, ovs
-    assert nnz == f.nnz
-    assert np.array_equal(g["d_in"], f.d_in) and np.array_equal(g["d_out"], f.d_out)
-    assert np.array_equal(g["rp"], f.AT_rp) and np.array_equal(g["col"], f.AT_col)
-    assert np.array_equal(g["val64"], f.AT_val)
-    assert np.array_equal(g["val32"], f.AT_val.astype(np.float32))
-    assert np.array_equal(g["Arp"], f.A_rp) and np.array_equal(g["Acol"], f.A_col)
-    assert np.array_equal(g["Aval"], f.A_val)
-    say("oracle K3")
-    want, wsums = oracle.pagerank(f.n, f.A_rp, f.A_col, f.A_val, oracle.init_r(f.n, seed), 20, C)
-    e64 = rel_l1(g["r64"], want)
-    e32 = rel_l1(g["r32"], want)
-    gap = rel_l1(g["r32"], g["r64"])
-    say(f"nnz {nnz}: FP64 vs oracle {e64:.3e}, FP32 vs oracle {e32:.3e}, FP32 vs FP64 GPU {gap:.3e}")
-    assert e64 <= 1e-12
-    assert e32 <= 1e-5
-    assert np.abs(g["s64"] / wsums - 1).max() <= 1e-12
-    assert np.abs(g["s32"] / wsums - 1).max() <= 1e-5
+
+@pytest.mark.timeout(600)
+def test_edges_and_sorted_edges(run):
+    d = run["g"]["digest"]
+    assert pg.gpu_digest(run["u"]) == d["u"]
+    assert pg.gpu_digest(run["v"]) == d["v"]
+    assert pg.gpu_digest(run["us"]) == d["u_sorted"]
+    assert pg.gpu_digest(run["vs"]) == d["v_sorted"]
+
+
+@pytest.mark.timeout(600)
+def test_filter_full_arrays(run):
+    g, d = run["g"], run["g"]["digest"]
+    AT64, AT32 = run["AT64"], run["AT32"]
+    assert AT64.nnz == g["nnz"] and AT32.nnz == g["nnz"]
+    assert int(run["d_in"].max()) == g["max_in_degree"]
+    assert pg.gpu_digest(run["d_in"]) == d["d_in"]
+    assert pg.gpu_digest(run["d_out"]) == d["d_out"]
+    assert pg.gpu_digest(AT64.row_ptr) == d["AT_row_ptr"]
+    assert pg.gpu_digest(AT32.row_ptr) == d["AT_row_ptr"]
+    assert pg.gpu_digest(AT64.col, AT64.nnz) == d["AT_col"]
+    assert pg.gpu_digest(AT32.col, AT32.nnz) == d["AT_col"]
+    assert pg.gpu_digest(AT64.val, AT64.nnz) == d["AT_val_f64"]
+    assert pg.gpu_digest(AT32.val, AT32.nnz) == d["AT_val_f32"]
+
+
+@pytest.mark.timeout(600)
+def test_row_form_full_arrays(run):
+    d = run["g"]["digest"]
+    A = pp.transpose(run["AT64"])
+    assert A.nnz == run["g"]["nnz"]
+    assert pg.gpu_digest(A.row_ptr) == d["A_row_ptr"]
+    assert pg.gpu_digest(A.col, A.nnz) == d["A_col"]
+    assert pg.gpu_digest(A.val, A.nnz) == d["A_val_f64"]
+    del A
+    torch.cuda.empty_cache()
+
+
+def test_initial_vectors(run):
+    d, n = run["g"]["digest"], run["spec"].n
+    assert pg.gpu_digest(pp.init_r(n, run["g"]["r0_seed"], "f64")) == d["r0_f64"]
+    assert pg.gpu_digest(pp.init_r(n, run["g"]["r0_seed"], "f32")) == d["r0_f32"]
+
+
+@pytest.fixture(scope="module")
+def oracle_r20(run):
+    # Only a matrix equal to the oracle's (all three digests) may feed the
+    # oracle's K3.
+    d, AT64 = run["g"]["digest"], run["AT64"]
+    assert pg.gpu_digest(AT64.row_ptr) == d["AT_row_ptr"]
+    assert pg.gpu_digest(AT64.col, AT64.nnz) == d["AT_col"]
+    assert pg.gpu_digest(AT64.val, AT64.nnz) == d["AT_val_f64"]
+    r, sums = pg.oracle_k3(AT64, run["g"], TAG)
+    assert f"0x{pg.oracle.digest(r):016x}" == d["r20_f64"]
+    assert [float(x).hex() for x in sums] == run["g"]["sums"]
+    return r, sums
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_pagerank_every_config(run, oracle_r20, dtype):
+    want_r, want_sums = oracle_r20
+    AT = run["AT64"] if dtype == "f64" else run["AT32"]
+    ws = torch.empty(pp.workspace_bytes(pp.K3, AT.n, AT.nnz, dtype), dtype=torch.uint8,
+                     device="cuda")
+    errs = pg.check_k3_configs(AT, dtype, run["d_out"], want_r, want_sums, run["g"], ws, TAG)
+    assert max(errs.values()) <= pg.TOL[dtype]

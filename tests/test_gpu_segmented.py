@@ -30,14 +30,14 @@ def restore_config():
     pp.set_k3_config()
 
 
-def gpu_k3(AT, n, dtype, slab, ipt=8, iters=20, seed=7, weights=None, hot=0):
-    pp.set_k3_config(ipt, 0, slab, hot)
+def gpu_k3(AT, n, dtype, slab, ipt=8, iters=20, seed=7, weights=None):
+    pp.set_k3_config(ipt, 0, slab)
     r = pp.init_r(n, seed, dtype)
     sums = pp.pagerank(AT, r, iters=iters, c=C, weights=weights)
     return host(r), host(sums)
 
 
-def check(n, rp, col, val, dtype, slabs, iters=20, weights=None, ipt=8, hot=0):
+def check(n, rp, col, val, dtype, slabs, iters=20, weights=None, ipt=8):
     """Oracle vs the GPU with each slab width; also the segmented result
     against the one-pass GPU result (same matrix, different sum order)."""
     trp, tcol, tval = oracle.transpose_csr(n, rp, col, val)
@@ -46,7 +46,7 @@ def check(n, rp, col, val, dtype, slabs, iters=20, weights=None, ipt=8, hot=0):
     w = None if weights is None else torch.as_tensor(weights).to(torch.int32).cuda()
     base, _ = gpu_k3(AT, n, dtype, 0, ipt, iters, weights=w)
     for slab in slabs:
-        got, sums = gpu_k3(AT, n, dtype, slab, ipt, iters, weights=w, hot=hot)
+        got, sums = gpu_k3(AT, n, dtype, slab, ipt, iters, weights=w)
         assert rel_l1(got, want) <= TOL[dtype], (slab, rel_l1(got, want))
         assert np.abs(sums / wsums - 1).max() <= TOL[dtype], slab
         assert rel_l1(got, base) <= TOL[dtype], slab
@@ -198,19 +198,17 @@ def test_automatic_slab_width(dtype, scale, same_as):
     assert auto[1].tobytes() == explicit[1].tobytes()
 
 
-# ------------------------------------------------ slab 0 through LDS windows
-# hot_windows = 1 sends slab 0 (slabs wider than one window: 2^14 columns in
-# FP32, 2^13 in FP64) through the window kernel: blocks of whole rows walking
-# windows of r in on-chip memory.  Cases: rows longer than one step of 4096 entries inside a
-# window (carried between steps), many blocks, windows with no entries,
-# slab 0 holding everything or almost nothing.
+# ------------------------------------------------ more structured matrices
+# Narrow slabs over matrices with rows far longer than a SpMV tile (carried
+# between workgroups), ragged sizes, every row in every slab, slab 0 holding
+# almost nothing or everything.
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("case", ["long-rows", "ragged", "dense-ish", "sparse-slab0", "one-slab0"])
-def test_hot_windows_structured(case, dtype):
+def test_segmented_structured_more(case, dtype):
     rng = np.random.default_rng({"long-rows": 21, "ragged": 22, "dense-ish": 23,
                                  "sparse-slab0": 24, "one-slab0": 25}[case])
-    if case == "long-rows":       # rows of ~7000 entries in one window: carries between steps
+    if case == "long-rows":       # rows far longer than one SpMV tile: carries between tiles
         n = 60000
         rp, col, val = random_matrix(n, rng, long_rows=[(5, 50000), (n - 1, 30000), (777, 4097)])
         slabs = [14, 15]
@@ -219,12 +217,12 @@ def test_hot_windows_structured(case, dtype):
         rp, col, val = random_matrix(n, rng, density=12.0,
                                      long_rows=[(0, 9000), (1, 8191), (2, 8193)])
         slabs = [14, 16]
-    elif case == "dense-ish":      # every row in slab 0 hits every window
+    elif case == "dense-ish":      # every row has entries in every slab
         n = 33000
         rp, col, val = random_matrix(n, rng, density=60.0)
         slabs = [15]
-    elif case == "sparse-slab0":   # slab 0 = [0, 65536): sources only in its first and last
-        n = 100000                 # windows (2^14 FP32 / 2^13 FP64 columns), the others empty
+    elif case == "sparse-slab0":   # slab 0 = [0, 65536): sources only at its two ends
+        n = 100000
         rp, col, val = random_matrix(n, rng, density=6.0)
         src = np.repeat(np.arange(n), np.diff(rp))
         keep = (src < 500) | (src >= 49152)
@@ -239,24 +237,4 @@ def test_hot_windows_structured(case, dtype):
         rp = np.concatenate([[0], np.cumsum(np.bincount(src[keep], minlength=n))])
         col, val = col[keep], val[keep]
         slabs = [15]
-    check(n, rp, col, val, dtype, slabs, hot=1)
-
-
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("scale,slab", [(16, 15), (18, 16), (18, 15)])
-def test_hot_windows_kronecker_relabelled(scale, slab, dtype):
-    f = kron_matrix(scale)
-    check(f.n, f.A_rp, f.A_col, f.A_val, dtype, slabs=[slab], weights=f.d_out, hot=1, ipt=16)
-
-
-def test_hot_windows_deterministic_and_auto():
-    s = spec(18)
-    u, v = pp.generate(s)
-    us, vs = pp.sort(18, u, v)
-    AT, _, d_out = pp.filter(18, us, vs, "f32")
-    runs = [gpu_k3(AT, AT.n, "f32", 16, weights=d_out, hot=h) for h in (1, 1, -1, 0)]
-    assert runs[0][0].tobytes() == runs[1][0].tobytes()
-    assert runs[0][1].tobytes() == runs[1][1].tobytes()
-    # relabelled slab 0 is dense here, so the automatic choice takes the windows
-    assert runs[2][0].tobytes() == runs[0][0].tobytes()
-    assert rel_l1(runs[0][0], runs[3][0]) <= 1e-6
+    check(n, rp, col, val, dtype, slabs)
