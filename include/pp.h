@@ -184,8 +184,11 @@ pp_status pp_transpose(const pp_csr *AT, pp_dtype dt, pp_csr *A, void *ws, size_
  *
  * pp_write_text_files: writes text[split[k], split[k+1]) (device) to file
  * "<prefix>.<k>" (k with five digits) for k < nfiles, through pinned host
- * staging buffers (allocated and freed by the call, 128 MiB); with sync
- * the files are flushed to storage (fsync) before the call returns.
+ * staging buffers: up to 8 I/O workers, each with its own stream and two
+ * 16 MiB pinned buffers, made on first use for the current device and kept
+ * for later file calls until the process ends (at most 256 MiB of pinned
+ * host memory); file calls are serialised.  With sync the files are
+ * flushed to storage (fsync) before the call returns.
  * pp_read_text_files: reads files "<prefix>.0" .. ".<nfiles-1>" back to
  * back into text (device, cap bytes); *nbytes (host) = total.  Both return
  * PP_EINVAL with the system's message for a file that cannot be opened,
