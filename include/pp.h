@@ -295,6 +295,28 @@ pp_status pp_pagerank_graphs(int32_t ngraphs, const pp_graph *graphs, pp_dtype d
  * on-chip memory of one workgroup holds two n-vectors). */
 int64_t pp_graphs_max_n(pp_dtype dt);
 
+/* pp_pagerank_graphs for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, checks, kernels and results as a direct
+ * launch (use_graph == 0) of pp_pagerank_graphs, but without a workspace
+ * argument.  The queue counter and the descriptor table live in a static
+ * device array of the library, sized for pp_graphs_noalloc_max() graphs
+ * (65536: 64 B per graph plus 512 B, about 4 MiB), which every GPU the
+ * library runs on holds until the process ends; its address is looked up
+ * once per device on the first call made with that device current.
+ * ngraphs above pp_graphs_noalloc_max() is PP_ERANGE (nothing launched).
+ * The call enqueues a fill kernel that resets the queue counter, the copy of
+ * the [host] descriptor table and the persistent kernel, and allocates
+ * nothing (no hipMalloc, hipFree or allocating library call).  Every call on
+ * one GPU shares that GPU's array, which keeps the last call's contents:
+ * calls that overlap on one GPU (other streams or threads) race on it and
+ * must be serialised by the caller. */
+pp_status pp_pagerank_graphs_noalloc(int32_t ngraphs, const pp_graph *graphs, pp_dtype dt,
+                                     int32_t iters, double c, void *stream);
+
+/* Largest batch pp_pagerank_graphs_noalloc accepts. */
+int32_t pp_graphs_noalloc_max(void);
+
 /* Launch configuration of pp_pagerank (process-wide; the autotuner in the
  * Python package measures the candidates on a given matrix and sets the
  * fastest).  items_per_thread in {4, 8, 16}: merge-path items per thread of

@@ -12,6 +12,7 @@
 // scan over the workgroup.  sum(r) is an FP64 block reduction in a fixed
 // order.  Workgroups never wait on each other: a workgroup exits when the
 // queue is empty.
+#include <mutex>
 #include <vector>
 
 #include "pp_common.hpp"
@@ -283,6 +284,54 @@ int cu_count() {
 constexpr size_t kStaticLds = 24 * 1024;  // reductions, scan tails, s_pre
 
 }  // namespace
+
+// Scratch of the allocation-free entry point: the queue counter and the
+// descriptor table of up to kStaticGraphs graphs, laid out as the workspace
+// of launch_graphs (graphs_ws_bytes).  Every GPU holds its own copy for the
+// life of the process; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr int32_t kStaticGraphs = 1 << 16;
+constexpr size_t kStaticScratch = 512 + size_t(kStaticGraphs) * sizeof(pp_graph);
+static __device__ __align__(256) uint8_t scratch[kStaticScratch];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's scratch, looked up once per device.
+pp_status static_scratch(void **out) {
+  int dev = -1;
+  PP_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PP_EHIP, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return check_hip(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(PP_EHIP, "hipGetSymbolAddress(scratch) returned null");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PP_OK;
+}
+
+}  // namespace
+
+int32_t graphs_static_max() { return kStaticGraphs; }
+
+pp_status launch_graphs_static(int32_t ngraphs, const pp_graph *graphs, int64_t max_n,
+                               pp_dtype dt, int32_t iters, double c, hipStream_t s) {
+  if (ngraphs < 1 || ngraphs > kStaticGraphs)
+    return fail(PP_ERANGE, "pp_pagerank_graphs_noalloc: %d graphs, at most %d", ngraphs,
+                kStaticGraphs);
+  void *ws = nullptr;
+  const pp_status st = static_scratch(&ws);
+  if (st != PP_OK) return st;
+  // Direct launches only: the kernels take the scratch as their workspace.
+  return launch_graphs(ngraphs, graphs, max_n, dt, iters, c, 0, ws, kStaticScratch, s);
+}
 
 size_t graphs_ws_bytes(int32_t ngraphs) {
   Carve c(nullptr);

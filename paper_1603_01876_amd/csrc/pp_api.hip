@@ -40,6 +40,35 @@ bool kron_ok(const pp_kron_params *p) {
 
 hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
 
+// Host checks shared by both batch entry points: every descriptor, so the
+// kernel takes each graph as it is.  Sets the largest n of the batch.
+pp_status check_graphs(const char *who, int32_t ngraphs, const pp_graph *graphs, pp_dtype dt,
+                       int32_t iters, double c, int64_t *max_n_out) {
+  if (ngraphs < 1 || ngraphs > (1 << 24)) return fail(PP_EINVAL, "%s: ngraphs %d", who, ngraphs);
+  if (!graphs) return fail(PP_EINVAL, "%s: null graphs", who);
+  if (dt != PP_F64 && dt != PP_F32) return fail(PP_EINVAL, "%s: dtype %d", who, int(dt));
+  if (iters < 0) return fail(PP_EINVAL, "%s: iters %d", who, iters);
+  if (!(c >= 0.0 && c <= 1.0)) return fail(PP_EINVAL, "%s: c = %g", who, c);
+  const int64_t limit = graphs_max_n(dt);
+  int64_t max_n = 0;
+  for (int32_t g = 0; g < ngraphs; ++g) {
+    const pp_graph &G = graphs[g];
+    if (G.n < 1 || G.nnz < 0)
+      return fail(PP_EINVAL, "%s: graph %d has n %lld, nnz %lld", who, g, (long long)G.n,
+                  (long long)G.nnz);
+    if (G.n > limit)
+      return fail(PP_ERANGE, "%s: graph %d has n %lld > %lld", who, g, (long long)G.n,
+                  (long long)limit);
+    if (G.n + G.nnz > INT32_MAX)
+      return fail(PP_ERANGE, "%s: graph %d: n + nnz beyond int32", who, g);
+    if (!G.row_ptr || !G.r || (G.nnz > 0 && (!G.col || !G.val)))
+      return fail(PP_EINVAL, "%s: graph %d lacks an array", who, g);
+    if (G.n > max_n) max_n = G.n;
+  }
+  *max_n_out = max_n;
+  return PP_OK;
+}
+
 }  // namespace
 }  // namespace pp
 
@@ -285,35 +314,29 @@ int64_t pp_graphs_max_n(pp_dtype dt) {
 pp_status pp_pagerank_graphs(int32_t ngraphs, const pp_graph *graphs, pp_dtype dt, int32_t iters,
                              double c, int32_t use_graph, void *ws, size_t ws_bytes,
                              void *stream) {
-  if (ngraphs < 1 || ngraphs > (1 << 24)) return fail(PP_EINVAL, "pp_pagerank_graphs: ngraphs %d", ngraphs);
-  if (!graphs) return fail(PP_EINVAL, "pp_pagerank_graphs: null graphs");
-  if (dt != PP_F64 && dt != PP_F32) return fail(PP_EINVAL, "pp_pagerank_graphs: dtype %d", int(dt));
-  if (iters < 0) return fail(PP_EINVAL, "pp_pagerank_graphs: iters %d", iters);
-  if (!(c >= 0.0 && c <= 1.0)) return fail(PP_EINVAL, "pp_pagerank_graphs: c = %g", c);
-  if (use_graph && !stream) return fail(PP_EINVAL, "pp_pagerank_graphs: graph capture needs a stream");
-  // Every descriptor is checked here, on the host: the kernel takes each
-  // graph as it is.
-  const int64_t limit = graphs_max_n(dt);
   int64_t max_n = 0;
-  for (int32_t g = 0; g < ngraphs; ++g) {
-    const pp_graph &G = graphs[g];
-    if (G.n < 1 || G.nnz < 0)
-      return fail(PP_EINVAL, "pp_pagerank_graphs: graph %d has n %lld, nnz %lld", g,
-                  (long long)G.n, (long long)G.nnz);
-    if (G.n > limit)
-      return fail(PP_ERANGE, "pp_pagerank_graphs: graph %d has n %lld > %lld", g,
-                  (long long)G.n, (long long)limit);
-    if (G.n + G.nnz > INT32_MAX)
-      return fail(PP_ERANGE, "pp_pagerank_graphs: graph %d: n + nnz beyond int32", g);
-    if (!G.row_ptr || !G.r || (G.nnz > 0 && (!G.col || !G.val)))
-      return fail(PP_EINVAL, "pp_pagerank_graphs: graph %d lacks an array", g);
-    if (G.n > max_n) max_n = G.n;
-  }
+  const pp_status st = check_graphs("pp_pagerank_graphs", ngraphs, graphs, dt, iters, c, &max_n);
+  if (st != PP_OK) return st;
+  if (use_graph && !stream) return fail(PP_EINVAL, "pp_pagerank_graphs: graph capture needs a stream");
   const size_t need = graphs_ws_bytes(ngraphs);
   if (!ws || ws_bytes < need) return fail(PP_EWORKSPACE, "pp_pagerank_graphs: workspace needs %zu bytes", need);
   return launch_graphs(ngraphs, graphs, max_n, dt, iters, c, use_graph, ws, ws_bytes,
                        as_stream(stream));
 }
+
+pp_status pp_pagerank_graphs_noalloc(int32_t ngraphs, const pp_graph *graphs, pp_dtype dt,
+                                     int32_t iters, double c, void *stream) {
+  if (ngraphs > graphs_static_max())
+    return fail(PP_ERANGE, "pp_pagerank_graphs_noalloc: %d graphs, at most %d", ngraphs,
+                graphs_static_max());
+  int64_t max_n = 0;
+  const pp_status st =
+      check_graphs("pp_pagerank_graphs_noalloc", ngraphs, graphs, dt, iters, c, &max_n);
+  if (st != PP_OK) return st;
+  return launch_graphs_static(ngraphs, graphs, max_n, dt, iters, c, as_stream(stream));
+}
+
+int32_t pp_graphs_noalloc_max(void) { return graphs_static_max(); }
 
 pp_status pp_set_k3_config(const pp_k3_config *cfg) {
   if (!cfg) return set_k3_config(8, 0, -1);

@@ -291,6 +291,9 @@ int64_t graphs_max_n(pp_dtype dt);
 pp_status launch_graphs(int32_t ngraphs, const pp_graph *graphs, int64_t max_n, pp_dtype dt,
                         int32_t iters, double c, int32_t use_graph, void *ws, size_t ws_bytes,
                         hipStream_t s);
+int32_t graphs_static_max();
+pp_status launch_graphs_static(int32_t ngraphs, const pp_graph *graphs, int64_t max_n,
+                               pp_dtype dt, int32_t iters, double c, hipStream_t s);
 
 pp_status set_k3_config(int32_t ipt, int32_t rhs_lanes, int32_t slab_log2);
 void get_k3_config(int32_t *ipt, int32_t *rhs_lanes, int32_t *slab_log2);

@@ -88,6 +88,8 @@ SIGNATURES = {
                                             ctypes.c_int, _VP, _VP, _VP, _VP, _VP,
                                             ctypes.POINTER(_I32), _VP, _SZ, _VP]),
     "pp_graphs_max_n": (_I64, [ctypes.c_int]),
+    "pp_pagerank_graphs_noalloc": (ctypes.c_int, [_I32, _VP, ctypes.c_int, _I32, _D, _VP]),
+    "pp_graphs_noalloc_max": (_I32, []),
     "pp_set_k3_config": (ctypes.c_int, [ctypes.c_void_p]),
     "pp_get_k3_config": (ctypes.c_int, [ctypes.c_void_p]),
     "pp_set_kernel_timing": (ctypes.c_int, [ctypes.c_int]),
@@ -408,6 +410,20 @@ def pagerank_graphs(batch: GraphBatch, iters: int = 20, c: float = 0.85, use_gra
     _check(lib().pp_pagerank_graphs(len(batch), ctypes.addressof(batch.table), batch.dtype,
                                     iters, c, int(bool(use_graph)), batch.ws.data_ptr(),
                                     batch.ws.numel(), _stream()), "pp_pagerank_graphs")
+
+
+def pagerank_graphs_noalloc(batch: GraphBatch, iters: int = 20, c: float = 0.85):
+    """pagerank_graphs() through pp_pagerank_graphs_noalloc: a direct launch
+    whose queue and descriptor table live in the library's static device
+    array, so the call allocates nothing (batch.ws is not used)."""
+    _check(lib().pp_pagerank_graphs_noalloc(len(batch), ctypes.addressof(batch.table),
+                                            batch.dtype, iters, c, _stream()),
+           "pp_pagerank_graphs_noalloc")
+
+
+def graphs_noalloc_max() -> int:
+    """Largest batch pagerank_graphs_noalloc() accepts."""
+    return int(lib().pp_graphs_noalloc_max())
 
 
 def set_k3_config(items_per_thread: int = 8, rhs_lanes: int = 0, slab_log2: int = -1) -> None:

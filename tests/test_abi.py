@@ -207,6 +207,40 @@ def test_pagerank_graphs_rejects_bad_args():
     assert call(g=table((mx,) + good[1:], good), wsb=1) == native.PP_EWORKSPACE
 
 
+def test_pagerank_graphs_noalloc_rejects_bad_args():
+    # The allocation-free batch call applies the same host checks (nothing is
+    # enqueued, no device address is touched) and bounds the batch by its
+    # static scratch.
+    L = native.lib()
+    cap = native.graphs_noalloc_max()
+    assert cap == 1 << 16
+    mx = native.graphs_max_n("f32")
+    good = (100, 50, 8, 16, 24, 32, 0, 1)
+
+    def table(*graphs):
+        t = (native._Graph * len(graphs))()
+        for i, g in enumerate(graphs):
+            t[i] = native._Graph(*g)
+        return t
+
+    ok = table(good, good)
+
+    def call(ng=2, g=ok, dt=1, iters=20, damp=0.85):
+        gp = None if g is None else ctypes.addressof(g)
+        return L.pp_pagerank_graphs_noalloc(ng, gp, dt, iters, damp, None)
+
+    assert call(ng=cap + 1) == native.PP_ERANGE
+    assert call(ng=1 << 25) == native.PP_ERANGE
+    assert call(ng=0) == native.PP_EINVAL
+    assert call(g=None) == native.PP_EINVAL
+    assert call(dt=5) == native.PP_EINVAL
+    assert call(iters=-1) == native.PP_EINVAL
+    assert call(damp=-0.1) == native.PP_EINVAL
+    assert call(g=table(good, (mx + 1,) + good[1:])) == native.PP_ERANGE
+    assert call(g=table(good, (100, 50, 8, 16, 24, 0) + good[6:])) == native.PP_EINVAL
+    assert b"noalloc" in L.pp_last_error()
+
+
 def test_edge_file_calls_reject_bad_args(tmp_path):
     L = native.lib()
     assert native.workspace_bytes(native.TSV_FORMAT, 0, 32, "f64", 3) > 0
