@@ -160,12 +160,26 @@ def copy_ceiling(torch, nbytes=1 << 31, reps=5):
     return 2 * nbytes / t / 1e9
 
 
-def spmv_label(cfg, dt):
+def spmv_label(cfg, dt, layout=None):
     v = "float" if dt == "f32" else "double"
     if cfg[2] > 0:
-        return (f"segmented SpMV iteration, slabs of 2^{cfg[2]} columns: "
-                f"k_spmv<{v},{cfg[0]},raw> + k_fix_raw<{v}> + k_seg_combine<{v}> + k_sum_blocks")
+        ent = ",uint8" if layout and layout.get("scaled") else ""
+        form = " (degree-scaled form: entries stored as counts)" if ent else ""
+        return (f"segmented SpMV iteration, slabs of 2^{cfg[2]} columns{form}: "
+                f"k_spmv<{v},{cfg[0]},raw{ent}> + k_fix_raw<{v}> + k_seg_combine<{v}> + "
+                f"k_sum_blocks")
     return f"k_spmv<{v},{cfg[0]}> + k_finish<{v}>"
+
+
+def form_bytes(n: int, nnz: int, dtype: str, layout) -> int | None:
+    """Bytes one iteration of the degree-scaled form must move at the
+    least: row pointers 4(N+1), columns 4Z, one count byte per entry, the
+    gathered vector once and the next one written, and the out-degrees the
+    combine divides by (4N).  None for the value form (spmv_bytes)."""
+    if not layout or not layout.get("scaled"):
+        return None
+    w = 8 if dtype == "f64" else 4
+    return 4 * (n + 1) + 5 * nnz + 2 * w * n + 4 * n
 
 
 def batched_form(args, pp, workloads, torch):
@@ -644,7 +658,8 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     pp.set_kernel_timing(False)
-    log(f"timed {args.steps} steps in {t1 - t0:.3f} s")
+    layout = pp.k3_last_layout()
+    log(f"timed {args.steps} steps in {t1 - t0:.3f} s (K3 layout {layout})")
 
     k = {name: [] for name in ("k0", "k1", "k2", "k3")}
     for ev in evs:
@@ -685,9 +700,10 @@ def main():
             "k3_edges_per_s": value,
             "spmv_avg_ms": spmv_avg_s * 1e3, "spmv_launches": len(spmv_ms),
         },
-        "roofline": {"bound": "hbm", "kernel": spmv_label(pp.get_k3_config(), dt),
+        "roofline": {"bound": "hbm", "kernel": spmv_label(pp.get_k3_config(), dt, layout),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
+                     "form_bytes_per_launch": form_bytes(n, z, dt, layout),
                      "traffic": (mt or {}).get("traffic"),
                      "traffic_unit": "GB per iteration (rocprofv3 FETCH_SIZE + WRITE_SIZE over the iteration's launches, copy-calibrated)",
                      "algorithmic_bytes_per_launch": nbytes,
@@ -697,7 +713,8 @@ def main():
         "sum_r": {"first": float(sums_h[0]), "last": float(sums_h[-1])},
         "k3_config": {"items_per_thread": pp.get_k3_config()[0],
                       "slab_log2": pp.get_k3_config()[2],
-                      "relabel": state["relabel"],
+                      "scaled_form": pp.get_k3_config()[3],
+                      "relabel": state["relabel"], "layout": layout,
                       "tuned": None if args.no_tune or args.warmup < 1 else tuned["ms"]},
     }
 
@@ -754,6 +771,7 @@ def main():
             torch.cuda.synchronize()
             times.append(e0.elapsed_time(e1) / 1e3)
         pp.set_kernel_timing(False)
+        layout_o = pp.k3_last_layout()
         pp.set_k3_config(*saved)
         t_o = sum(times) / len(times)
         s_o = sum(spmv_o) / len(spmv_o) / 1e3
@@ -762,8 +780,9 @@ def main():
             "workload": f"kron-s{S}-{other}", "k3_edges_per_s": args.iters * m / t_o,
             "k3_ms": t_o * 1e3, "spmv_avg_ms": s_o * 1e3, "spmv_GBps": b_o / s_o / 1e9,
             "spmv_frac_of_peak": b_o / s_o / 1e9 / HBM_PEAK_GBS,
-            "kernel": spmv_label(cfg_o, other), "relabel": wo is not None,
-            "k3_config": list(cfg_o),
+            "kernel": spmv_label(cfg_o, other, layout_o), "relabel": wo is not None,
+            "k3_config": list(cfg_o), "layout": layout_o,
+            "form_bytes_per_launch": form_bytes(n, ATo.nnz, other, layout_o),
             "tuned": None if tuned_o is None else tuned_o["ms"]}
         t32, t64 = (mean["k3"], t_o) if dt == "f32" else (t_o, mean["k3"])
         r32, r64 = (r_main, ro.double()) if dt == "f32" else (ro.double(), r_main)

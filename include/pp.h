@@ -227,8 +227,12 @@ pp_status pp_init_r(int64_t n, int32_t nrhs, uint64_t seed, pp_dtype dt, void *r
  * matrix (in the workspace) whose vertices are relabelled by decreasing
  * floor(log2(weight + 1)), ties in label order, so that frequently gathered
  * ranks share cache lines; r is permuted in and out, so inputs and outputs
- * keep the original labels.  The weights only affect speed and the order
- * of floating-point sums.  The caller must supply a valid CSR (row_ptr
+ * keep the original labels.  When the weights are pp_filter's d_out for
+ * this matrix, a segmented run also stores the entries as integer counts
+ * and gathers r_i / d_out[i] (the degree-scaled form; see scaled_form in
+ * pp_k3_config): A = D^-1 C with C the count matrix of Sec. IV.C, verified
+ * entry by entry.  The weights only affect speed and the rounding and order
+ * of floating-point operations.  The caller must supply a valid CSR (row_ptr
  * non-decreasing from 0 to nnz, columns in [0, n)); pp_filter's output
  * always is. */
 pp_status pp_pagerank(const pp_csr *AT, pp_dtype dt, int32_t nrhs, int32_t iters, double c,
@@ -331,16 +335,36 @@ int32_t pp_graphs_noalloc_max(void);
  * of 2 MiB of r (2^19 FP32 or 2^18 FP64 vertices) once r exceeds 4 MiB,
  * else one pass.  The segmented layout is built inside each pp_pagerank
  * call, which then synchronizes its stream once to read the number of
- * (slab, row) pairs.  Results do not depend on the configuration beyond
- * the order of floating-point sums.  pp_set_k3_config(NULL) restores the
- * defaults (8, 0, -1). */
+ * (slab, row) pairs.  scaled_form in {0, 1}: with 1, a pp_pagerank call
+ * that relabels (order_weights given) and segments stores each entry as
+ * its integer count k = A(i,j) * w[i] instead of its value whenever every
+ * entry verifies as A(i,j) == V(k / w[i]) with k in [1, 255] (as for
+ * pp_filter's output with its d_out as the weights: Sec. IV.C's counts
+ * divided by out-degrees), and the iterations gather r_i / w[i]; any entry
+ * that does not verify keeps the values (one more stream synchronisation
+ * reads the verdict).  rhs_tile in {0, 2, 4, 8, 16, 32}: with nrhs above
+ * it, the sparse matrix-dense matrix form runs the right-hand sides rhs_tile
+ * columns at a time, each tile held as an n x rhs_tile block of its own in
+ * the workspace (a tile's rows are gathered from a block small enough to
+ * stay in the 256 MB Infinity Cache); 0 runs all columns in one pass.
+ * Results do not depend on the configuration beyond the rounding of
+ * floating-point products and the order of sums.  pp_set_k3_config(NULL)
+ * restores the defaults (8, 0, -1, 1, 0). */
 typedef struct {
   int32_t items_per_thread;
   int32_t rhs_lanes;
   int32_t slab_log2;
+  int32_t scaled_form;
+  int32_t rhs_tile;
 } pp_k3_config;
 pp_status pp_set_k3_config(const pp_k3_config *cfg);
 pp_status pp_get_k3_config(pp_k3_config *cfg);
+
+/* Layout the most recent pp_pagerank / pp_pagerank_converge call (in this
+ * process) iterated on: bit 0 vertices relabelled, bit 1 columns
+ * segmented, bit 2 entries stored as counts (degree-scaled form).  0 before
+ * any call.  Instrumentation for tests and benchmarks. */
+int32_t pp_k3_last_layout(void);
 
 /* Benchmark instrumentation.  While enabled (enable != 0), each
  * pp_pagerank call records a pair of HIP events on its stream around every

@@ -10,7 +10,10 @@ with the iterations it serves.  Candidates are
   tile is 256 times that), or column slabs of 2^18, 2^19, 2^20 vertices with
   16 items per thread; each with vertex relabelling on or off when the
   caller passes weights;
-* nrhs > 1: SpMM lane-group width (the next power of two >= nrhs, or 64).
+* nrhs > 1: SpMM lane-group width (the next power of two >= nrhs, or 64)
+  with all right-hand sides in one pass, or column tiles of 16 or 8
+  right-hand sides (each tile its own n x T block; lanes = T), each with
+  relabelling on or off when the caller passes weights.
 
 The choice is applied with set_k3_config() and cached in a JSON file keyed
 by device architecture, size bucket, dtype, nrhs, iteration count and
@@ -31,8 +34,13 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pp_mi355x", "k3
 SLABS = (0, 18, 19, 20)
 
 
-def candidates(nrhs: int, relabel_options=(False,)) -> list[tuple[int, int, int, bool]]:
-    """(items_per_thread, rhs_lanes, slab_log2, relabel) tuples."""
+RHS_TILES = (16, 8)
+
+
+def candidates(nrhs: int, relabel_options=(False,)) -> list[tuple]:
+    """(items_per_thread, rhs_lanes, slab_log2, relabel) tuples for one
+    right-hand side; (items_per_thread, rhs_lanes, slab_log2, relabel,
+    rhs_tile) for several (rhs_tile 0: all columns in one pass)."""
     if nrhs == 1:
         out = []
         for rl in relabel_options:
@@ -42,8 +50,20 @@ def candidates(nrhs: int, relabel_options=(False,)) -> list[tuple[int, int, int,
     lanes = 2
     while lanes < nrhs:
         lanes *= 2
-    return [(8, lanes, 0, rl) for rl in relabel_options] + \
-        ([(8, 64, 0, rl) for rl in relabel_options] if lanes < 64 else [])
+    out = [(8, lanes, 0, rl, 0) for rl in relabel_options]
+    if lanes < 64:
+        out += [(8, 64, 0, rl, 0) for rl in relabel_options]
+    for t in RHS_TILES:
+        if t < nrhs:
+            out += [(8, 0, 0, rl, t) for rl in relabel_options]
+    return out
+
+
+def config_of(cand) -> list[int]:
+    """set_k3_config() arguments of a candidate (degree-scaled form on)."""
+    ipt, lanes, slab = (int(x) for x in cand[:3])
+    tile = int(cand[4]) if len(cand) > 4 else 0
+    return [ipt, lanes, slab, 1, tile]
 
 
 def name(cand) -> str:
@@ -69,9 +89,9 @@ def _load(path):
 def tune(AT, dtype="f32", nrhs: int = 1, weights=None, iters: int = 20, cache: str | None = None,
          force: bool = False, ws=None, repeats: int = 2) -> dict:
     """Measures the candidates on this matrix, applies the fastest with
-    set_k3_config() and returns {"config": [ipt, lanes, slab_log2],
-    "relabel": bool, "ms": {candidate: ms per call}}.  The
-    caller passes `weights` to pagerank() only when "relabel" is true."""
+    set_k3_config() and returns {"config": set_k3_config() arguments,
+    "relabel": bool, "candidate": its name, "ms": {candidate: ms per call}}.
+    The caller passes `weights` to pagerank() only when "relabel" is true."""
     cache = cache or DEFAULT_CACHE
     k = key(AT, dtype, nrhs, weights is not None, iters)
     table = _load(cache)
@@ -88,8 +108,8 @@ def tune(AT, dtype="f32", nrhs: int = 1, weights=None, iters: int = 20, cache: s
     opts = (False, True) if weights is not None else (False,)
     times = {}
     for cand in candidates(nrhs, opts):
-        ipt, lanes, slab, rl = cand
-        pp.set_k3_config(ipt, lanes, slab)
+        rl = bool(cand[3])
+        pp.set_k3_config(*config_of(cand))
         w = weights if rl else None
         best = float("inf")
         for rep in range(repeats + 1):
@@ -105,9 +125,9 @@ def tune(AT, dtype="f32", nrhs: int = 1, weights=None, iters: int = 20, cache: s
         times[name(cand)] = best
     win = min(times, key=times.get)
     cand = [int(x) for x in win.split(",")]
-    cfg, relabel = cand[:3], bool(cand[3])
+    cfg, relabel = config_of(cand), bool(cand[3])
     pp.set_k3_config(*cfg)
-    entry = {"config": cfg, "relabel": relabel, "ms": times}
+    entry = {"config": cfg, "relabel": relabel, "candidate": win, "ms": times}
     table[k] = entry
     try:
         os.makedirs(os.path.dirname(cache), exist_ok=True)

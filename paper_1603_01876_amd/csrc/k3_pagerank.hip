@@ -20,6 +20,7 @@
 // reduced in FP64 in a fixed order and the teleport scalar (1-c)/N * sum(r)
 // is FP64.  The partition, the carries' row ids and the fix-up flags depend
 // only on the matrix, so they are computed once per call.
+#include <type_traits>
 #include <vector>
 
 #include "pp_common.hpp"
@@ -42,8 +43,13 @@ struct K3Config {
   int ipt = 8;
   int rhs_lanes = 0;  // 0: next power of two >= nrhs
   int slab_log2 = -1; // 0: one pass over all columns; > 0: slab width 2^slab_log2; -1: auto
+  int scaled = 1;     // degree-scaled form of a relabelled, segmented matrix when it verifies
+  int rhs_tile = 0;   // SpMM: 0 all right-hand sides per pass; else tiles of this many columns
 };
 K3Config g_cfg;
+// What the most recent pagerank call ran: bit 0 relabelled, bit 1 column
+// segmented, bit 2 degree-scaled form (instrumentation).
+int32_t g_last_layout = 0;
 constexpr int kFinishPer = kThreads;         // spmv workgroups per finish workgroup
 constexpr int64_t kSumChunk = kThreads * 64; // entries of r per workgroup of sum(r_0)
 
@@ -142,10 +148,12 @@ __device__ __forceinline__ AccF shfl_up_acc(AccF a, int o) {
 
 // With kRaw the rows are (slab, row) pairs of the column-segmented layout
 // below: each completed row stores its raw accumulator into part[] instead
-// of c * sum + t into y, and no sum(y) is formed.
-template <typename V, int IPT, bool kRaw>
+// of c * sum + t into y, and no sum(y) is formed.  E is the stored entry
+// type: the values (V), or the integer counts (uint8_t) of the
+// degree-scaled form, whose x holds r_u / w[u].
+template <typename V, int IPT, bool kRaw, typename E = V>
 __global__ __launch_bounds__(kThreads) void k_spmv(
-    const int32_t *__restrict__ rp, const int32_t *__restrict__ col, const V *__restrict__ val,
+    const int32_t *__restrict__ rp, const int32_t *__restrict__ col, const E *__restrict__ val,
     const V *__restrict__ x, V *__restrict__ y, int32_t n, const int2 *__restrict__ coord,
     double c, const double *__restrict__ tele, double *__restrict__ blk_ysum,
     typename Form<V>::Acc *__restrict__ blk_carry, typename Form<V>::Acc *__restrict__ blk_head,
@@ -171,7 +179,8 @@ __global__ __launch_bounds__(kThreads) void k_spmv(
   // all IPT gathers, before it waits on any of them.
   {
     int32_t cc[IPT], ee[IPT];
-    V vv[IPT], xv[IPT];
+    E vv[IPT];
+    V xv[IPT];
     if (nz > 0) {
 #pragma unroll
       for (int r = 0; r < IPT; ++r) {
@@ -194,7 +203,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv(
 #pragma unroll
       for (int r = 0; r < IPT; ++r) {
         const int k = r * kThreads + tid;
-        if (k < nz) s_prod[k] = xv[r] * vv[r];
+        if (k < nz) s_prod[k] = xv[r] * V(vv[r]);
       }
     }
     if (na > 0) {
@@ -661,18 +670,55 @@ __global__ __launch_bounds__(256) void k_order_keys(const int32_t *__restrict__ 
   }
 }
 
-// order[p] = old label at new position p; newlabel[old] = p; row lengths in
-// the new order (into rp2, scanned afterwards).
+// order[p] = old label at new position p; lab[old] = (p, weight of old);
+// wnew[p] = weight of the vertex at p; row lengths in the new order (into
+// rp2, scanned afterwards).  Inside a bucket p and old ascend together, so
+// the weight reads and lab writes walk memory in order.
 __global__ __launch_bounds__(256) void k_relabel_maps(const uint64_t *__restrict__ keys,
-                                                      const int32_t *__restrict__ rp, int32_t n,
+                                                      const int32_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ w, int32_t n,
                                                       int32_t *__restrict__ order,
-                                                      int32_t *__restrict__ newlabel,
+                                                      int2 *__restrict__ lab,
+                                                      int32_t *__restrict__ wnew,
                                                       uint32_t *__restrict__ len2) {
   for (int32_t p = blockIdx.x * 256 + threadIdx.x; p < n; p += gridDim.x * 256) {
     const int32_t o = int32_t(keys[p] & 0xFFFFFFFFull);
+    const int32_t wo = w[o];
     order[p] = o;
-    newlabel[o] = p;
+    lab[o] = make_int2(p, wo);
+    wnew[p] = wo;
     len2[p] = uint32_t(rp[o + 1] - rp[o]);
+  }
+}
+
+// Cache in front of lab[] for the heaviest vertices: one 16-byte slot per
+// hash bucket holding (vertex, new label, weight) of the heaviest vertex
+// hashed there (vertex -1 when empty).  A lookup reads the slot and falls
+// back to lab[u] when the slot holds another vertex; results never depend
+// on what the cache holds.
+struct Hot2 {
+  const int4 *tab;
+  uint32_t mask;
+};
+
+__device__ __forceinline__ int2 hot2_get(Hot2 h, const int2 *__restrict__ lab, int32_t u) {
+  const int4 e = h.tab[hot_mix(uint32_t(u)) & h.mask];
+  return e.x == u ? make_int2(e.y, e.z) : lab[u];
+}
+
+// Winners (weight << 32 | u, 0 = empty) -> slots.
+__global__ __launch_bounds__(256) void k_hot2_fill(const uint64_t *__restrict__ win,
+                                                   const int2 *__restrict__ lab,
+                                                   int4 *__restrict__ tab, uint32_t slots) {
+  for (uint32_t k = blockIdx.x * 256 + threadIdx.x; k < slots; k += gridDim.x * 256) {
+    const uint64_t e = win[k];
+    const int32_t u = int32_t(uint32_t(e));
+    if (e) {
+      const int2 l = lab[u];
+      tab[k] = make_int4(u, l.x, l.y, 0);
+    } else {
+      tab[k] = make_int4(-1, 0, 0, 0);
+    }
   }
 }
 
@@ -687,7 +733,7 @@ __global__ void k_set_total(int32_t *rp2, int32_t n, const int64_t *total) {
 template <typename V>
 __global__ __launch_bounds__(kThreads) void k_relabel_copy(
     const int32_t *__restrict__ rp, const int32_t *__restrict__ col, const V *__restrict__ val,
-    const int32_t *__restrict__ order, const int32_t *__restrict__ newlabel, HotTab hot,
+    const int32_t *__restrict__ order, const int2 *__restrict__ lab, Hot2 hot,
     const int32_t *__restrict__ rp2, int32_t n, const int2 *__restrict__ coord,
     int32_t *__restrict__ col2, V *__restrict__ val2) {
   __shared__ int32_t s_end[kItemsMax];
@@ -715,32 +761,57 @@ __global__ __launch_bounds__(kThreads) void k_relabel_copy(
         hi = m;
     }
     const int32_t src = s_old[lo] + (q - s_new[lo]);
-    col2[q] = hot_get(hot, newlabel, col[src]);
+    col2[q] = hot2_get(hot, lab, col[src]).x;
     val2[q] = val[src];
   }
 }
 
 // Rows of width k: dst row p <- src row order[p] (in), dst row order[p] <-
-// src row p (out).
+// src row p (out); order null keeps the labels.  The iterations' side of
+// the copy is stored in column tiles of T right-hand sides (T >= k: plain
+// row-major): tile t holds columns [tT, tT + Tt), Tt = min(T, k - tT), as an
+// n x Tt row-major block starting at element n * tT.
+__device__ __forceinline__ int64_t tiled_index(int64_t p, int32_t j, int64_t n, int32_t k,
+                                               int32_t T) {
+  const int32_t t = j / T, jj = j - t * T;
+  const int32_t Tt = k - t * T < T ? k - t * T : T;
+  return n * t * T + p * Tt + jj;
+}
+
 template <typename V>
 __global__ __launch_bounds__(256) void k_permute_in(const V *__restrict__ src,
                                                     const int32_t *__restrict__ order, int32_t n,
-                                                    int32_t k, V *__restrict__ dst) {
+                                                    int32_t k, int32_t T, V *__restrict__ dst) {
   const int64_t total = int64_t(n) * k;
   for (int64_t e = blockIdx.x * int64_t(256) + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
-    const int64_t p = e / k, j = e - p * k;
-    dst[e] = src[int64_t(order[p]) * k + j];
+    const int64_t p = e / k;
+    const int32_t j = int32_t(e - p * k);
+    dst[tiled_index(p, j, n, k, T)] = src[int64_t(order ? order[p] : int32_t(p)) * k + j];
+  }
+}
+
+// Degree-scaled form, one right-hand side: dst[p] = src[order[p]] / d[p]
+// (0 where d[p] <= 0: such a vertex has no entries in its column).
+template <typename V>
+__global__ __launch_bounds__(256) void k_permute_in_scaled(const V *__restrict__ src,
+                                                           const int32_t *__restrict__ order,
+                                                           const int32_t *__restrict__ d,
+                                                           int32_t n, V *__restrict__ dst) {
+  for (int32_t p = blockIdx.x * 256 + threadIdx.x; p < n; p += gridDim.x * 256) {
+    const int32_t dp = d[p];
+    dst[p] = dp > 0 ? V(double(src[order[p]]) / double(dp)) : V(0);
   }
 }
 
 template <typename V>
 __global__ __launch_bounds__(256) void k_permute_out(const V *__restrict__ src,
                                                      const int32_t *__restrict__ order, int32_t n,
-                                                     int32_t k, V *__restrict__ dst) {
+                                                     int32_t k, int32_t T, V *__restrict__ dst) {
   const int64_t total = int64_t(n) * k;
   for (int64_t e = blockIdx.x * int64_t(256) + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
-    const int64_t p = e / k, j = e - p * k;
-    dst[int64_t(order[p]) * k + j] = src[e];
+    const int64_t p = e / k;
+    const int32_t j = int32_t(e - p * k);
+    dst[int64_t(order ? order[p] : int32_t(p)) * k + j] = src[tiled_index(p, j, n, k, T)];
   }
 }
 
@@ -790,19 +861,31 @@ constexpr int kMaskWords = kMaxSlabs / 32;
 // order (still stored tile by tile) and fmask the cont masks.  The tile is staged in LDS in slab order
 // so that one slab's run is stored contiguously; a pair start also stores
 // its entry position and row (prp, pair_row).
+//
+// E is the stored entry type: V (the matrix values) or, in the degree-scaled
+// form, uint8_t: the integer count k of the entry, with the entry's value
+// k / w[u] carried by the ranks (the iterations gather r_u / w[u]).  The
+// relabelling count pass derives k from the value and the weight of its
+// column, k = rint(val * w), and accepts the entry only if k is in [1, 255]
+// and V(k / w) reproduces the value bit for bit (the IEEE FP64 quotient,
+// rounded to FP32 in the FP32 form); any other entry sets *bad, and the
+// caller falls back to storing values.
 struct RelabelSrc {
-  const int32_t *rp0, *col0, *order, *newlabel;
+  const int32_t *rp0, *col0, *order;
+  const int2 *lab;   // (new label, weight) of every old label
   const void *val0;
-  HotTab hot;   // cache of newlabel for the heaviest vertices
+  Hot2 hot;          // cache of lab for the heaviest vertices
+  uint32_t *bad;     // set when an entry is not count / weight (scaled form)
 };
 
-template <typename V, bool kScatter, bool kRelabel>
+template <typename V, typename E, bool kScatter, bool kRelabel>
 __global__ __launch_bounds__(kThreads) void k_seg_tile(
-    const int32_t *__restrict__ rp, int32_t *__restrict__ col, V *__restrict__ val, int32_t n,
+    const int32_t *__restrict__ rp, int32_t *__restrict__ col, E *__restrict__ val, int32_t n,
     RelabelSrc rs, const int2 *__restrict__ coord, int32_t sbits, int32_t ns, int32_t dbits,
     int32_t ntiles, uint32_t *__restrict__ ecnt, uint32_t *__restrict__ pcnt,
     uint32_t *__restrict__ fmask, uint32_t *__restrict__ lmask, int32_t *__restrict__ seg_col,
-    V *__restrict__ seg_val, int32_t *__restrict__ prp, int32_t *__restrict__ pair_row) {
+    E *__restrict__ seg_val, int32_t *__restrict__ prp, int32_t *__restrict__ pair_row) {
+  constexpr bool kCount = !std::is_same<E, V>::value;
   static_assert(!(kScatter && kRelabel), "relabelling happens in the count pass");
   constexpr int kWaves = kThreads / kWave;
   constexpr int kChunks = kSegTile / kWave;   // 64 consecutive slots each
@@ -814,7 +897,7 @@ __global__ __launch_bounds__(kThreads) void k_seg_tile(
   __shared__ uint32_t s_pre[kChunks + 1];      // pair starts before each chunk
   __shared__ int32_t s_end[kSegTile];   // row ends; then the staged local rows
   __shared__ int32_t s_col[kSegTile];
-  __shared__ V s_val[kScatter ? kSegTile : 1];
+  __shared__ E s_val[kScatter ? kSegTile : 1];
   __shared__ int32_t s_src[kRelabel ? kSegTile + 1 : 1];   // old row start - new row start
   for (int i = threadIdx.x; i < kWaves * kMaxSlabs; i += kThreads) (&wh[0][0])[i] = 0u;
   const int b = blockIdx.x, tid = threadIdx.x, w = tid / kWave, lane = lane_id();
@@ -828,7 +911,8 @@ __global__ __launch_bounds__(kThreads) void k_seg_tile(
   if (kScatter && tid < kMaskWords) s_cont[tid] = fmask[int64_t(b) * kMaskWords + tid];
   __syncthreads();
   int32_t cc[kSegPer], rr[kSegPer];
-  V vv[kSegPer];
+  E vv[kSegPer];
+  V v0[kRelabel ? kSegPer : 1];
   uint32_t rank[kSegPer];
 #pragma unroll
   for (int r = 0; r < kSegPer; ++r) {
@@ -838,17 +922,35 @@ __global__ __launch_bounds__(kThreads) void k_seg_tile(
     if constexpr (kRelabel) {
       const int32_t src = valid ? j0 + e + s_src[rr[r]] : 0;
       cc[r] = valid ? rs.col0[src] : 0;
-      vv[r] = valid ? static_cast<const V *>(rs.val0)[src] : V(0);
+      v0[r] = valid ? static_cast<const V *>(rs.val0)[src] : V(0);
     } else {
       cc[r] = valid ? col[j0 + e] : 0;
-      if constexpr (kScatter) vv[r] = valid ? val[j0 + e] : V(0);
+      if constexpr (kScatter) vv[r] = valid ? val[j0 + e] : E(0);
     }
   }
   if constexpr (kRelabel) {
+    bool bad = false;
 #pragma unroll
-    for (int r = 0; r < kSegPer; ++r)
-      if (w * (kSegTile / kWaves) + r * kWave + lane < nz)
-        cc[r] = hot_get(rs.hot, rs.newlabel, cc[r]);
+    for (int r = 0; r < kSegPer; ++r) {
+      vv[r] = E(0);
+      if (w * (kSegTile / kWaves) + r * kWave + lane < nz) {
+        const int2 l = hot2_get(rs.hot, rs.lab, cc[r]);
+        cc[r] = l.x;
+        if constexpr (kCount) {
+          const double wd = double(l.y);
+          const double k = rint(double(v0[r]) * wd);
+          const bool ok = l.y > 0 && k >= 1.0 && k <= 255.0 && V(k / wd) == v0[r];
+          bad = bad || !ok;
+          vv[r] = ok ? E(k) : E(0);
+        } else {
+          vv[r] = v0[r];
+        }
+      }
+    }
+    if constexpr (kCount) {
+      const uint64_t any_bad = __ballot(bad);
+      if (any_bad && lane == 0) atomicOr(rs.bad, 1u);
+    }
 #pragma unroll
     for (int r = 0; r < kSegPer; ++r) {
       const int32_t e = w * (kSegTile / kWaves) + r * kWave + lane;
@@ -1116,11 +1218,16 @@ __global__ __launch_bounds__(256) void k_comb_bounds(const int32_t *__restrict__
 // per row adds its run.  Each workgroup stores its part of sum(y) in
 // blk_ysum; k_sum_blocks adds them (tens of thousands of workgroups would
 // queue on a shared arrival counter).
+//
+// With wdiv (degree-scaled form, every iteration but the last) the block
+// stores y[v] / wdiv[v] (0 where wdiv[v] <= 0), the vector the next
+// iteration gathers, instead of y[v]; sum(y) is formed from y either way.
 template <typename V>
 __global__ __launch_bounds__(kThreads) void k_seg_combine(
     const typename Form<V>::Part *__restrict__ part, const int32_t *__restrict__ rpp,
     const int32_t *__restrict__ pidx, const int2 *__restrict__ cstart, double c,
-    const double *__restrict__ tele_in, V *__restrict__ y, double *__restrict__ blk_ysum) {
+    const double *__restrict__ tele_in, V *__restrict__ y, double *__restrict__ blk_ysum,
+    const int32_t *__restrict__ wdiv) {
   using Acc = typename Form<V>::Acc;
   using Part = typename Form<V>::Part;
   constexpr int kCap = kCombItems + kMaxSlabs;
@@ -1168,7 +1275,12 @@ __global__ __launch_bounds__(kThreads) void k_seg_combine(
     Acc acc{};
     for (int32_t j = s_off[i]; j < e; ++j) acc = merge(acc, Form<V>::acc(s_part[j]));
     const V yv = Form<V>::finish(acc, c, tk);
-    y[R0 + i] = yv;
+    if (wdiv) {
+      const int32_t d = wdiv[R0 + i];
+      y[R0 + i] = d > 0 ? V(double(yv) / double(d)) : V(0);
+    } else {
+      y[R0 + i] = yv;
+    }
     ysum += double(yv);
   }
   const double tot = block_sum256(ysum, sh);
@@ -1343,8 +1455,10 @@ struct Layout {
   uint64_t *keys_in, *keys_out;
   void *radix_ws;
   size_t radix_bytes;
-  int32_t *order, *newlabel, *rp2, *col2;
-  uint64_t *hot;
+  int32_t *order, *wnew, *rp2, *col2;
+  int2 *lab;
+  int4 *hot;
+  uint32_t *bad;
   V *val2, *x2;
   int64_t *total;
   // column segmenting
@@ -1389,8 +1503,10 @@ Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs, size_t *byte
   L.radix_bytes = radix_ws_bytes(n, 31) + scan_ws_elems(n) * 4 + 256;
   L.radix_ws = c.take<uint8_t>(L.radix_bytes);
   L.order = c.take<int32_t>(size_t(n));
-  L.newlabel = c.take<int32_t>(size_t(n));
-  L.hot = c.take<uint64_t>(hot_bytes(n) / 8);
+  L.lab = c.take<int2>(size_t(n));
+  L.wnew = c.take<int32_t>(size_t(n));
+  L.hot = c.take<int4>(size_t(1) << hot_log2(n));
+  L.bad = c.take<uint32_t>(1);
   L.rp2 = c.take<int32_t>(size_t(n + 1));
   {
     // One region for the relabelled entries; when the columns are
@@ -1468,20 +1584,20 @@ void launch_spmm(int G, int32_t nb, hipStream_t s, const int32_t *rp, const int3
   }
 }
 
-template <typename V, bool kRaw>
+template <typename V, bool kRaw, typename E = V>
 void launch_spmv(int ipt, int32_t nb, hipStream_t s, const int32_t *rp, const int32_t *col,
-                 const V *val, const V *x, V *y, int32_t n, const int2 *coord, double c,
+                 const E *val, const V *x, V *y, int32_t n, const int2 *coord, double c,
                  const double *tele, double *blk_ysum, typename Form<V>::Acc *blk_carry,
                  typename Form<V>::Acc *blk_head, typename Form<V>::Part *part) {
   if (ipt == 4)
-    hipLaunchKernelGGL((k_spmv<V, 4, kRaw>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x, y,
-                       n, coord, c, tele, blk_ysum, blk_carry, blk_head, part);
+    hipLaunchKernelGGL((k_spmv<V, 4, kRaw, E>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x,
+                       y, n, coord, c, tele, blk_ysum, blk_carry, blk_head, part);
   else if (ipt == 16)
-    hipLaunchKernelGGL((k_spmv<V, 16, kRaw>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x, y,
-                       n, coord, c, tele, blk_ysum, blk_carry, blk_head, part);
+    hipLaunchKernelGGL((k_spmv<V, 16, kRaw, E>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x,
+                       y, n, coord, c, tele, blk_ysum, blk_carry, blk_head, part);
   else
-    hipLaunchKernelGGL((k_spmv<V, 8, kRaw>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x, y,
-                       n, coord, c, tele, blk_ysum, blk_carry, blk_head, part);
+    hipLaunchKernelGGL((k_spmv<V, 8, kRaw, E>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x,
+                       y, n, coord, c, tele, blk_ysum, blk_carry, blk_head, part);
 }
 
 // info[0] = P, info[1 + d] = first pair of slab d (d <= ns; slab ns = the
@@ -1503,6 +1619,7 @@ struct SegInfo {
   int32_t sbits = 0, ns = 0;
   int64_t P = 0;
   bool relabelled = false;   // the count pass wrote the relabelled entries
+  bool scaled = false;       // ... as counts (degree-scaled form), stored so by the scatter
 };
 
 // In-place slab-major offsets of a tile-by-tile count matrix (k_col_sums,
@@ -1523,12 +1640,19 @@ pp_status col_offsets(uint32_t *cnt, int32_t ntiles, int32_t ns, uint32_t *bsum,
 // Segmented layout of the matrix (rp, col, val): see the kernels above.
 // With rl the matrix is the relabelled one, whose entries (col, val) the
 // count pass writes from rl's source matrix (out->relabelled tells whether
-// it ran).  Segmenting does not apply with fewer than two slabs or when
-// pairs + entries reach 2^31.  Reads the pair counts back to the host, so it
-// synchronizes the stream once.
+// it ran).  With scaled (and rl) the count pass first tries the
+// degree-scaled form, writing the entries' counts (as bytes, into val's
+// space) instead of their values; if any entry is not count / weight it
+// runs again storing values.  The host reads that verdict (one stream
+// synchronisation) and the scatter pass stores whichever form was written
+// (out->scaled).  Segmenting does not apply with fewer than two slabs or
+// when pairs + entries reach 2^31; if the count form was written then, the
+// relabelled entries are left to k_relabel_copy (out->relabelled false).
+// Reads the pair counts back to the host, so it synchronizes the stream
+// once more.
 template <typename V>
 pp_status build_segments(const Layout<V> &L, const int32_t *rp, int32_t *col, V *val, int64_t n,
-                         int64_t nnz, int slab_log2, const RelabelSrc *rl,
+                         int64_t nnz, int slab_log2, const RelabelSrc *rl, bool scaled,
                          SegInfo *out, hipStream_t s) {
   *out = SegInfo{};
   int sbits = slab_log2;
@@ -1538,18 +1662,33 @@ pp_status build_segments(const Layout<V> &L, const int32_t *rp, int32_t *col, V 
   const int32_t dbits = 32 - __builtin_clz(uint32_t(ns - 1));
   const int32_t n32 = int32_t(n);
   const int32_t ntiles = int32_t((n + nnz + kSegTile - 1) / kSegTile);
+  uint8_t *cnt = reinterpret_cast<uint8_t *>(val);
   hipLaunchKernelGGL(k_partition, dim3(grid_for(int64_t(ntiles) + 1, 256, 4096)), dim3(256), 0, s,
                      rp, n32, int32_t(nnz), ntiles, kSegTile, L.seg_coord);
-  if (rl) {
-    hipLaunchKernelGGL((k_seg_tile<V, false, true>), dim3(ntiles), dim3(kThreads), 0, s, rp, col,
-                       val, n32, *rl, L.seg_coord, sbits, ns, dbits, ntiles, L.seg_cnt,
+  bool counts = false;
+  if (rl && scaled) {
+    pp_status st = fill_i32(reinterpret_cast<int32_t *>(rl->bad), 1, 0, s);
+    if (st != PP_OK) return st;
+    hipLaunchKernelGGL((k_seg_tile<V, uint8_t, false, true>), dim3(ntiles), dim3(kThreads), 0, s,
+                       rp, col, cnt, n32, *rl, L.seg_coord, sbits, ns, dbits, ntiles, L.seg_cnt,
                        L.seg_pcnt, L.seg_fmask, L.seg_lmask, nullptr, nullptr, nullptr, nullptr);
-    out->relabelled = true;
-  } else {
-    hipLaunchKernelGGL((k_seg_tile<V, false, false>), dim3(ntiles), dim3(kThreads), 0, s, rp, col,
-                       val, n32, RelabelSrc{}, L.seg_coord, sbits, ns, dbits, ntiles, L.seg_cnt,
-                       L.seg_pcnt, L.seg_fmask, L.seg_lmask, nullptr, nullptr, nullptr, nullptr);
+    PP_LAUNCHED("k_seg_tile (count, scaled)");
+    uint32_t bad = 1;
+    PP_HIP(hipMemcpyAsync(&bad, rl->bad, sizeof(bad), hipMemcpyDeviceToHost, s));
+    PP_HIP(hipStreamSynchronize(s));
+    counts = bad == 0;
   }
+  if (rl && !counts) {
+    hipLaunchKernelGGL((k_seg_tile<V, V, false, true>), dim3(ntiles), dim3(kThreads), 0, s, rp,
+                       col, val, n32, *rl, L.seg_coord, sbits, ns, dbits, ntiles, L.seg_cnt,
+                       L.seg_pcnt, L.seg_fmask, L.seg_lmask, nullptr, nullptr, nullptr, nullptr);
+  } else if (!rl) {
+    hipLaunchKernelGGL((k_seg_tile<V, V, false, false>), dim3(ntiles), dim3(kThreads), 0, s, rp,
+                       col, val, n32, RelabelSrc{}, L.seg_coord, sbits, ns, dbits, ntiles,
+                       L.seg_cnt, L.seg_pcnt, L.seg_fmask, L.seg_lmask, nullptr, nullptr, nullptr,
+                       nullptr);
+  }
+  out->relabelled = rl != nullptr;
   hipLaunchKernelGGL(k_seg_cont, dim3(grid_for(ntiles, 256, 4096)), dim3(256), 0, s, rp, n32,
                      L.seg_coord, ntiles, ns, L.seg_lmask, L.seg_fmask, L.seg_pcnt);
   PP_LAUNCHED("k_seg_tile (count)/k_seg_cont");
@@ -1557,9 +1696,16 @@ pp_status build_segments(const Layout<V> &L, const int32_t *rp, int32_t *col, V 
   if (st != PP_OK) return st;
   st = col_offsets(L.seg_pcnt, ntiles, ns, L.seg_bsum, L.seg_scan, L.total, s);
   if (st != PP_OK) return st;
-  hipLaunchKernelGGL((k_seg_tile<V, true, false>), dim3(ntiles), dim3(kThreads), 0, s, rp, col,
-                     val, n32, RelabelSrc{}, L.seg_coord, sbits, ns, dbits, ntiles, L.seg_cnt,
-                     L.seg_pcnt, L.seg_fmask, nullptr, L.seg_col, L.seg_val, L.prp, L.pair_row);
+  if (counts)
+    hipLaunchKernelGGL((k_seg_tile<V, uint8_t, true, false>), dim3(ntiles), dim3(kThreads), 0, s,
+                       rp, col, cnt, n32, RelabelSrc{}, L.seg_coord, sbits, ns, dbits, ntiles,
+                       L.seg_cnt, L.seg_pcnt, L.seg_fmask, nullptr, L.seg_col,
+                       reinterpret_cast<uint8_t *>(L.seg_val), L.prp, L.pair_row);
+  else
+    hipLaunchKernelGGL((k_seg_tile<V, V, true, false>), dim3(ntiles), dim3(kThreads), 0, s, rp,
+                       col, val, n32, RelabelSrc{}, L.seg_coord, sbits, ns, dbits, ntiles,
+                       L.seg_cnt, L.seg_pcnt, L.seg_fmask, nullptr, L.seg_col, L.seg_val, L.prp,
+                       L.pair_row);
   hipLaunchKernelGGL(k_seg_info, dim3(1), dim3(256), 0, s, L.seg_pcnt, ns, nnz, L.total, L.prp,
                      L.info);
   PP_LAUNCHED("k_seg_tile (scatter)/k_seg_info");
@@ -1567,9 +1713,13 @@ pp_status build_segments(const Layout<V> &L, const int32_t *rp, int32_t *col, V 
   PP_HIP(hipMemcpyAsync(info, L.info, sizeof(int64_t) * size_t(2 + ns), hipMemcpyDeviceToHost, s));
   PP_HIP(hipStreamSynchronize(s));
   const int64_t P = info[0];
-  if (P <= 0 || P > nnz || P + nnz > int64_t(INT32_MAX)) return PP_OK;
+  if (P <= 0 || P > nnz || P + nnz > int64_t(INT32_MAX)) {
+    if (counts) out->relabelled = false;   // the one-pass path needs values
+    return PP_OK;
+  }
   SegInfo si;
   si.relabelled = out->relabelled;
+  si.scaled = counts;
   si.sbits = sbits;
   si.ns = ns;
   si.P = P;
@@ -1632,6 +1782,21 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
     lanes = g_cfg.rhs_lanes;
   const int gN = grid_for(n, 256, 8192);
   const int gNK = grid_for(n * k, 256, 8192);
+  // SpMM column tiles: T < k runs the right-hand sides T at a time, each
+  // tile an n x Tt block of its own (see k_permute_in), so one pass gathers
+  // rows of Tt values from a block small enough to stay in the Infinity
+  // Cache; T = k is the single pass over row-major blocks.
+  const int32_t T = (k > 1 && g_cfg.rhs_tile > 0 && g_cfg.rhs_tile < k) ? g_cfg.rhs_tile : k;
+  const bool tiled = T < k;
+  const int32_t ntile = (k + T - 1) / T;
+  auto tile_cols = [&](int32_t t) { return k - t * T < T ? k - t * T : T; };
+  auto tile_lanes = [&](int32_t Tt) {
+    if (!tiled) return lanes;
+    int gl = 2;
+    while (gl < Tt) gl <<= 1;
+    if (g_cfg.rhs_lanes >= gl && g_cfg.rhs_lanes <= 64) gl = g_cfg.rhs_lanes;
+    return gl;
+  };
   pp_status st;
   if ((st = fill_i32(reinterpret_cast<int32_t *>(L.counter), 4, 0, s)) != PP_OK) return st;
 
@@ -1639,23 +1804,29 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
   const int32_t *rp = AT0.row_ptr, *col = AT0.col;
   const V *val = static_cast<const V *>(AT0.val);
   V *x0 = r;
-  HotTab hot{nullptr, 0};
+  Hot2 hot{nullptr, 0};
   if (weights) {
     hipLaunchKernelGGL(k_order_keys, dim3(gN), dim3(256), 0, s, weights, n32, L.keys_in);
     PP_LAUNCHED("k_order_keys");
     st = radix_sort(RadixIn{L.keys_in, nullptr, nullptr}, RadixOut{L.keys_out, nullptr, nullptr},
                     n, 5, L.radix_ws, L.radix_bytes, 0, false, nullptr, s, false);
     if (st != PP_OK) return st;
-    hipLaunchKernelGGL(k_relabel_maps, dim3(gN), dim3(256), 0, s, L.keys_out, AT0.row_ptr, n32,
-                       L.order, L.newlabel, reinterpret_cast<uint32_t *>(L.rp2));
+    hipLaunchKernelGGL(k_relabel_maps, dim3(gN), dim3(256), 0, s, L.keys_out, AT0.row_ptr,
+                       weights, n32, L.order, L.lab, L.wnew, reinterpret_cast<uint32_t *>(L.rp2));
     PP_LAUNCHED("k_relabel_maps");
     st = exscan_u32(reinterpret_cast<uint32_t *>(L.rp2), reinterpret_cast<uint32_t *>(L.rp2), n,
                     reinterpret_cast<uint32_t *>(L.keys_in), L.total, s);
     if (st != PP_OK) return st;
     hipLaunchKernelGGL(k_set_total, dim3(1), dim3(64), 0, s, L.rp2, n32, L.total);
-    // Every entry's column goes through newlabel at random; the heaviest
-    // sources' new labels are cached in an L2-sized table in front of it.
-    if ((st = hot_build(weights, L.newlabel, n32, L.hot, &hot, s)) != PP_OK) return st;
+    // Every entry's column goes through lab at random; the heaviest
+    // sources' entries are cached in an L2-sized table in front of it (the
+    // winners are picked into keys_in, free once rp2 is scanned).
+    const int lg = hot_log2(n);
+    if ((st = hot_select(weights, n32, L.keys_in, lg, s)) != PP_OK) return st;
+    hipLaunchKernelGGL(k_hot2_fill, dim3(grid_for(int64_t(1) << lg, 256, 1024)), dim3(256), 0, s,
+                       L.keys_in, L.lab, L.hot, 1u << lg);
+    PP_LAUNCHED("k_hot2_fill");
+    hot = Hot2{L.hot, (1u << lg) - 1u};
     rp = L.rp2;
     col = L.col2;
     val = L.val2;
@@ -1676,24 +1847,39 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
   if (slab_log2 < 0)
     slab_log2 = n * int64_t(sizeof(V)) > (int64_t(4) << 20) ? (sizeof(V) == 4 ? 19 : 18) : 0;
   const bool segment = k == 1 && slab_log2 > 0 && iters > 0;
-  if (weights) {
-    hipLaunchKernelGGL(k_permute_in<V>, dim3(gNK), dim3(256), 0, s, r, L.order, n32, k, L.x2);
-    PP_LAUNCHED("k_permute_in");
-  }
   SegInfo si;
   int32_t nbp = 0, ncomb = 0;
   int64_t Pr = 0;   // pairs (and their entries) left to the raw SpMV
   if (segment) {
-    const RelabelSrc rl{AT0.row_ptr, AT0.col, L.order, L.newlabel, AT0.val, hot};
+    // The degree-scaled form needs the relabelled, segmented path and is
+    // left out of runs to a convergence test (their pass reads x as ranks).
+    const RelabelSrc rl{AT0.row_ptr, AT0.col, L.order, L.lab, AT0.val, hot, L.bad};
     st = build_segments<V>(L, rp, const_cast<int32_t *>(col), const_cast<V *>(val), n, nnz,
-                           slab_log2, weights ? &rl : nullptr, &si, s);
+                           slab_log2, weights ? &rl : nullptr, g_cfg.scaled != 0 && !cv, &si, s);
     if (st != PP_OK) return st;
   }
   if (weights && !si.relabelled) {
     hipLaunchKernelGGL(k_relabel_copy<V>, dim3(nb), dim3(kThreads), 0, s, AT0.row_ptr, AT0.col,
-                       static_cast<const V *>(AT0.val), L.order, L.newlabel, hot, L.rp2, n32,
+                       static_cast<const V *>(AT0.val), L.order, L.lab, hot, L.rp2, n32,
                        L.coord, L.col2, L.val2);
     PP_LAUNCHED("k_relabel_copy");
+  }
+  const bool scaled = si.P > 0 && si.scaled;
+  g_last_layout = (weights ? 1 : 0) | (si.P > 0 ? 2 : 0) | (scaled ? 4 : 0);
+  if (weights) {
+    // r into the new labels; in the degree-scaled form divided by the
+    // weights (the gathered vector is r_u / w[u]).
+    if (scaled)
+      hipLaunchKernelGGL(k_permute_in_scaled<V>, dim3(gN), dim3(256), 0, s, r, L.order, L.wnew,
+                         n32, L.x2);
+    else
+      hipLaunchKernelGGL(k_permute_in<V>, dim3(gNK), dim3(256), 0, s, r, L.order, n32, k, T,
+                         L.x2);
+    PP_LAUNCHED("k_permute_in");
+  } else if (tiled) {
+    hipLaunchKernelGGL(k_permute_in<V>, dim3(gNK), dim3(256), 0, s, r, nullptr, n32, k, T, L.x2);
+    PP_LAUNCHED("k_permute_in (tiles)");
+    x0 = L.x2;
   }
   if (segment) {
     if (si.P > 0) {
@@ -1705,16 +1891,19 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
       hipLaunchKernelGGL(k_block_flags, dim3(grid_for(nbp, 256, 4096)), dim3(256), 0, s, L.prp,
                          int32_t(Pr), nbp, L.coord, L.carry_row, L.closes);
       PP_LAUNCHED("k_partition/k_block_flags (pairs)");
+
     }
   }
 
   const int G0 = int((n + kSumChunk - 1) / kSumChunk);
-  if (k == 1)
-    hipLaunchKernelGGL(k_sum0<V>, dim3(G0), dim3(kThreads), 0, s, x0, n, kSumChunk, L.part,
-                       L.counter, w, sums, L.tele);
-  else
-    hipLaunchKernelGGL(k_sum0_mm<V>, dim3(G0), dim3(kThreads), 0, s, x0, n, k, lanes, kSumChunk,
+  if (k == 1)   // sum(r_0) from the ranks themselves (x0 holds r_0 / w in the scaled form)
+    hipLaunchKernelGGL(k_sum0<V>, dim3(G0), dim3(kThreads), 0, s, scaled ? r : x0, n, kSumChunk,
                        L.part, L.counter, w, sums, L.tele);
+  else
+    for (int32_t t = 0; t < ntile; ++t)
+      hipLaunchKernelGGL(k_sum0_mm<V>, dim3(G0), dim3(kThreads), 0, s, x0 + n * t * T, n,
+                         tile_cols(t), tile_lanes(tile_cols(t)), kSumChunk, L.part, L.counter, w,
+                         sums ? sums + t * T : nullptr, L.tele + t * T);
   PP_LAUNCHED("k_sum0");
   const int cblk = grid_for(n, kThreads * 4, kConvBlocks);
   const uint8_t *dflag = nullptr;
@@ -1744,34 +1933,47 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
     done = it + 1;
     if ((st = timed_begin(s)) != PP_OK) return st;
     if (si.P > 0) {
-      launch_spmv<V, true>(ipt, nbp, s, L.prp, L.seg_col, L.seg_val, x, nullptr, int32_t(Pr),
-                           L.coord, c, t_in, nullptr, L.blk_carry, L.blk_head, L.seg_part);
+      if (scaled)
+        launch_spmv<V, true, uint8_t>(ipt, nbp, s, L.prp, L.seg_col,
+                                      reinterpret_cast<const uint8_t *>(L.seg_val), x, nullptr,
+                                      int32_t(Pr), L.coord, c, t_in, nullptr, L.blk_carry,
+                                      L.blk_head, L.seg_part);
+      else
+        launch_spmv<V, true>(ipt, nbp, s, L.prp, L.seg_col, L.seg_val, x, nullptr, int32_t(Pr),
+                             L.coord, c, t_in, nullptr, L.blk_carry, L.blk_head, L.seg_part);
       hipLaunchKernelGGL(k_fix_raw<V>, dim3(grid_for(nbp, 256, 4096)), dim3(256), 0, s,
                          L.seg_part, nbp, L.coord, L.closes, L.carry_row, L.blk_carry,
                          L.blk_head);
+      // The scaled form stores y / w for the next iteration, y itself after the last.
       hipLaunchKernelGGL(k_seg_combine<V>, dim3(ncomb), dim3(kThreads), 0, s, L.seg_part, L.rpp,
-                         L.pidx, L.cstart, c, t_in, yv, L.blk_ysum);
+                         L.pidx, L.cstart, c, t_in, yv, L.blk_ysum,
+                         scaled && it + 1 < iters ? L.wnew : nullptr);
       hipLaunchKernelGGL(k_sum_blocks, dim3(1), dim3(1024), 0, s, L.blk_ysum, ncomb, w, s_out,
                          t_out);
       if ((st = timed_end(s)) != PP_OK) return st;
       PP_LAUNCHED("k_spmv raw/k_fix_raw/k_seg_combine");
-    } else {
-      if (k == 1)
-        launch_spmv<V, false>(ipt, nb, s, rp, col, val, x, yv, n32, L.coord, c, t_in, L.blk_ysum,
-                              L.blk_carry, L.blk_head, nullptr);
-      else
-        launch_spmm<V>(lanes, nb, s, rp, col, val, x, yv, n32, k, L.coord, c, t_in, L.blk_ysum,
-                       L.blk_carry, L.blk_head);
+    } else if (k == 1) {
+      launch_spmv<V, false>(ipt, nb, s, rp, col, val, x, yv, n32, L.coord, c, t_in, L.blk_ysum,
+                            L.blk_carry, L.blk_head, nullptr);
       if ((st = timed_end(s)) != PP_OK) return st;
-      if (k == 1)
-        hipLaunchKernelGGL(k_finish<V>, dim3(G), dim3(kThreads), 0, s, yv, nb, L.coord, L.closes,
-                           L.carry_row, L.blk_carry, L.blk_head, L.blk_ysum, c, t_in, L.part,
-                           L.counter, w, s_out, t_out);
-      else
-        hipLaunchKernelGGL(k_finish_mm<V>, dim3(G), dim3(kThreads), 0, s, yv, nb, k, lanes,
-                           L.coord, L.closes, L.carry_row, L.blk_carry, L.blk_head, L.blk_ysum,
-                           c, t_in, L.part, L.counter, w, s_out, t_out);
+      hipLaunchKernelGGL(k_finish<V>, dim3(G), dim3(kThreads), 0, s, yv, nb, L.coord, L.closes,
+                         L.carry_row, L.blk_carry, L.blk_head, L.blk_ysum, c, t_in, L.part,
+                         L.counter, w, s_out, t_out);
       PP_LAUNCHED("k_spmv/k_finish");
+    } else {
+      // One SpMM and its finish per column tile; the event pair spans them all.
+      for (int32_t t = 0; t < ntile; ++t) {
+        const int32_t Tt = tile_cols(t), gl = tile_lanes(Tt);
+        const int64_t off = n * t * T;
+        launch_spmm<V>(gl, nb, s, rp, col, val, x + off, yv + off, n32, Tt, L.coord, c,
+                       t_in + t * T, L.blk_ysum, L.blk_carry, L.blk_head);
+        hipLaunchKernelGGL(k_finish_mm<V>, dim3(G), dim3(kThreads), 0, s, yv + off, nb, Tt, gl,
+                           L.coord, L.closes, L.carry_row, L.blk_carry, L.blk_head, L.blk_ysum,
+                           c, t_in + t * T, L.part, L.counter, w, s_out ? s_out + t * T : nullptr,
+                           t_out + t * T);
+      }
+      if ((st = timed_end(s)) != PP_OK) return st;
+      PP_LAUNCHED("k_spmm/k_finish_mm");
     }
     if (cv) {
       // The step's dangling term, difference, sum and teleport; the host
@@ -1792,8 +1994,9 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
   }
   if (cv) *cv->iters_done = done;
   const V *last = (done & 1) ? L.y : x0;
-  if (weights) {
-    hipLaunchKernelGGL(k_permute_out<V>, dim3(gNK), dim3(256), 0, s, last, L.order, n32, k, r);
+  if (weights || tiled) {
+    hipLaunchKernelGGL(k_permute_out<V>, dim3(gNK), dim3(256), 0, s, last,
+                       weights ? L.order : nullptr, n32, k, T, r);
     PP_LAUNCHED("k_permute_out");
     return PP_OK;
   }
@@ -1826,21 +2029,32 @@ int32_t kernel_times(float *ms, int32_t cap) {
   return n;
 }
 
-pp_status set_k3_config(int32_t ipt, int32_t rhs_lanes, int32_t slab_log2) {
+int32_t k3_last_layout() { return g_last_layout; }
+
+pp_status set_k3_config(int32_t ipt, int32_t rhs_lanes, int32_t slab_log2, int32_t scaled,
+                        int32_t rhs_tile) {
   if (ipt != 4 && ipt != 8 && ipt != 16) return fail(PP_EINVAL, "items per thread %d", ipt);
   if (rhs_lanes != 0 && (rhs_lanes < 2 || rhs_lanes > 64 || (rhs_lanes & (rhs_lanes - 1))))
     return fail(PP_EINVAL, "rhs lanes %d", rhs_lanes);
   if (slab_log2 < -1 || slab_log2 > 30) return fail(PP_EINVAL, "slab log2 %d", slab_log2);
+  if (scaled != 0 && scaled != 1) return fail(PP_EINVAL, "scaled form %d", scaled);
+  if (rhs_tile != 0 && (rhs_tile < 2 || rhs_tile > 32 || (rhs_tile & (rhs_tile - 1))))
+    return fail(PP_EINVAL, "rhs tile %d", rhs_tile);
   g_cfg.ipt = ipt;
   g_cfg.rhs_lanes = rhs_lanes;
   g_cfg.slab_log2 = slab_log2;
+  g_cfg.scaled = scaled;
+  g_cfg.rhs_tile = rhs_tile;
   return PP_OK;
 }
 
-void get_k3_config(int32_t *ipt, int32_t *rhs_lanes, int32_t *slab_log2) {
+void get_k3_config(int32_t *ipt, int32_t *rhs_lanes, int32_t *slab_log2, int32_t *scaled,
+                   int32_t *rhs_tile) {
   *ipt = g_cfg.ipt;
   *rhs_lanes = g_cfg.rhs_lanes;
   *slab_log2 = g_cfg.slab_log2;
+  *scaled = g_cfg.scaled;
+  *rhs_tile = g_cfg.rhs_tile;
 }
 
 size_t pagerank_ws_bytes(int64_t n, int64_t nnz_cap, pp_dtype dt, int32_t nrhs) {

@@ -339,15 +339,19 @@ pp_status pp_pagerank_graphs_noalloc(int32_t ngraphs, const pp_graph *graphs, pp
 int32_t pp_graphs_noalloc_max(void) { return graphs_static_max(); }
 
 pp_status pp_set_k3_config(const pp_k3_config *cfg) {
-  if (!cfg) return set_k3_config(8, 0, -1);
-  return set_k3_config(cfg->items_per_thread, cfg->rhs_lanes, cfg->slab_log2);
+  if (!cfg) return set_k3_config(8, 0, -1, 1, 0);
+  return set_k3_config(cfg->items_per_thread, cfg->rhs_lanes, cfg->slab_log2, cfg->scaled_form,
+                       cfg->rhs_tile);
 }
 
 pp_status pp_get_k3_config(pp_k3_config *cfg) {
   if (!cfg) return fail(PP_EINVAL, "pp_get_k3_config: null");
-  get_k3_config(&cfg->items_per_thread, &cfg->rhs_lanes, &cfg->slab_log2);
+  get_k3_config(&cfg->items_per_thread, &cfg->rhs_lanes, &cfg->slab_log2, &cfg->scaled_form,
+                &cfg->rhs_tile);
   return PP_OK;
 }
+
+int32_t pp_k3_last_layout(void) { return k3_last_layout(); }
 
 pp_status pp_set_kernel_timing(int enable) { return set_kernel_timing(enable != 0); }
 

@@ -210,6 +210,9 @@ pp_status copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t s);
 // out) with values full[u]; hot_bytes(n) is the table's size.
 int hot_log2(int64_t n);
 size_t hot_bytes(int64_t n);
+// hot_select only picks the winners: tab[slot] = (deg[u] << 32 | u) of the
+// heaviest u (deg >= 8) hashed to the slot, 0 for an empty slot.
+pp_status hot_select(const int32_t *deg, int32_t n, uint64_t *tab, int lg, hipStream_t s);
 pp_status hot_build(const int32_t *deg, const int32_t *full, int32_t n, uint64_t *tab,
                     HotTab *h, hipStream_t s);
 
@@ -295,8 +298,11 @@ int32_t graphs_static_max();
 pp_status launch_graphs_static(int32_t ngraphs, const pp_graph *graphs, int64_t max_n,
                                pp_dtype dt, int32_t iters, double c, hipStream_t s);
 
-pp_status set_k3_config(int32_t ipt, int32_t rhs_lanes, int32_t slab_log2);
-void get_k3_config(int32_t *ipt, int32_t *rhs_lanes, int32_t *slab_log2);
+pp_status set_k3_config(int32_t ipt, int32_t rhs_lanes, int32_t slab_log2, int32_t scaled,
+                        int32_t rhs_tile);
+void get_k3_config(int32_t *ipt, int32_t *rhs_lanes, int32_t *slab_log2, int32_t *scaled,
+                   int32_t *rhs_tile);
+int32_t k3_last_layout();
 pp_status set_kernel_timing(bool enable);
 int32_t kernel_times(float *ms, int32_t cap);
 

@@ -56,15 +56,23 @@ __global__ __launch_bounds__(256) void k_hot_fill(const int32_t *__restrict__ fu
   }
 }
 
-pp_status hot_build(const int32_t *deg, const int32_t *full, int32_t n, uint64_t *tab, HotTab *h,
-                    hipStream_t s) {
-  const int lg = hot_log2(n);
+pp_status hot_select(const int32_t *deg, int32_t n, uint64_t *tab, int lg, hipStream_t s) {
   const uint32_t slots = 1u << lg;
   pp_status st;
   if ((st = fill_u64(tab, slots, 0, s)) != PP_OK) return st;
   if (n > 0)
     hipLaunchKernelGGL(k_hot_max, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, deg, n,
                        reinterpret_cast<unsigned long long *>(tab), slots - 1u);
+  PP_LAUNCHED("k_hot_max");
+  return PP_OK;
+}
+
+pp_status hot_build(const int32_t *deg, const int32_t *full, int32_t n, uint64_t *tab, HotTab *h,
+                    hipStream_t s) {
+  const int lg = hot_log2(n);
+  const uint32_t slots = 1u << lg;
+  pp_status st;
+  if ((st = hot_select(deg, n, tab, lg, s)) != PP_OK) return st;
   hipLaunchKernelGGL(k_hot_fill, dim3(grid_for(slots, 256, 1024)), dim3(256), 0, s, full, tab,
                      slots);
   PP_LAUNCHED("k_hot_max/k_hot_fill");

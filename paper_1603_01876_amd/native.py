@@ -47,7 +47,8 @@ class _Csr(ctypes.Structure):
 
 class _K3Config(ctypes.Structure):
     _fields_ = [("items_per_thread", ctypes.c_int32), ("rhs_lanes", ctypes.c_int32),
-                ("slab_log2", ctypes.c_int32)]
+                ("slab_log2", ctypes.c_int32), ("scaled_form", ctypes.c_int32),
+                ("rhs_tile", ctypes.c_int32)]
 
 
 class _Graph(ctypes.Structure):
@@ -92,6 +93,7 @@ SIGNATURES = {
     "pp_graphs_noalloc_max": (_I32, []),
     "pp_set_k3_config": (ctypes.c_int, [ctypes.c_void_p]),
     "pp_get_k3_config": (ctypes.c_int, [ctypes.c_void_p]),
+    "pp_k3_last_layout": (_I32, []),
     "pp_set_kernel_timing": (ctypes.c_int, [ctypes.c_int]),
     "pp_kernel_times": (_I32, [ctypes.POINTER(ctypes.c_float), _I32]),
 }
@@ -426,19 +428,28 @@ def graphs_noalloc_max() -> int:
     return int(lib().pp_graphs_noalloc_max())
 
 
-def set_k3_config(items_per_thread: int = 8, rhs_lanes: int = 0, slab_log2: int = -1) -> None:
+def set_k3_config(items_per_thread: int = 8, rhs_lanes: int = 0, slab_log2: int = -1,
+                  scaled_form: int = 1, rhs_tile: int = 0) -> None:
     """Launch configuration of pagerank() (see pp_set_k3_config)."""
-    cfg = _K3Config(items_per_thread, rhs_lanes, slab_log2)
+    cfg = _K3Config(items_per_thread, rhs_lanes, slab_log2, scaled_form, rhs_tile)
     _check(lib().pp_set_k3_config(ctypes.addressof(cfg)), "pp_set_k3_config")
 
 
-def get_k3_config() -> tuple[int, int, int]:
+def get_k3_config() -> tuple[int, int, int, int, int]:
+    """(items_per_thread, rhs_lanes, slab_log2, scaled_form, rhs_tile)."""
     cfg = _K3Config()
     _check(lib().pp_get_k3_config(ctypes.addressof(cfg)), "pp_get_k3_config")
-    return int(cfg.items_per_thread), int(cfg.rhs_lanes), int(cfg.slab_log2)
+    return (int(cfg.items_per_thread), int(cfg.rhs_lanes), int(cfg.slab_log2),
+            int(cfg.scaled_form), int(cfg.rhs_tile))
 
 
 # ------------------------------------------------------------ instrumentation
+def k3_last_layout() -> dict:
+    """What the last pagerank() call iterated on (see pp_k3_last_layout)."""
+    v = int(lib().pp_k3_last_layout())
+    return {"relabelled": bool(v & 1), "segmented": bool(v & 2), "scaled": bool(v & 4)}
+
+
 def set_kernel_timing(enable: bool) -> None:
     """Records HIP events around every sparse-product launch of pagerank()."""
     _check(lib().pp_set_kernel_timing(int(enable)), "pp_set_kernel_timing")

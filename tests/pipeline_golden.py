@@ -77,8 +77,13 @@ def oracle_k3(AT64, golden: dict, tag: str):
 
 def k3_configs():
     """The library default plus every candidate the benchmark's tuner may
-    time (items per thread, lanes, slab width, relabelling)."""
-    return [(8, 0, -1, False), (8, 0, -1, True)] + autotune.candidates(1, (False, True))
+    time (items per thread, lanes, slab width, relabelling), each with the
+    degree-scaled form on (the default; it applies to relabelled, segmented
+    runs), plus the relabelled, segmented candidates with it off."""
+    cands = [(8, 0, -1, False), (8, 0, -1, True)] + autotune.candidates(1, (False, True))
+    on = [c + (1,) for c in cands]
+    off = [c + (0,) for c in cands if c[3] and c[2] != 0]
+    return on + off
 
 
 def rel_l1(a, b) -> float:
@@ -97,7 +102,7 @@ def check_k3_configs(AT, dtype, d_out, want_r, want_sums, golden, ws, tag):
     rows = np.asarray(golden["r20_rows"], np.int64)
     try:
         for cfg in k3_configs():
-            pp.set_k3_config(*cfg[:3])
+            pp.set_k3_config(*cfg[:3], cfg[4])
             r = pp.init_r(n, golden["r0_seed"], dtype, ws=ws)
             sums = pp.pagerank(AT, r, iters=iters, c=golden["damping"], ws=ws,
                                weights=d_out if cfg[3] else None)
@@ -105,8 +110,9 @@ def check_k3_configs(AT, dtype, d_out, want_r, want_sums, golden, ws, tag):
             gs = sums.cpu().numpy()
             e = rel_l1(got, want_r)
             es = float(np.abs(gs / want_sums - 1).max())
-            errs[autotune.name(cfg)] = e
-            say(tag, f"{dtype} config {autotune.name(cfg)}: rel L1 {e:.3e}, sums {es:.3e}")
+            errs[autotune.name(cfg[:4]) + f",scaled{cfg[4]}"] = e
+            say(tag, f"{dtype} config {autotune.name(cfg[:4])},scaled{cfg[4]}: rel L1 {e:.3e}, "
+                     f"sums {es:.3e}")
             assert e <= TOL[dtype], (cfg, e)
             assert es <= TOL[dtype], (cfg, es)
             # The stored samples agree too (they are the same oracle run).

@@ -290,13 +290,17 @@ def test_product_path_has_no_cpu_fallback():
 
 def test_k3_config_roundtrip_and_validation():
     native.set_k3_config(16, 0, 19)
-    assert native.get_k3_config() == (16, 0, 19)
-    for bad in ((8, 0, -2), (8, 0, 31), (5, 0, 0), (8, 3, 0), (8, 128, 0)):
+    assert native.get_k3_config() == (16, 0, 19, 1, 0)
+    native.set_k3_config(16, 0, 19, 0, 8)
+    assert native.get_k3_config() == (16, 0, 19, 0, 8)
+    for bad in ((8, 0, -2), (8, 0, 31), (5, 0, 0), (8, 3, 0), (8, 128, 0), (8, 0, 0, 2),
+                (8, 0, 0, -1), (8, 0, 0, 1, 3), (8, 0, 0, 1, 64), (8, 0, 0, 1, 1),
+                (8, 0, 0, 1, -2)):
         with pytest.raises(native.PPError):
             native.set_k3_config(*bad)
-    assert native.get_k3_config() == (16, 0, 19)   # a rejected call changes nothing
+    assert native.get_k3_config() == (16, 0, 19, 0, 8)   # a rejected call changes nothing
     native.lib().pp_set_k3_config(None)
-    assert native.get_k3_config() == (8, 0, -1)
+    assert native.get_k3_config() == (8, 0, -1, 1, 0)
 
 
 def test_transpose_validation():

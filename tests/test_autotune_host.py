@@ -18,13 +18,20 @@ def test_single_vector_candidates():
     assert all(c[3] for c in both[5:])
 
 
-def test_spmm_lane_candidates():
-    assert [c[1] for c in autotune.candidates(32)] == [32, 64]
+def test_spmm_lane_and_tile_candidates():
+    # One pass with lanes = nextpow2(nrhs) or 64, then column tiles of 16 and
+    # 8 right-hand sides where they are narrower than nrhs.
+    assert autotune.candidates(32) == [(8, 32, 0, False, 0), (8, 64, 0, False, 0),
+                                       (8, 0, 0, False, 16), (8, 0, 0, False, 8)]
     assert [c[1] for c in autotune.candidates(3)] == [4, 64]
-    assert [c[1] for c in autotune.candidates(64)] == [64]
+    assert [c[4] for c in autotune.candidates(12)] == [0, 0, 8]
+    assert autotune.candidates(64) == [(8, 64, 0, False, 0), (8, 0, 0, False, 16),
+                                       (8, 0, 0, False, 8)]
     assert [c[1] for c in autotune.candidates(2, (False, True))] == [2, 2, 64, 64]
-    for c in autotune.candidates(17, (False, True)):
-        native.set_k3_config(*c[:3])           # every candidate is a valid configuration
+    for c in autotune.candidates(17, (False, True)) + autotune.candidates(1, (False, True)):
+        native.set_k3_config(*autotune.config_of(c))   # every candidate is a valid configuration
+    assert autotune.config_of((8, 0, 0, True, 16)) == [8, 0, 0, 1, 16]
+    assert autotune.config_of((16, 0, 19, True)) == [16, 0, 19, 1, 0]
     native.set_k3_config()
 
 
@@ -46,7 +53,7 @@ def test_cache_hit_applies_the_stored_choice(tmp_path):
     native.set_k3_config()
     got = autotune.tune(AT, "f32", 1, weights=object(), iters=20, cache=str(cache))
     assert got == entry
-    assert native.get_k3_config() == (16, 0, 19)
+    assert native.get_k3_config()[:3] == (16, 0, 19)
     native.set_k3_config()
 
 

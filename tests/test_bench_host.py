@@ -77,6 +77,21 @@ def test_spmv_label_names_the_timed_launches():
     assert bench.spmv_label((8, 0, 0), "f64") == "k_spmv<double,8> + k_finish<double>"
 
 
+def test_scaled_form_bytes_and_label():
+    # Degree-scaled form: row pointers, columns, one count byte per entry,
+    # the gathered vector read and the next one written, the out-degrees.
+    lay = {"relabelled": True, "segmented": True, "scaled": True}
+    n, z = 1 << 26, 1051749331
+    assert bench.form_bytes(n, z, "f64", lay) == 4 * (n + 1) + 5 * z + 16 * n + 4 * n
+    assert bench.form_bytes(n, z, "f32", lay) == 4 * (n + 1) + 5 * z + 8 * n + 4 * n
+    assert bench.form_bytes(n, z, "f64", dict(lay, scaled=False)) is None
+    assert bench.form_bytes(n, z, "f64", None) is None
+    assert bench.spmv_label((16, 0, 18, 1), "f64", lay) == (
+        "segmented SpMV iteration, slabs of 2^18 columns (degree-scaled form: entries stored as "
+        "counts): k_spmv<double,16,raw,uint8> + k_fix_raw<double> + k_seg_combine<double> + "
+        "k_sum_blocks")
+
+
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120, cwd=ROOT)

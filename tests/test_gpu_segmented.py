@@ -238,3 +238,81 @@ def test_segmented_structured_more(case, dtype):
         col, val = col[keep], val[keep]
         slabs = [15]
     check(n, rp, col, val, dtype, slabs)
+
+
+# ------------------------------------------------------- degree-scaled form
+# With K2's d_out as the weights, a relabelled, segmented run stores each
+# entry as its integer count and gathers r_i / d_out[i] (A = D^-1 C, Sec.
+# IV.C); any entry that is not count / weight with a count in [1, 255] keeps
+# the values.  Either way the ranks meet the oracle's tolerance.
+def scaled_run(AT, n, dtype, slab, w, scaled, seed=7):
+    pp.set_k3_config(8, 0, slab, scaled)
+    r = pp.init_r(n, seed, dtype)
+    sums = pp.pagerank(AT, r, iters=20, c=C, weights=w)
+    return host(r), host(sums), pp.k3_last_layout()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("scale", [12, 16])
+def test_scaled_form_kronecker(scale, dtype):
+    f = kron_matrix(scale)
+    trp, tcol, tval = oracle.transpose_csr(f.n, f.A_rp, f.A_col, f.A_val)
+    AT = pp.CSR.from_arrays(f.n, trp, tcol, tval, dtype)
+    want, wsums = oracle.pagerank(f.n, f.A_rp, f.A_col, f.A_val, oracle.init_r(f.n, 7), 20, C)
+    w = torch.as_tensor(f.d_out).to(torch.int32).cuda()
+    for slab in (scale - 4, scale - 2):
+        got_s, sums_s, lay_s = scaled_run(AT, f.n, dtype, slab, w, 1)
+        assert lay_s == {"relabelled": True, "segmented": True, "scaled": True}, slab
+        got_v, sums_v, lay_v = scaled_run(AT, f.n, dtype, slab, w, 0)
+        assert lay_v == {"relabelled": True, "segmented": True, "scaled": False}, slab
+        for got, sums in ((got_s, sums_s), (got_v, sums_v)):
+            assert rel_l1(got, want) <= TOL[dtype], (slab, rel_l1(got, want))
+            assert np.abs(sums / wsums - 1).max() <= TOL[dtype], slab
+        assert rel_l1(got_s, got_v) <= TOL[dtype]
+
+
+def heavy_edge_matrix(scale, copies):
+    """K2 (oracle) of a Kronecker edge list plus `copies` repeats of one
+    edge into an ordinary column, so one entry has count >= copies."""
+    ou, ov = oracle.generate(okron(spec(scale)))
+    n = 1 << scale
+    indeg = np.bincount(ov, minlength=n)
+    v0 = int(np.flatnonzero((indeg >= 4) & (indeg < indeg.max() // 4))[0])
+    u0 = int(ou[0])
+    ou = np.concatenate([ou, np.full(copies, u0, np.int64)])
+    ov = np.concatenate([ov, np.full(copies, v0, np.int64)])
+    ous, ovs = oracle.sort(scale, ou, ov)
+    return oracle.filter(scale, ous, ovs), u0, v0
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["count-over-255", "value-off-by-ulp", "wrong-weights"])
+def test_scaled_form_falls_back_to_values(case, dtype):
+    scale = 12
+    if case == "count-over-255":
+        f, u0, v0 = heavy_edge_matrix(scale, 300)
+        k = np.flatnonzero(f.A_col[f.A_rp[u0]:f.A_rp[u0 + 1]] == v0)
+        assert k.size == 1 and round(f.A_val[f.A_rp[u0] + k[0]] * f.d_out[u0]) >= 300
+        rp, col, val, d = f.A_rp, f.A_col, f.A_val, f.d_out
+    else:
+        f = kron_matrix(scale)
+        rp, col, val, d = f.A_rp, f.A_col, f.A_val.copy(), f.d_out
+        if case == "value-off-by-ulp":
+            j = len(val) // 3
+            val[j] = np.nextafter(val[j], 1.0) if dtype == "f64" else \
+                float(np.nextafter(np.float32(val[j]), np.float32(1.0)))
+        else:
+            d = d + 1
+    n = 1 << scale
+    trp, tcol, tval = oracle.transpose_csr(n, rp, col, val)
+    AT = pp.CSR.from_arrays(n, trp, tcol, tval, dtype)
+    want, wsums = oracle.pagerank(n, rp, col, val, oracle.init_r(n, 7), 20, C)
+    w = torch.as_tensor(d).to(torch.int32).cuda()
+    got, sums, lay = scaled_run(AT, n, dtype, scale - 3, w, 1)
+    assert lay == {"relabelled": True, "segmented": True, "scaled": False}
+    assert rel_l1(got, want) <= TOL[dtype], rel_l1(got, want)
+    assert np.abs(sums / wsums - 1).max() <= TOL[dtype]
+    # The same weights with the form off give the same ranks bit for bit.
+    got_v, sums_v, _ = scaled_run(AT, n, dtype, scale - 3, w, 0)
+    assert got.tobytes() == got_v.tobytes() and sums.tobytes() == sums_v.tobytes()
+
