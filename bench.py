@@ -317,8 +317,17 @@ def graphs_form(args, pp, workloads, torch):
         err = max(float((a.double() - r.double()).abs().sum() / r.double().abs().sum())
                   for a, (_, r, _, _) in zip(r_persist, gb.items))
     t = min(ts)
+    # Algorithmic bytes as for one SpMV per graph and iteration (8Z + 12N + 4
+    # in FP32); each graph's CSR is read from HBM once and from L2 in its
+    # later iterations, r and y never leave LDS.
+    alg = sum(spmv_bytes(AT.n, AT.nnz, "f32") for AT, *_ in gb.items) * args.iters
+    once = sum(4 * (AT.n + 1) + 8 * AT.nnz for AT, *_ in gb.items)
+    roof = {"bound": "hbm", "kernel": "k_graphs<float> (one persistent launch)",
+            "achieved": alg / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": alg / t / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": alg,
+            "csr_bytes_read_once": once, "csr_once_GBps": once / t / 1e9}
     return {"workload": f"kron-batch{args.ngraphs}-s8to14-f32", "graphs": args.ngraphs,
-            "edges_total": edges, "nnz_total": nnz, "k3_ms": t * 1e3,
+            "edges_total": edges, "nnz_total": nnz, "k3_ms": t * 1e3, "roofline": roof,
             "k3_ms_mean": sum(ts) / len(ts) * 1e3,
             "edges_per_s": args.iters * edges / t,
             "per_graph_calls_ms": t_calls * 1e3,

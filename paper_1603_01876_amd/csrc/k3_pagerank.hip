@@ -691,34 +691,53 @@ __global__ __launch_bounds__(256) void k_relabel_maps(const uint64_t *__restrict
   }
 }
 
-// Cache in front of lab[] for the heaviest vertices: one 16-byte slot per
-// hash bucket holding (vertex, new label, weight) of the heaviest vertex
-// hashed there (vertex -1 when empty).  A lookup reads the slot and falls
-// back to lab[u] when the slot holds another vertex; results never depend
-// on what the cache holds.
+// Cache in front of lab[] for the heaviest vertices: one 8-byte slot per
+// hash bucket for the heaviest vertex hashed there, packing (tag, new
+// label, weight).  hot_mix is a bijection of 32-bit words, so the bucket
+// (its low lg bits) and the tag (the other 32 - lg bits) identify the
+// vertex; the new label takes nbits and the weight the remaining bits, and
+// weight 0 marks an empty slot (the cache holds weights >= 8 only).  A
+// lookup reads the slot and falls back to lab[u] when the slot holds
+// another vertex; results never depend on what the cache holds.  Packing
+// doubles the vertices a 2 MiB table (one XCD's L2 half) holds.
 struct Hot2 {
-  const int4 *tab;
+  const uint64_t *tab;
   uint32_t mask;
+  int32_t lg, nbits;
 };
 
 __device__ __forceinline__ int2 hot2_get(Hot2 h, const int2 *__restrict__ lab, int32_t u) {
-  const int4 e = h.tab[hot_mix(uint32_t(u)) & h.mask];
-  return e.x == u ? make_int2(e.y, e.z) : lab[u];
+  const uint32_t m = hot_mix(uint32_t(u));
+  const uint64_t e = h.tab[m & h.mask];
+  const int tb = 32 - h.lg;
+  const uint64_t rest = e >> tb;
+  const uint32_t wgt = uint32_t(rest >> h.nbits);
+  if (wgt != 0u && uint32_t(e & ((1ull << tb) - 1ull)) == (m >> h.lg))
+    return make_int2(int32_t(rest & ((1ull << h.nbits) - 1ull)), int32_t(wgt));
+  return lab[u];
 }
 
-// Winners (weight << 32 | u, 0 = empty) -> slots.
+// Winners (weight << 32 | u, 0 = empty) -> packed slots; a winner whose
+// weight does not fit the slot's weight bits leaves the slot empty.
 __global__ __launch_bounds__(256) void k_hot2_fill(const uint64_t *__restrict__ win,
                                                    const int2 *__restrict__ lab,
-                                                   int4 *__restrict__ tab, uint32_t slots) {
+                                                   uint64_t *__restrict__ tab, int32_t lg,
+                                                   int32_t nbits) {
+  const uint32_t slots = 1u << lg;
+  const int tb = 32 - lg;
+  const int wbits = 64 - tb - nbits;
   for (uint32_t k = blockIdx.x * 256 + threadIdx.x; k < slots; k += gridDim.x * 256) {
     const uint64_t e = win[k];
-    const int32_t u = int32_t(uint32_t(e));
+    uint64_t slot = 0;
     if (e) {
+      const uint32_t u = uint32_t(e);
       const int2 l = lab[u];
-      tab[k] = make_int4(u, l.x, l.y, 0);
-    } else {
-      tab[k] = make_int4(-1, 0, 0, 0);
+      const uint64_t w = uint64_t(uint32_t(l.y));
+      if (l.y > 0 && (wbits >= 32 || w < (1ull << wbits)))
+        slot = uint64_t(hot_mix(u) >> lg) | (uint64_t(uint32_t(l.x)) << tb) |
+               (w << (tb + nbits));
     }
+    tab[k] = slot;
   }
 }
 
@@ -1457,7 +1476,7 @@ struct Layout {
   size_t radix_bytes;
   int32_t *order, *wnew, *rp2, *col2;
   int2 *lab;
-  int4 *hot;
+  uint64_t *hot;
   uint32_t *bad;
   V *val2, *x2;
   int64_t *total;
@@ -1505,7 +1524,7 @@ Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs, size_t *byte
   L.order = c.take<int32_t>(size_t(n));
   L.lab = c.take<int2>(size_t(n));
   L.wnew = c.take<int32_t>(size_t(n));
-  L.hot = c.take<int4>(size_t(1) << hot_log2(n));
+  L.hot = c.take<uint64_t>(size_t(2) << hot_log2(n));
   L.bad = c.take<uint32_t>(1);
   L.rp2 = c.take<int32_t>(size_t(n + 1));
   {
@@ -1821,12 +1840,13 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
     // Every entry's column goes through lab at random; the heaviest
     // sources' entries are cached in an L2-sized table in front of it (the
     // winners are picked into keys_in, free once rp2 is scanned).
-    const int lg = hot_log2(n);
+    const int lg = hot_log2(n) + 1;
+    const int nbits = n > 1 ? 32 - __builtin_clz(uint32_t(n - 1)) : 1;
     if ((st = hot_select(weights, n32, L.keys_in, lg, s)) != PP_OK) return st;
     hipLaunchKernelGGL(k_hot2_fill, dim3(grid_for(int64_t(1) << lg, 256, 1024)), dim3(256), 0, s,
-                       L.keys_in, L.lab, L.hot, 1u << lg);
+                       L.keys_in, L.lab, L.hot, lg, nbits);
     PP_LAUNCHED("k_hot2_fill");
-    hot = Hot2{L.hot, (1u << lg) - 1u};
+    hot = Hot2{L.hot, (1u << lg) - 1u, lg, nbits};
     rp = L.rp2;
     col = L.col2;
     val = L.val2;
