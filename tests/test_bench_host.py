@@ -18,9 +18,9 @@ SUMMARY = os.path.join(ROOT, "profiles", "k3_spmv_kron_s26_f32_counters.md")
 SOURCE = os.path.join(ROOT, "paper_1603_01876_amd", "csrc", "k3_pagerank.hip")
 
 
-def summary_fields():
+def summary_fields(dtype="f32"):
     out = {}
-    for line in open(SUMMARY):
+    for line in open(os.path.join(ROOT, "profiles", f"k3_spmv_kron_s26_{dtype}_counters.md")):
         if ":" in line:
             k, v = line.split(":", 1)
             out[k.strip()] = v.strip()
@@ -35,11 +35,13 @@ def test_spmv_bytes_match_the_pull_form_counts():
         assert bench.spmv_bytes(n, z, "f64") == 12 * z + 20 * n + 4
 
 
-def test_measured_traffic_follows_the_committed_summary():
-    f = summary_fields()
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_measured_traffic_follows_the_committed_summary(dtype):
+    f = summary_fields(dtype)
+    other_dt = "f64" if dtype == "f32" else "f32"
     cfg = tuple(int(x) for x in f["k3_config"].split(","))
     relabel = f["relabel"] == "1"
-    got = bench.measured_traffic(26, "f32", cfg, relabel)
+    got = bench.measured_traffic(26, dtype, cfg, relabel)
     src_sha = hashlib.sha256(open(SOURCE, "rb").read()).hexdigest()
     if f["kernel_source_sha256"] != src_sha:
         assert got is None          # stale summary: no traffic is reported
@@ -50,11 +52,13 @@ def test_measured_traffic_follows_the_committed_summary():
     assert l2["requests_per_s"] == pytest.approx(
         float(f["spmv_l2_read_requests_per_launch"]) / (float(f["spmv_launch_us"]) * 1e-6))
     # another launch configuration, relabelling choice, scale or dtype: none
-    other = (cfg[0], cfg[1], cfg[2] + 1)
-    assert bench.measured_traffic(26, "f32", other, relabel) is None
-    assert bench.measured_traffic(26, "f32", cfg, not relabel) is None
-    assert bench.measured_traffic(25, "f32", cfg, relabel) is None
-    assert bench.measured_traffic(26, "f64", cfg, relabel) is None
+    other = (cfg[0], cfg[1], cfg[2] + 1) + cfg[3:]
+    assert bench.measured_traffic(26, dtype, other, relabel) is None
+    assert bench.measured_traffic(26, dtype, cfg, not relabel) is None
+    assert bench.measured_traffic(25, dtype, cfg, relabel) is None
+    assert bench.measured_traffic(26, other_dt, cfg, relabel) is None
+    scaled_off = cfg[:3] + (0,) + cfg[4:]
+    assert bench.measured_traffic(26, dtype, scaled_off, relabel) is None
 
 
 def test_measured_traffic_ignores_a_summary_of_other_source(tmp_path, monkeypatch):
