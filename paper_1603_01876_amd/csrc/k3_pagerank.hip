@@ -231,6 +231,13 @@ __global__ __launch_bounds__(kThreads) void k_spmv(
       hi = m;
   }
   int32_t ti = lo, tj = d - lo;
+  // Raw mode stages its pairs' partials in LDS and stores them together at
+  // the end (one coalesced store per 64 pairs instead of one per pair).  A
+  // pair is never empty, so when a thread ends the k-th pair it began
+  // itself it has consumed at least k + 1 products: the k-th partial goes
+  // to s_prod[tj0 + k], a product slot this thread has already read.
+  const int32_t tj0 = tj;
+  int32_t nstaged = 0;
 
   Acc acc{}, first{};
   int32_t first_row = -1;
@@ -241,7 +248,8 @@ __global__ __launch_bounds__(kThreads) void k_spmv(
         first_row = ti;
         first = acc;
       } else if constexpr (kRaw) {
-        part[i0 + ti] = Form<V>::part(acc);
+        s_prod[tj0 + nstaged] = Form<V>::part(acc);
+        ++nstaged;
       } else {
         const V yv = Form<V>::finish(acc, c, tk);
         y[i0 + ti] = yv;
@@ -284,6 +292,8 @@ __global__ __launch_bounds__(kThreads) void k_spmv(
   s_pre[tid] = v;
   __syncthreads();
 
+  typename Form<V>::Part first_part{};
+  bool has_first = false;
   if (first_row >= 0) {
     // The first row this thread ends is the row thread tid-1 left open, so
     // its earlier part is that thread's segmented prefix.
@@ -292,7 +302,8 @@ __global__ __launch_bounds__(kThreads) void k_spmv(
     if (R == i0 && mid_row) {
       blk_head[b] = sum;  // row began in an earlier workgroup: completed later
     } else if constexpr (kRaw) {
-      part[R] = Form<V>::part(sum);
+      first_part = Form<V>::part(sum);
+      has_first = true;
     } else {
       const V yv = Form<V>::finish(sum, c, tk);
       y[R] = yv;
@@ -300,7 +311,27 @@ __global__ __launch_bounds__(kThreads) void k_spmv(
     }
   }
   if (tid == kThreads - 1) blk_carry[b] = c1.x < n ? v : Acc{};
-  if constexpr (!kRaw) {
+  if constexpr (kRaw) {
+    // Every completed pair of the tile (local rows [0, na), less a first
+    // row carried in from the previous tile) has its partial in LDS: the
+    // first one a thread ends in s_pre[tid] (free once every thread has read
+    // its neighbour's prefix), the others in the thread's consumed product
+    // slots; s_end, free after the walk, maps each row to its slot.
+    using Part = typename Form<V>::Part;
+    Part *s_first = reinterpret_cast<Part *>(s_pre);
+    __syncthreads();
+    if (has_first) {
+      s_first[tid] = first_part;
+      s_end[first_row] = -(tid + 1);
+    }
+    for (int32_t k = 0; k < nstaged; ++k) s_end[first_row + 1 + k] = tj0 + k;
+    __syncthreads();
+    for (int32_t r = tid; r < na; r += kThreads) {
+      if (r == 0 && mid_row) continue;
+      const int32_t loc = s_end[r];
+      part[i0 + r] = loc >= 0 ? Part(s_prod[loc]) : s_first[-loc - 1];
+    }
+  } else {
     const double bs = block_sum256(ysum, s_red);
     if (tid == 0) blk_ysum[b] = bs;
   }
