@@ -748,6 +748,39 @@ __device__ __forceinline__ int2 hot2_get(Hot2 h, const int2 *__restrict__ lab, i
   return lab[u];
 }
 
+// kN lookups at once, every read issued before any is used: first all slot
+// reads, then all fallback reads (a hit reads lab[0] instead, so the read is
+// unconditional and the hit lanes of a wave share one line).  A read under
+// a per-lane condition would be waited for before the next one is issued.
+template <int kN>
+__device__ __forceinline__ void hot2_get_n(Hot2 h, const int2 *__restrict__ lab,
+                                           const int32_t (&u)[kN], int2 (&out)[kN]) {
+  const int tb = 32 - h.lg;
+  uint64_t e[kN];
+  uint32_t m[kN];
+#pragma unroll
+  for (int i = 0; i < kN; ++i) {
+    m[i] = hot_mix(uint32_t(u[i]));
+    e[i] = h.tab[m[i] & h.mask];
+  }
+  bool hit[kN];
+#pragma unroll
+  for (int i = 0; i < kN; ++i) {
+    const uint32_t wgt = uint32_t((e[i] >> tb) >> h.nbits);
+    hit[i] = wgt != 0u && uint32_t(e[i] & ((1ull << tb) - 1ull)) == (m[i] >> h.lg);
+  }
+  int2 fb[kN];
+#pragma unroll
+  for (int i = 0; i < kN; ++i) fb[i] = lab[hit[i] ? 0 : u[i]];
+#pragma unroll
+  for (int i = 0; i < kN; ++i) {
+    const uint64_t rest = e[i] >> tb;
+    out[i] = hit[i] ? make_int2(int32_t(rest & ((1ull << h.nbits) - 1ull)),
+                                int32_t(uint32_t(rest >> h.nbits)))
+                    : fb[i];
+  }
+}
+
 // Winners (weight << 32 | u, 0 = empty) -> packed slots; a winner whose
 // weight does not fit the slot's weight bits leaves the slot empty.
 __global__ __launch_bounds__(256) void k_hot2_fill(const uint64_t *__restrict__ win,
@@ -970,9 +1003,13 @@ __global__ __launch_bounds__(kThreads) void k_seg_tile(
     const bool valid = e < nz;
     rr[r] = valid ? row_of(s_end, na, e) : 0;
     if constexpr (kRelabel) {
+      // Unconditional reads (entry 0 for lanes past the end), so that they
+      // are all in flight together.
       const int32_t src = valid ? j0 + e + s_src[rr[r]] : 0;
-      cc[r] = valid ? rs.col0[src] : 0;
-      v0[r] = valid ? static_cast<const V *>(rs.val0)[src] : V(0);
+      const int32_t c0v = rs.col0[src];
+      const V v0v = static_cast<const V *>(rs.val0)[src];
+      cc[r] = valid ? c0v : 0;
+      v0[r] = valid ? v0v : V(0);
     } else {
       cc[r] = valid ? col[j0 + e] : 0;
       if constexpr (kScatter) vv[r] = valid ? val[j0 + e] : E(0);
@@ -980,11 +1017,13 @@ __global__ __launch_bounds__(kThreads) void k_seg_tile(
   }
   if constexpr (kRelabel) {
     bool bad = false;
+    int2 lk[kSegPer];
+    hot2_get_n<kSegPer>(rs.hot, rs.lab, cc, lk);   // lanes past the end look up column 0
 #pragma unroll
     for (int r = 0; r < kSegPer; ++r) {
       vv[r] = E(0);
       if (w * (kSegTile / kWaves) + r * kWave + lane < nz) {
-        const int2 l = hot2_get(rs.hot, rs.lab, cc[r]);
+        const int2 l = lk[r];
         cc[r] = l.x;
         if constexpr (kCount) {
           const double wd = double(l.y);
@@ -1293,12 +1332,14 @@ __global__ __launch_bounds__(kThreads) void k_seg_combine(
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int32_t q = k * kThreads + tid;
-      pi[k] = q < np ? pidx[j0 + q] : 0;
-      ro[k] = q <= nr ? rpp[R0 + q] : 0;
+      // Indices clamped into range, so every load is issued unconditionally
+      // (a load under a per-lane condition is waited for before the next).
+      pi[k] = pidx[np > 0 ? j0 + (q < np ? q : np - 1) : 0];
+      ro[k] = rpp[R0 + (q <= nr ? q : nr)];
     }
     {
       const int32_t q = kPer * kThreads + tid;
-      ro[kPer] = q <= nr ? rpp[R0 + q] : 0;
+      ro[kPer] = rpp[R0 + (q <= nr ? q : nr)];
     }
 #pragma unroll
     for (int k = 0; k <= kPer; ++k) {
@@ -1307,10 +1348,7 @@ __global__ __launch_bounds__(kThreads) void k_seg_combine(
     }
     Part pa[kPer];
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const int32_t q = k * kThreads + tid;
-      if (q < np) pa[k] = part[pi[k]];
-    }
+    for (int k = 0; k < kPer; ++k) pa[k] = part[pi[k]];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int32_t q = k * kThreads + tid;
