@@ -38,7 +38,8 @@ typedef enum {
   PP_EINVAL = 1,     /* invalid argument or input that violates a precondition */
   PP_ERANGE = 2,     /* size beyond the int32 index range or scale > 30 */
   PP_EWORKSPACE = 3, /* workspace NULL or smaller than pp_workspace_bytes() */
-  PP_EHIP = 4        /* HIP runtime or launch failure */
+  PP_EHIP = 4,       /* HIP runtime or launch failure */
+  PP_EINTERNAL = 5   /* a device-side consistency check of the library failed (a library bug) */
 } pp_status;
 
 typedef enum {

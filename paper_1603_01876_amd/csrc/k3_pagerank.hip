@@ -1235,30 +1235,12 @@ __global__ __launch_bounds__(256) void k_seg_cont(const int32_t *__restrict__ rp
   }
 }
 
-// Row-major order of the pairs (pidx) for the combine.  pcount[row] counts
-// a row's pairs.  The pairs are stored slab by slab, rows ascending inside
-// a slab, and a row has at most one pair per slab; so appending each
-// slab's pairs to their rows' runs, one launch per slab in slab order,
-// lists every row's pairs in slab order, and inside a launch every row's
-// cursor has one writer.
+// Per-row pair counts (pcount[row], scanned into rpp afterwards).
 __global__ __launch_bounds__(256) void k_pair_count(const int32_t *__restrict__ pair_row, int64_t P,
                                                     uint32_t *__restrict__ pcount) {
   for (int64_t p = blockIdx.x * int64_t(256) + threadIdx.x; p < P; p += int64_t(gridDim.x) * 256)
     atomicAdd(pcount + pair_row[p], 1u);
 }
-
-__global__ __launch_bounds__(256) void k_pair_place(const int32_t *__restrict__ pair_row, int64_t p0,
-                                                    int64_t p1, int32_t *__restrict__ cursor,
-                                                    int32_t *__restrict__ pidx) {
-  for (int64_t p = p0 + blockIdx.x * int64_t(256) + threadIdx.x; p < p1;
-       p += int64_t(gridDim.x) * 256) {
-    const int32_t r = pair_row[p];
-    const int32_t q = cursor[r];
-    pidx[q] = int32_t(p);
-    cursor[r] = q + 1;
-  }
-}
-
 // Completes pairs that span SpMV workgroups (raw accumulators, no sum).
 template <typename V>
 __global__ __launch_bounds__(256) void k_fix_raw(typename Form<V>::Part *__restrict__ part,
@@ -1298,6 +1280,135 @@ __global__ __launch_bounds__(256) void k_comb_bounds(const int32_t *__restrict__
     }
     const int32_t R = b == nblk ? n : lo;
     cstart[b] = make_int2(R, rpp[R]);
+  }
+}
+
+// First pair of slab d whose row is >= R.  The pairs are stored slab by
+// slab and, inside a slab, build tile by tile (poff[t * ns + d] = first
+// pair of tile t in slab d), rows ascending.  Row R's first merge item lies
+// in build tile t = (R + rp[R]) / kSegTile; pairs of rows >= R start in
+// tiles >= t and pairs of earlier rows in tiles <= t, so the answer is
+// found by a binary search of tile t's run alone.
+__device__ __forceinline__ int64_t slab_bound(const int32_t *__restrict__ pair_row,
+                                              const uint32_t *__restrict__ poff,
+                                              const int64_t *__restrict__ slab_start,
+                                              const int32_t *__restrict__ rp, int32_t n,
+                                              int32_t ntiles, int32_t ns, int32_t d, int32_t R) {
+  if (R >= n) return slab_start[d + 1];
+  const int64_t t = (int64_t(R) + rp[R]) / kSegTile;
+  int64_t lo = poff[t * ns + d];
+  int64_t hi = t + 1 < ntiles ? int64_t(poff[(t + 1) * ns + d]) : slab_start[d + 1];
+  while (lo < hi) {
+    const int64_t m = (lo + hi) >> 1;
+    if (pair_row[m] < R)
+      lo = m + 1;
+    else
+      hi = m;
+  }
+  return lo;
+}
+
+// lo[b * ns + d] = first pair of slab d whose row is >= the first row of
+// combine block b (b <= nblk; block nblk starts at row n).
+__global__ __launch_bounds__(256) void k_pair_bounds(const int32_t *__restrict__ pair_row,
+                                                     const uint32_t *__restrict__ poff,
+                                                     const int64_t *__restrict__ slab_start,
+                                                     const int32_t *__restrict__ rp, int32_t n,
+                                                     int32_t ntiles, int32_t ns, int32_t nblk,
+                                                     const int2 *__restrict__ cstart,
+                                                     int32_t *__restrict__ lo) {
+  const int64_t total = (int64_t(nblk) + 1) * ns;
+  for (int64_t k = blockIdx.x * int64_t(256) + threadIdx.x; k < total;
+       k += int64_t(gridDim.x) * 256) {
+    const int32_t b = int32_t(k / ns), d = int32_t(k - int64_t(b) * ns);
+    lo[k] = int32_t(slab_bound(pair_row, poff, slab_start, rp, n, ntiles, ns, d, cstart[b].x));
+  }
+}
+
+// Row-major order of the pairs (pidx) for the combine: each row's pairs,
+// in slab order, at rpp[row] ...  One workgroup per combine block (rows
+// [R0, R1), at most kCap rows plus pairs); its pairs in slab d are
+// [lo[b][d], lo[b + 1][d]) (rows ascending, each row at most once), taken
+// 32 slabs at a time.  Every pair sets its slab's bit in its row's word;
+// then its rank inside the row is the row's pairs in earlier windows plus
+// the set bits below its own.  OR commutes, so the result does not depend
+// on the order of the updates.  bad is set (and nothing stored) if a
+// block's runs do not add up to its pair count.
+__global__ __launch_bounds__(kThreads) void k_pair_index(
+    const int32_t *__restrict__ pair_row, const int32_t *__restrict__ lo_tab, int32_t ns,
+    const int2 *__restrict__ cstart, const int32_t *__restrict__ rpp, int32_t *__restrict__ pidx,
+    uint32_t *__restrict__ bad) {
+  constexpr int kCap = kCombItems + kMaxSlabs;
+  __shared__ uint32_t s_bits[kCap];
+  __shared__ uint16_t s_cum[kCap], s_off[kCap], s_row[kCap];
+  __shared__ int32_t s_lo[kMaxSlabs];
+  __shared__ int32_t s_base[kMaxSlabs + 1];
+  __shared__ uint32_t s_scan[4];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int2 c0 = cstart[b], c1 = cstart[b + 1];
+  const int32_t R0 = c0.x, nr = c1.x - c0.x, j0 = c0.y, np = c1.y - c0.y;
+  uint32_t cnt = 0;
+  if (tid < ns) {
+    const int32_t lo = lo_tab[int64_t(b) * ns + tid];
+    s_lo[tid] = lo;
+    cnt = uint32_t(lo_tab[int64_t(b + 1) * ns + tid] - lo);
+  }
+  uint32_t all;
+  const uint32_t base = block_exscan256(cnt, s_scan, &all);
+  if (tid < ns) s_base[tid] = int32_t(base);
+  if (tid == 0) s_base[ns] = int32_t(all);
+  if (all != uint32_t(np) || nr + np > kCap) {
+    if (tid == 0) atomicOr(bad, 1u);
+    return;   // uniform: every thread sees the same all, np and nr
+  }
+  for (int32_t r = tid; r < nr; r += kThreads) {
+    s_bits[r] = 0u;
+    s_cum[r] = 0;
+    s_off[r] = uint16_t(rpp[R0 + r] - j0);
+  }
+  __syncthreads();
+  // Slab d of item i: s_base[d] <= i < s_base[d + 1], d in [w0, w1).
+  auto slab_of = [&](int32_t i, int32_t w0, int32_t w1) {
+    int32_t lo = w0, hi = w1;
+    while (hi - lo > 1) {
+      const int32_t m = (lo + hi) >> 1;
+      if (s_base[m] <= i)
+        lo = m;
+      else
+        hi = m;
+    }
+    return lo;
+  };
+  for (int32_t w0 = 0; w0 < ns; w0 += 32) {
+    const int32_t w1 = w0 + 32 < ns ? w0 + 32 : ns;
+    const int32_t i0 = s_base[w0], i1 = s_base[w1];
+    if (i0 == i1) continue;   // uniform
+    for (int32_t i = i0 + tid; i < i1; i += kThreads) {
+      const int32_t d = slab_of(i, w0, w1);
+      const int32_t r = pair_row[s_lo[d] + (i - s_base[d])] - R0;
+      const bool ok = r >= 0 && r < nr;
+      if (ok) atomicOr(&s_bits[r], 1u << (d - w0));
+      else atomicOr(bad, 1u);
+      s_row[i] = uint16_t(ok ? r : 0xFFFF);
+    }
+    __syncthreads();
+    for (int32_t i = i0 + tid; i < i1; i += kThreads) {
+      const int32_t r = s_row[i];
+      if (r == 0xFFFF) continue;
+      const int32_t d = slab_of(i, w0, w1);
+      const uint32_t bit = 1u << (d - w0);
+      const int32_t dst = int32_t(s_off[r]) + s_cum[r] + __popc(s_bits[r] & (bit - 1u));
+      if (dst < np)
+        pidx[j0 + dst] = s_lo[d] + (i - s_base[d]);
+      else
+        atomicOr(bad, 1u);
+    }
+    __syncthreads();
+    for (int32_t r = tid; r < nr; r += kThreads) {
+      s_cum[r] = uint16_t(s_cum[r] + __popc(s_bits[r]));
+      s_bits[r] = 0u;
+    }
+    __syncthreads();
   }
 }
 
@@ -1812,8 +1923,9 @@ pp_status build_segments(const Layout<V> &L, const int32_t *rp, int32_t *col, V 
   si.ns = ns;
   si.P = P;
 
-  // Row-major index of the pairs for the combine (see k_pair_place): the
-  // row cursors live in the relabelling's key buffer, free by now.
+  // Row-major index of the pairs for the combine: per-row pair counts,
+  // their scan (rpp), the combine blocks, then one workgroup per block
+  // places the block's pairs (k_pair_index).
   st = fill_i32(L.rpp, n + 1, 0, s);
   if (st != PP_OK) return st;
   hipLaunchKernelGGL(k_pair_count, dim3(grid_for(P, 256, 16384)), dim3(256), 0, s, L.pair_row, P,
@@ -1822,19 +1934,23 @@ pp_status build_segments(const Layout<V> &L, const int32_t *rp, int32_t *col, V 
   st = exscan_u32(reinterpret_cast<uint32_t *>(L.rpp), reinterpret_cast<uint32_t *>(L.rpp), n + 1,
                   L.seg_scan, nullptr, s);
   if (st != PP_OK) return st;
-  int32_t *cursor = reinterpret_cast<int32_t *>(L.keys_out);
-  if ((st = copy_bytes(cursor, L.rpp, size_t(n + 1) * 4, s)) != PP_OK) return st;
-  for (int32_t d = 0; d < ns; ++d) {
-    const int64_t p0 = info[1 + d], p1 = info[2 + d];
-    if (p1 > p0)
-      hipLaunchKernelGGL(k_pair_place, dim3(grid_for(p1 - p0, 256, 8192)), dim3(256), 0, s,
-                         L.pair_row, p0, p1, cursor, L.pidx);
-  }
-  PP_LAUNCHED("k_pair_place");
   const int32_t ncomb = int32_t((n + P + kCombItems - 1) / kCombItems);
   hipLaunchKernelGGL(k_comb_bounds, dim3(grid_for(int64_t(ncomb) + 1, 256, 4096)), dim3(256), 0, s,
                      L.rpp, n32, ncomb, L.cstart);
-  PP_LAUNCHED("k_comb_bounds");
+  if ((st = fill_i32(reinterpret_cast<int32_t *>(L.bad), 1, 0, s)) != PP_OK) return st;
+  // The bounds table takes the entry offsets' buffer (dead after the
+  // scatter pass; kMaxSlabs * ntiles >= (ncomb + 1) * ns).
+  int32_t *lo_tab = reinterpret_cast<int32_t *>(L.seg_cnt);
+  hipLaunchKernelGGL(k_pair_bounds, dim3(grid_for((int64_t(ncomb) + 1) * ns, 256, 16384)),
+                     dim3(256), 0, s, L.pair_row, L.seg_pcnt, L.info + 1, rp, n32, ntiles, ns,
+                     ncomb, L.cstart, lo_tab);
+  hipLaunchKernelGGL(k_pair_index, dim3(ncomb), dim3(kThreads), 0, s, L.pair_row, lo_tab, ns,
+                     L.cstart, L.rpp, L.pidx, L.bad);
+  PP_LAUNCHED("k_comb_bounds/k_pair_bounds/k_pair_index");
+  uint32_t bad = 0;
+  PP_HIP(hipMemcpyAsync(&bad, L.bad, sizeof(bad), hipMemcpyDeviceToHost, s));
+  PP_HIP(hipStreamSynchronize(s));
+  if (bad) return fail(PP_EINTERNAL, "k_pair_index: a combine block's pairs do not match its count");
   *out = si;
   return PP_OK;
 }

@@ -83,6 +83,7 @@ const char *pp_strerror(pp_status st) {
     case PP_ERANGE: return "size out of range";
     case PP_EWORKSPACE: return "workspace missing or too small";
     case PP_EHIP: return "HIP runtime error";
+    case PP_EINTERNAL: return "internal consistency check failed";
   }
   return "unknown status";
 }

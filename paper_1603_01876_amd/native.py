@@ -17,7 +17,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpp.so")
 
-PP_OK, PP_EINVAL, PP_ERANGE, PP_EWORKSPACE, PP_EHIP = range(5)
+PP_OK, PP_EINVAL, PP_ERANGE, PP_EWORKSPACE, PP_EHIP, PP_EINTERNAL = range(6)
 F64, F32 = 0, 1
 K0, K1, K2, K3, K3_GRAPHS, K2_ROWFORM, TSV_FORMAT, TSV_PARSE = range(8)
 

@@ -43,6 +43,7 @@ def test_strerror():
     L = native.lib()
     assert L.pp_strerror(0) == b"success"
     assert L.pp_strerror(3).startswith(b"workspace")
+    assert L.pp_strerror(5).startswith(b"internal")
 
 
 def test_workspace_sizes():
