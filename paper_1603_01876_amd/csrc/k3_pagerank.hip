@@ -1235,12 +1235,6 @@ __global__ __launch_bounds__(256) void k_seg_cont(const int32_t *__restrict__ rp
   }
 }
 
-// Per-row pair counts (pcount[row], scanned into rpp afterwards).
-__global__ __launch_bounds__(256) void k_pair_count(const int32_t *__restrict__ pair_row, int64_t P,
-                                                    uint32_t *__restrict__ pcount) {
-  for (int64_t p = blockIdx.x * int64_t(256) + threadIdx.x; p < P; p += int64_t(gridDim.x) * 256)
-    atomicAdd(pcount + pair_row[p], 1u);
-}
 // Completes pairs that span SpMV workgroups (raw accumulators, no sum).
 template <typename V>
 __global__ __launch_bounds__(256) void k_fix_raw(typename Form<V>::Part *__restrict__ part,
@@ -1309,20 +1303,89 @@ __device__ __forceinline__ int64_t slab_bound(const int32_t *__restrict__ pair_r
 }
 
 // lo[b * ns + d] = first pair of slab d whose row is >= the first row of
-// combine block b (b <= nblk; block nblk starts at row n).
+// block b, b <= nblk: row min(n, b * row_step) for row blocks of a fixed
+// height, cstart[b].x for combine blocks (row_step 0; block nblk starts at
+// row n).
 __global__ __launch_bounds__(256) void k_pair_bounds(const int32_t *__restrict__ pair_row,
                                                      const uint32_t *__restrict__ poff,
                                                      const int64_t *__restrict__ slab_start,
                                                      const int32_t *__restrict__ rp, int32_t n,
                                                      int32_t ntiles, int32_t ns, int32_t nblk,
+                                                     int32_t row_step,
                                                      const int2 *__restrict__ cstart,
                                                      int32_t *__restrict__ lo) {
   const int64_t total = (int64_t(nblk) + 1) * ns;
   for (int64_t k = blockIdx.x * int64_t(256) + threadIdx.x; k < total;
        k += int64_t(gridDim.x) * 256) {
     const int32_t b = int32_t(k / ns), d = int32_t(k - int64_t(b) * ns);
-    lo[k] = int32_t(slab_bound(pair_row, poff, slab_start, rp, n, ntiles, ns, d, cstart[b].x));
+    const int64_t R = row_step > 0 ? int64_t(b) * row_step : int64_t(cstart[b].x);
+    lo[k] = int32_t(slab_bound(pair_row, poff, slab_start, rp, n, ntiles, ns, d,
+                               R < n ? int32_t(R) : n));
   }
+}
+
+// Slab d of item i of a block whose slab runs start at s_base[0 .. ns]:
+// s_base[d] <= i < s_base[d + 1], searched in [lo, hi).
+__device__ __forceinline__ int32_t run_of(const int32_t *s_base, int32_t i, int32_t lo,
+                                          int32_t hi) {
+  while (hi - lo > 1) {
+    const int32_t m = (lo + hi) >> 1;
+    if (s_base[m] <= i)
+      lo = m;
+    else
+      hi = m;
+  }
+  return lo;
+}
+
+// Pairs per row, for rows in blocks of kCountRows: the block's pairs in
+// slab d are [lo[b][d], lo[b + 1][d]), each adds one to its row's counter
+// in LDS (integer adds, so the order does not matter), and the block then
+// stores its rows' counts in order (pcount, scanned into rpp afterwards).
+constexpr int kCountRows = 4096;
+constexpr int kBatch = 8;
+__global__ __launch_bounds__(kThreads) void k_pair_count(const int32_t *__restrict__ pair_row,
+                                                         const int32_t *__restrict__ lo_tab,
+                                                         int32_t ns, int32_t n,
+                                                         uint32_t *__restrict__ pcount) {
+  __shared__ uint32_t s_cnt[kCountRows];
+  __shared__ int32_t s_lo[kMaxSlabs];
+  __shared__ int32_t s_base[kMaxSlabs + 1];
+  __shared__ uint32_t s_scan[4];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int32_t R0 = b * kCountRows;
+  const int32_t nr = n - R0 < kCountRows ? n - R0 : kCountRows;
+  uint32_t cnt = 0;
+  if (tid < ns) {
+    const int32_t lo = lo_tab[int64_t(b) * ns + tid];
+    s_lo[tid] = lo;
+    cnt = uint32_t(lo_tab[int64_t(b + 1) * ns + tid] - lo);
+  }
+  uint32_t all;
+  const uint32_t base = block_exscan256(cnt, s_scan, &all);
+  if (tid < ns) s_base[tid] = int32_t(base);
+  if (tid == 0) s_base[ns] = int32_t(all);
+  for (int32_t r = tid; r < kCountRows; r += kThreads) s_cnt[r] = 0u;
+  __syncthreads();
+  // kBatch items per thread at a time, every read issued before any is
+  // used (items past the end read pair 0 and are dropped).
+  for (int32_t i0 = 0; i0 < int32_t(all); i0 += kThreads * kBatch) {
+    int32_t rr[kBatch];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const int32_t i = i0 + k * kThreads + tid;
+      const int32_t d = run_of(s_base, i < int32_t(all) ? i : 0, 0, ns);
+      rr[k] = pair_row[i < int32_t(all) ? s_lo[d] + (i - s_base[d]) : 0];
+    }
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const int32_t i = i0 + k * kThreads + tid;
+      const int32_t r = rr[k] - R0;
+      if (i < int32_t(all) && r >= 0 && r < nr) atomicAdd(&s_cnt[r], 1u);
+    }
+  }
+  __syncthreads();
+  for (int32_t r = tid; r < nr; r += kThreads) pcount[R0 + r] = s_cnt[r];
 }
 
 // Row-major order of the pairs (pidx) for the combine: each row's pairs,
@@ -1367,24 +1430,12 @@ __global__ __launch_bounds__(kThreads) void k_pair_index(
     s_off[r] = uint16_t(rpp[R0 + r] - j0);
   }
   __syncthreads();
-  // Slab d of item i: s_base[d] <= i < s_base[d + 1], d in [w0, w1).
-  auto slab_of = [&](int32_t i, int32_t w0, int32_t w1) {
-    int32_t lo = w0, hi = w1;
-    while (hi - lo > 1) {
-      const int32_t m = (lo + hi) >> 1;
-      if (s_base[m] <= i)
-        lo = m;
-      else
-        hi = m;
-    }
-    return lo;
-  };
   for (int32_t w0 = 0; w0 < ns; w0 += 32) {
     const int32_t w1 = w0 + 32 < ns ? w0 + 32 : ns;
     const int32_t i0 = s_base[w0], i1 = s_base[w1];
     if (i0 == i1) continue;   // uniform
     for (int32_t i = i0 + tid; i < i1; i += kThreads) {
-      const int32_t d = slab_of(i, w0, w1);
+      const int32_t d = run_of(s_base, i, w0, w1);
       const int32_t r = pair_row[s_lo[d] + (i - s_base[d])] - R0;
       const bool ok = r >= 0 && r < nr;
       if (ok) atomicOr(&s_bits[r], 1u << (d - w0));
@@ -1395,7 +1446,7 @@ __global__ __launch_bounds__(kThreads) void k_pair_index(
     for (int32_t i = i0 + tid; i < i1; i += kThreads) {
       const int32_t r = s_row[i];
       if (r == 0xFFFF) continue;
-      const int32_t d = slab_of(i, w0, w1);
+      const int32_t d = run_of(s_base, i, w0, w1);
       const uint32_t bit = 1u << (d - w0);
       const int32_t dst = int32_t(s_off[r]) + s_cum[r] + __popc(s_bits[r] & (bit - 1u));
       if (dst < np)
@@ -1925,12 +1976,18 @@ pp_status build_segments(const Layout<V> &L, const int32_t *rp, int32_t *col, V 
 
   // Row-major index of the pairs for the combine: per-row pair counts,
   // their scan (rpp), the combine blocks, then one workgroup per block
-  // places the block's pairs (k_pair_index).
-  st = fill_i32(L.rpp, n + 1, 0, s);
-  if (st != PP_OK) return st;
-  hipLaunchKernelGGL(k_pair_count, dim3(grid_for(P, 256, 16384)), dim3(256), 0, s, L.pair_row, P,
+  // places the block's pairs (k_pair_index).  The bounds tables take the
+  // entry offsets' buffer, dead after the scatter pass (kMaxSlabs * ntiles
+  // entries, more than (blocks + 1) * ns for either kind of block).
+  int32_t *lo_tab = reinterpret_cast<int32_t *>(L.seg_cnt);
+  const int32_t ncnt = int32_t((n + kCountRows - 1) / kCountRows);
+  if ((st = fill_i32(L.rpp + n, 1, 0, s)) != PP_OK) return st;   // the scan's last element
+  hipLaunchKernelGGL(k_pair_bounds, dim3(grid_for((int64_t(ncnt) + 1) * ns, 256, 16384)),
+                     dim3(256), 0, s, L.pair_row, L.seg_pcnt, L.info + 1, rp, n32, ntiles, ns,
+                     ncnt, kCountRows, nullptr, lo_tab);
+  hipLaunchKernelGGL(k_pair_count, dim3(ncnt), dim3(kThreads), 0, s, L.pair_row, lo_tab, ns, n32,
                      reinterpret_cast<uint32_t *>(L.rpp));
-  PP_LAUNCHED("k_pair_count");
+  PP_LAUNCHED("k_pair_bounds/k_pair_count");
   st = exscan_u32(reinterpret_cast<uint32_t *>(L.rpp), reinterpret_cast<uint32_t *>(L.rpp), n + 1,
                   L.seg_scan, nullptr, s);
   if (st != PP_OK) return st;
@@ -1938,12 +1995,9 @@ pp_status build_segments(const Layout<V> &L, const int32_t *rp, int32_t *col, V 
   hipLaunchKernelGGL(k_comb_bounds, dim3(grid_for(int64_t(ncomb) + 1, 256, 4096)), dim3(256), 0, s,
                      L.rpp, n32, ncomb, L.cstart);
   if ((st = fill_i32(reinterpret_cast<int32_t *>(L.bad), 1, 0, s)) != PP_OK) return st;
-  // The bounds table takes the entry offsets' buffer (dead after the
-  // scatter pass; kMaxSlabs * ntiles >= (ncomb + 1) * ns).
-  int32_t *lo_tab = reinterpret_cast<int32_t *>(L.seg_cnt);
   hipLaunchKernelGGL(k_pair_bounds, dim3(grid_for((int64_t(ncomb) + 1) * ns, 256, 16384)),
                      dim3(256), 0, s, L.pair_row, L.seg_pcnt, L.info + 1, rp, n32, ntiles, ns,
-                     ncomb, L.cstart, lo_tab);
+                     ncomb, 0, L.cstart, lo_tab);
   hipLaunchKernelGGL(k_pair_index, dim3(ncomb), dim3(kThreads), 0, s, L.pair_row, lo_tab, ns,
                      L.cstart, L.rpp, L.pidx, L.bad);
   PP_LAUNCHED("k_comb_bounds/k_pair_bounds/k_pair_index");
