@@ -691,7 +691,8 @@ __global__ __launch_bounds__(256) void k_init_write(int64_t n, int32_t nrhs, uin
 // Rows are permuted with the same map, so x and y stay in one numbering; r
 // is permuted in before the first iteration and out after the last.
 
-// key = bucket << 32 | v, bucket = clz(weight + 1): hotter sorts first.
+// key = bucket << 32 | v, bucket = clz(weight + 1): hotter sorts first;
+// weights <= 0 take bucket 31, after every positive weight.
 __global__ __launch_bounds__(256) void k_order_keys(const int32_t *__restrict__ w, int32_t n,
                                                     uint64_t *__restrict__ keys) {
   for (int32_t v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256) {
@@ -805,8 +806,23 @@ __global__ __launch_bounds__(256) void k_hot2_fill(const uint64_t *__restrict__ 
   }
 }
 
-__global__ void k_set_total(int32_t *rp2, int32_t n, const int64_t *total) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) rp2[n] = int32_t(*total);
+// rp2[n] = the entry count; npos = the vertices of weight > 0, which take
+// the new labels [0, npos): the first sorted key of bucket 31 (found by a
+// binary search of the sorted keys).
+__global__ void k_set_total(int32_t *rp2, int32_t n, const int64_t *total,
+                            const uint64_t *__restrict__ keys, uint32_t *npos) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    rp2[n] = int32_t(*total);
+    int32_t lo = 0, hi = n;
+    while (lo < hi) {
+      const int32_t m = (lo + hi) >> 1;
+      if ((keys[m] >> 32) < 31u)
+        lo = m + 1;
+      else
+        hi = m;
+    }
+    *npos = uint32_t(lo);
+  }
 }
 
 // Entries of the relabelled matrix, one thread per entry q of the new
@@ -927,6 +943,14 @@ __device__ __forceinline__ int32_t row_of(const int32_t *s_end, int32_t na, int3
 }
 
 constexpr int kMaskWords = kMaxSlabs / 32;
+
+// Slab of column c: c >> sbits, the columns from the last slab on all in
+// the last one (a relabelled matrix puts the vertices of weight <= 0, which
+// normally have no entries, past the last slab).
+__device__ __forceinline__ uint32_t slab_of(int32_t c, int32_t sbits, int32_t ns) {
+  const uint32_t d = uint32_t(c) >> sbits;
+  return d < uint32_t(ns) ? d : uint32_t(ns - 1);
+}
 
 // One build tile (kSegTile merge items of the matrix) ordered stably by
 // slab: ranks come from wave ballots in entry order, so inside a slab the
@@ -1052,7 +1076,7 @@ __global__ __launch_bounds__(kThreads) void k_seg_tile(
 #pragma unroll
   for (int r = 0; r < kSegPer; ++r) {
     const bool valid = w * (kSegTile / kWaves) + r * kWave + lane < nz;
-    rank[r] = wave_digit_rank(uint32_t(cc[r]) >> sbits, valid, dbits, wh[w]);
+    rank[r] = wave_digit_rank(slab_of(cc[r], sbits, ns), valid, dbits, wh[w]);
   }
   __syncthreads();
   const int d = tid;   // one slab per thread (ns <= 256 = kThreads)
@@ -1079,7 +1103,7 @@ __global__ __launch_bounds__(kThreads) void k_seg_tile(
   for (int r = 0; r < kSegPer; ++r) {
     const int32_t e = w * (kSegTile / kWaves) + r * kWave + lane;
     if (e < nz) {
-      const uint32_t dg = uint32_t(cc[r]) >> sbits;
+      const uint32_t dg = slab_of(cc[r], sbits, ns);
       const uint32_t slot = s_toff[dg] + wh[w][dg] + rank[r];
       s_col[slot] = cc[r];
       s_end[slot] = rr[r];
@@ -1095,9 +1119,9 @@ __global__ __launch_bounds__(kThreads) void k_seg_tile(
     const int32_t slot = k * kThreads + tid;
     bool f = false;
     if (slot < nz) {
-      const uint32_t dg = uint32_t(s_col[slot]) >> sbits;
+      const uint32_t dg = slab_of(s_col[slot], sbits, ns);
       const int32_t lr = s_end[slot];
-      const bool head = slot == 0 || (uint32_t(s_col[slot - 1]) >> sbits) != dg;
+      const bool head = slot == 0 || slab_of(s_col[slot - 1], sbits, ns) != dg;
       f = head || s_end[slot - 1] != lr;
       if (kScatter && head && lr == 0 && ((s_cont[dg >> 5] >> (dg & 31)) & 1u)) f = false;
     }
@@ -1140,7 +1164,7 @@ __global__ __launch_bounds__(kThreads) void k_seg_tile(
       const int32_t slot = k * kThreads + tid;
       if (slot < nz) {
         const int32_t cv = s_col[slot];
-        const uint32_t dg = uint32_t(cv) >> sbits;
+        const uint32_t dg = slab_of(cv, sbits, ns);
         const int64_t pos = int64_t(s_goff[dg]) + (slot - int32_t(s_toff[dg]));
         seg_col[pos] = cv;
         seg_val[pos] = s_val[slot];
@@ -1708,7 +1732,7 @@ struct Layout {
   int32_t *order, *wnew, *rp2, *col2;
   int2 *lab;
   uint64_t *hot;
-  uint32_t *bad;
+  uint32_t *bad, *npos;
   V *val2, *x2;
   int64_t *total;
   // column segmenting
@@ -1757,6 +1781,7 @@ Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs, size_t *byte
   L.wnew = c.take<int32_t>(size_t(n));
   L.hot = c.take<uint64_t>(size_t(2) << hot_log2(n));
   L.bad = c.take<uint32_t>(1);
+  L.npos = c.take<uint32_t>(1);
   L.rp2 = c.take<int32_t>(size_t(n + 1));
   {
     // One region for the relabelled entries; when the columns are
@@ -1888,7 +1913,8 @@ pp_status col_offsets(uint32_t *cnt, int32_t ntiles, int32_t ns, uint32_t *bsum,
 }
 
 // Segmented layout of the matrix (rp, col, val): see the kernels above.
-// With rl the matrix is the relabelled one, whose entries (col, val) the
+// The slabs cover columns [0, ncols) (columns beyond fall into the last
+// slab).  With rl the matrix is the relabelled one, whose entries (col, val) the
 // count pass writes from rl's source matrix (out->relabelled tells whether
 // it ran).  With scaled (and rl) the count pass first tries the
 // degree-scaled form, writing the entries' counts (as bytes, into val's
@@ -1902,12 +1928,13 @@ pp_status col_offsets(uint32_t *cnt, int32_t ntiles, int32_t ns, uint32_t *bsum,
 // once more.
 template <typename V>
 pp_status build_segments(const Layout<V> &L, const int32_t *rp, int32_t *col, V *val, int64_t n,
-                         int64_t nnz, int slab_log2, const RelabelSrc *rl, bool scaled,
-                         SegInfo *out, hipStream_t s) {
+                         int64_t ncols, int64_t nnz, int slab_log2, const RelabelSrc *rl,
+                         bool scaled, SegInfo *out, hipStream_t s) {
   *out = SegInfo{};
   int sbits = slab_log2;
-  while (((n - 1) >> sbits) + 1 > kMaxSlabs) ++sbits;
-  const int32_t ns = int32_t(((n - 1) >> sbits) + 1);
+  if (ncols < 1) ncols = 1;
+  while (((ncols - 1) >> sbits) + 1 > kMaxSlabs) ++sbits;
+  const int32_t ns = int32_t(((ncols - 1) >> sbits) + 1);
   if (ns < 2 || nnz <= 0) return PP_OK;
   const int32_t dbits = 32 - __builtin_clz(uint32_t(ns - 1));
   const int32_t n32 = int32_t(n);
@@ -2075,7 +2102,8 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
     st = exscan_u32(reinterpret_cast<uint32_t *>(L.rp2), reinterpret_cast<uint32_t *>(L.rp2), n,
                     reinterpret_cast<uint32_t *>(L.keys_in), L.total, s);
     if (st != PP_OK) return st;
-    hipLaunchKernelGGL(k_set_total, dim3(1), dim3(64), 0, s, L.rp2, n32, L.total);
+    hipLaunchKernelGGL(k_set_total, dim3(1), dim3(64), 0, s, L.rp2, n32, L.total, L.keys_out,
+                       L.npos);
     // Every entry's column goes through lab at random; the heaviest
     // sources' entries are cached in an L2-sized table in front of it (the
     // winners are picked into keys_in, free once rp2 is scanned).
@@ -2113,7 +2141,17 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
     // The degree-scaled form needs the relabelled, segmented path and is
     // left out of runs to a convergence test (their pass reads x as ranks).
     const RelabelSrc rl{AT0.row_ptr, AT0.col, L.order, L.lab, AT0.val, hot, L.bad};
-    st = build_segments<V>(L, rp, const_cast<int32_t *>(col), const_cast<V *>(val), n, nnz,
+    // The slabs need only cover the columns that can hold entries: after
+    // relabelling, the vertices of weight > 0 come first (one more stream
+    // synchronisation to read their count).
+    int64_t ncols = n;
+    if (weights) {
+      uint32_t npos = 0;
+      PP_HIP(hipMemcpyAsync(&npos, L.npos, sizeof(npos), hipMemcpyDeviceToHost, s));
+      PP_HIP(hipStreamSynchronize(s));
+      ncols = int64_t(npos);
+    }
+    st = build_segments<V>(L, rp, const_cast<int32_t *>(col), const_cast<V *>(val), n, ncols, nnz,
                            slab_log2, weights ? &rl : nullptr, g_cfg.scaled != 0 && !cv, &si, s);
     if (st != PP_OK) return st;
   }
