@@ -691,35 +691,89 @@ __global__ __launch_bounds__(256) void k_init_write(int64_t n, int32_t nrhs, uin
 // Rows are permuted with the same map, so x and y stay in one numbering; r
 // is permuted in before the first iteration and out after the last.
 
-// key = bucket << 32 | v, bucket = clz(weight + 1): hotter sorts first;
+// Bucket of a weight: clz(weight + 1), so heavier vertices sort first and
 // weights <= 0 take bucket 31, after every positive weight.
-__global__ __launch_bounds__(256) void k_order_keys(const int32_t *__restrict__ w, int32_t n,
-                                                    uint64_t *__restrict__ keys) {
-  for (int32_t v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256) {
-    const int32_t wv = w[v] > 0 ? w[v] : 0;
-    const uint32_t b = uint32_t(__clz(int(uint32_t(wv) + 1u)));
-    keys[v] = (uint64_t(b) << 32) | uint32_t(v);
+__device__ __forceinline__ uint32_t weight_bucket(int32_t w) {
+  const int32_t wv = w > 0 ? w : 0;
+  return uint32_t(__clz(int(uint32_t(wv) + 1u)));
+}
+
+// The new order is a stable counting sort of the vertices by bucket, in
+// blocks of kRelTile vertices; each wave takes a contiguous quarter of its
+// block, so wave-ballot ranks (in vertex order) keep the sort stable.
+constexpr int kRelTile = 4096;
+constexpr int kRelPer = kRelTile / kThreads;
+
+// Bucket counts of each block, bucket-major: hist[c * nblk + b].
+__global__ __launch_bounds__(kThreads) void k_bucket_count(const int32_t *__restrict__ w,
+                                                           int32_t n, int32_t nblk,
+                                                           uint32_t *__restrict__ hist) {
+  constexpr int kWaves = kThreads / kWave;
+  __shared__ uint32_t wh[kWaves][32];
+  const int tid = threadIdx.x, wv = tid / kWave, lane = lane_id();
+  if (tid < kWaves * 32) (&wh[0][0])[tid] = 0u;
+  __syncthreads();
+  const int64_t base = int64_t(blockIdx.x) * kRelTile + wv * (kRelTile / kWaves);
+  int32_t ww[kRelPer];
+#pragma unroll
+  for (int r = 0; r < kRelPer; ++r) {
+    const int64_t v = base + r * kWave + lane;
+    ww[r] = w[v < n ? v : 0];
+  }
+#pragma unroll
+  for (int r = 0; r < kRelPer; ++r)
+    wave_digit_rank(weight_bucket(ww[r]), base + r * kWave + lane < n, 5, wh[wv]);
+  __syncthreads();
+  if (tid < 32) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) t += wh[q][tid];
+    hist[int64_t(tid) * nblk + blockIdx.x] = t;
   }
 }
 
-// order[p] = old label at new position p; lab[old] = (p, weight of old);
-// wnew[p] = weight of the vertex at p; row lengths in the new order (into
-// rp2, scanned afterwards).  Inside a bucket p and old ascend together, so
-// the weight reads and lab writes walk memory in order.
-__global__ __launch_bounds__(256) void k_relabel_maps(const uint64_t *__restrict__ keys,
-                                                      const int32_t *__restrict__ rp,
-                                                      const int32_t *__restrict__ w, int32_t n,
-                                                      int32_t *__restrict__ order,
-                                                      int2 *__restrict__ lab,
-                                                      int32_t *__restrict__ wnew,
-                                                      uint32_t *__restrict__ len2) {
-  for (int32_t p = blockIdx.x * 256 + threadIdx.x; p < n; p += gridDim.x * 256) {
-    const int32_t o = int32_t(keys[p] & 0xFFFFFFFFull);
-    const int32_t wo = w[o];
-    order[p] = o;
-    lab[o] = make_int2(p, wo);
-    wnew[p] = wo;
-    len2[p] = uint32_t(rp[o + 1] - rp[o]);
+// off = the exclusive scan of hist: vertex v of block b goes to p = off[c *
+// nblk + b] + (its rank among the block's vertices of bucket c).  Writes
+// order[p] = v, lab[v] = (p, weight of v), wnew[p] = weight of v and the row
+// lengths in the new order (into rp2, scanned afterwards).  Reads are in
+// vertex order; each block's writes in the new order are one run per bucket.
+__global__ __launch_bounds__(kThreads) void k_bucket_scatter(
+    const int32_t *__restrict__ w, const int32_t *__restrict__ rp, int32_t n, int32_t nblk,
+    const uint32_t *__restrict__ off, int32_t *__restrict__ order, int2 *__restrict__ lab,
+    int32_t *__restrict__ wnew, uint32_t *__restrict__ len2) {
+  constexpr int kWaves = kThreads / kWave;
+  __shared__ uint32_t wh[kWaves][32];
+  __shared__ uint32_t s_off[32];
+  const int tid = threadIdx.x, wv = tid / kWave, lane = lane_id();
+  if (tid < kWaves * 32) (&wh[0][0])[tid] = 0u;
+  if (tid < 32) s_off[tid] = off[int64_t(tid) * nblk + blockIdx.x];
+  __syncthreads();
+  const int64_t base = int64_t(blockIdx.x) * kRelTile + wv * (kRelTile / kWaves);
+  int32_t ww[kRelPer], r0[kRelPer], r1[kRelPer];
+  uint32_t rank[kRelPer];
+#pragma unroll
+  for (int r = 0; r < kRelPer; ++r) {
+    const int64_t v = base + r * kWave + lane;
+    const int64_t vc = v < n ? v : 0;
+    ww[r] = w[vc];
+    r0[r] = rp[vc];
+    r1[r] = rp[vc + 1];
+  }
+#pragma unroll
+  for (int r = 0; r < kRelPer; ++r)
+    rank[r] = wave_digit_rank(weight_bucket(ww[r]), base + r * kWave + lane < n, 5, wh[wv]);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRelPer; ++r) {
+    const int64_t v = base + r * kWave + lane;
+    if (v >= n) continue;
+    const uint32_t c = weight_bucket(ww[r]);
+    uint32_t p = s_off[c] + rank[r];
+    for (int q = 0; q < wv; ++q) p += wh[q][c];
+    order[p] = int32_t(v);
+    lab[v] = make_int2(int32_t(p), ww[r]);
+    wnew[p] = ww[r];
+    len2[p] = uint32_t(r1[r] - r0[r]);
   }
 }
 
@@ -807,21 +861,12 @@ __global__ __launch_bounds__(256) void k_hot2_fill(const uint64_t *__restrict__ 
 }
 
 // rp2[n] = the entry count; npos = the vertices of weight > 0, which take
-// the new labels [0, npos): the first sorted key of bucket 31 (found by a
-// binary search of the sorted keys).
+// the new labels [0, npos) (the start of bucket 31 in the new order).
 __global__ void k_set_total(int32_t *rp2, int32_t n, const int64_t *total,
-                            const uint64_t *__restrict__ keys, uint32_t *npos) {
+                            const uint32_t *__restrict__ start31, uint32_t *npos) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     rp2[n] = int32_t(*total);
-    int32_t lo = 0, hi = n;
-    while (lo < hi) {
-      const int32_t m = (lo + hi) >> 1;
-      if ((keys[m] >> 32) < 31u)
-        lo = m + 1;
-      else
-        hi = m;
-    }
-    *npos = uint32_t(lo);
+    *npos = *start31;
   }
 }
 
@@ -1726,9 +1771,8 @@ struct Layout {
   uint32_t *counter;
   unsigned long long *ksum;
   // vertex relabelling
-  uint64_t *keys_in, *keys_out;
-  void *radix_ws;
-  size_t radix_bytes;
+  uint64_t *keys_in;
+  uint32_t *bucket_off;
   int32_t *order, *wnew, *rp2, *col2;
   int2 *lab;
   uint64_t *hot;
@@ -1773,9 +1817,7 @@ Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs, size_t *byte
   L.blk_ysum = c.take<double>(size_t(nb) * nrhs);
   L.part = c.take<double>(size_t(G > G0 ? G : G0) * nrhs);
   L.keys_in = c.take<uint64_t>(size_t(n));
-  L.keys_out = c.take<uint64_t>(size_t(n));
-  L.radix_bytes = radix_ws_bytes(n, 31) + scan_ws_elems(n) * 4 + 256;
-  L.radix_ws = c.take<uint8_t>(L.radix_bytes);
+  L.bucket_off = c.take<uint32_t>(size_t(32) * size_t((n + kRelTile - 1) / kRelTile));
   L.order = c.take<int32_t>(size_t(n));
   L.lab = c.take<int2>(size_t(n));
   L.wnew = c.take<int32_t>(size_t(n));
@@ -2091,19 +2133,21 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
   V *x0 = r;
   Hot2 hot{nullptr, 0};
   if (weights) {
-    hipLaunchKernelGGL(k_order_keys, dim3(gN), dim3(256), 0, s, weights, n32, L.keys_in);
-    PP_LAUNCHED("k_order_keys");
-    st = radix_sort(RadixIn{L.keys_in, nullptr, nullptr}, RadixOut{L.keys_out, nullptr, nullptr},
-                    n, 5, L.radix_ws, L.radix_bytes, 0, false, nullptr, s, false);
+    const int32_t nrb = int32_t((n + kRelTile - 1) / kRelTile);
+    hipLaunchKernelGGL(k_bucket_count, dim3(nrb), dim3(kThreads), 0, s, weights, n32, nrb,
+                       L.bucket_off);
+    st = exscan_u32(L.bucket_off, L.bucket_off, int64_t(32) * nrb,
+                    reinterpret_cast<uint32_t *>(L.keys_in), nullptr, s);
     if (st != PP_OK) return st;
-    hipLaunchKernelGGL(k_relabel_maps, dim3(gN), dim3(256), 0, s, L.keys_out, AT0.row_ptr,
-                       weights, n32, L.order, L.lab, L.wnew, reinterpret_cast<uint32_t *>(L.rp2));
-    PP_LAUNCHED("k_relabel_maps");
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(nrb), dim3(kThreads), 0, s, weights, AT0.row_ptr,
+                       n32, nrb, L.bucket_off, L.order, L.lab, L.wnew,
+                       reinterpret_cast<uint32_t *>(L.rp2));
+    PP_LAUNCHED("k_bucket_count/k_bucket_scatter");
     st = exscan_u32(reinterpret_cast<uint32_t *>(L.rp2), reinterpret_cast<uint32_t *>(L.rp2), n,
                     reinterpret_cast<uint32_t *>(L.keys_in), L.total, s);
     if (st != PP_OK) return st;
-    hipLaunchKernelGGL(k_set_total, dim3(1), dim3(64), 0, s, L.rp2, n32, L.total, L.keys_out,
-                       L.npos);
+    hipLaunchKernelGGL(k_set_total, dim3(1), dim3(64), 0, s, L.rp2, n32, L.total,
+                       L.bucket_off + int64_t(31) * nrb, L.npos);
     // Every entry's column goes through lab at random; the heaviest
     // sources' entries are cached in an L2-sized table in front of it (the
     // winners are picked into keys_in, free once rp2 is scanned).
