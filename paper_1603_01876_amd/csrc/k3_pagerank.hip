@@ -973,7 +973,7 @@ __global__ __launch_bounds__(256) void k_permute_out(const V *__restrict__ src,
 constexpr int kSegTile = kThreads * 4;    // merge items per build tile
 constexpr int kSegPer = kSegTile / kThreads;
 constexpr int kMaxSlabs = 256;
-constexpr int kCombItems = kThreads * 16; // rows + pairs per combine workgroup
+constexpr int kCombItems = kThreads * 8;  // rows + pairs per combine workgroup
 
 __device__ __forceinline__ int32_t row_of(const int32_t *s_end, int32_t na, int32_t e) {
   int32_t lo = 0, hi = na;
