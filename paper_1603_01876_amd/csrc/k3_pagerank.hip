@@ -1542,12 +1542,14 @@ __global__ __launch_bounds__(kThreads) void k_pair_index(
 // With wdiv (degree-scaled form, every iteration but the last) the block
 // stores y[v] / wdiv[v] (0 where wdiv[v] <= 0), the vector the next
 // iteration gathers, instead of y[v]; sum(y) is formed from y either way.
+// With perm (the last iteration of a relabelled run) y[v] goes to
+// y[perm[v]]: the result in the caller's labels, with no pass of its own.
 template <typename V>
 __global__ __launch_bounds__(kThreads) void k_seg_combine(
     const typename Form<V>::Part *__restrict__ part, const int32_t *__restrict__ rpp,
     const int32_t *__restrict__ pidx, const int2 *__restrict__ cstart, double c,
     const double *__restrict__ tele_in, V *__restrict__ y, double *__restrict__ blk_ysum,
-    const int32_t *__restrict__ wdiv) {
+    const int32_t *__restrict__ wdiv, const int32_t *__restrict__ perm) {
   using Acc = typename Form<V>::Acc;
   using Part = typename Form<V>::Part;
   constexpr int kCap = kCombItems + kMaxSlabs;
@@ -1597,6 +1599,8 @@ __global__ __launch_bounds__(kThreads) void k_seg_combine(
     if (wdiv) {
       const int32_t d = wdiv[R0 + i];
       y[R0 + i] = d > 0 ? V(double(yv) / double(d)) : V(0);
+    } else if (perm) {
+      y[perm[R0 + i]] = yv;
     } else {
       y[R0 + i] = yv;
     }
@@ -1607,13 +1611,23 @@ __global__ __launch_bounds__(kThreads) void k_seg_combine(
 }
 
 // sum(y) = the nblk workgroup partials added in a fixed order by one
-// workgroup of 1024 threads; stores it and the next teleport scalar.
+// workgroup of 1024 threads; stores it and the next teleport scalar.  Each
+// thread keeps 8 running sums over interleaved partials (8 reads in flight),
+// added in a fixed order at the end.
 __global__ __launch_bounds__(1024) void k_sum_blocks(const double *__restrict__ blk_ysum,
                                                      int32_t nblk, double w, double *sum_out,
                                                      double *tele_out) {
   __shared__ double sh[1024 / kWave];
-  double a = 0.0;
-  for (int k = threadIdx.x; k < nblk; k += 1024) a += blk_ysum[k];
+  double acc[8] = {};
+  for (int k0 = 0; k0 < nblk; k0 += 8 * 1024) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int k = k0 + i * 1024 + int(threadIdx.x);
+      const double v = blk_ysum[k < nblk ? k : 0];   // unconditional read (nblk >= 1)
+      acc[i] += k < nblk ? v : 0.0;
+    }
+  }
+  double a = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   a = wave_sum(a);
   if (lane_id() == 0) sh[threadIdx.x / kWave] = a;
   __syncthreads();
@@ -2264,6 +2278,7 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
 
   g_timing.used = 0;
   int32_t done = 0;
+  bool out_done = false;   // the last combine wrote r already
   for (int32_t it = 0; it < iters; ++it) {
     const V *x = (it & 1) ? L.y : x0;
     V *yv = (it & 1) ? x0 : L.y;
@@ -2285,10 +2300,15 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
       hipLaunchKernelGGL(k_fix_raw<V>, dim3(grid_for(nbp, 256, 4096)), dim3(256), 0, s,
                          L.seg_part, nbp, L.coord, L.closes, L.carry_row, L.blk_carry,
                          L.blk_head);
-      // The scaled form stores y / w for the next iteration, y itself after the last.
+      // The scaled form stores y / w for the next iteration, y itself after
+      // the last; a relabelled run stores the last y straight into r in the
+      // caller's labels (not with a convergence test, which may stop early).
+      const bool last_out = weights && !cv && it + 1 == iters;
       hipLaunchKernelGGL(k_seg_combine<V>, dim3(ncomb), dim3(kThreads), 0, s, L.seg_part, L.rpp,
-                         L.pidx, L.cstart, c, t_in, yv, L.blk_ysum,
-                         scaled && it + 1 < iters ? L.wnew : nullptr);
+                         L.pidx, L.cstart, c, t_in, last_out ? r : yv, L.blk_ysum,
+                         scaled && it + 1 < iters ? L.wnew : nullptr,
+                         last_out ? L.order : nullptr);
+      out_done = last_out;
       hipLaunchKernelGGL(k_sum_blocks, dim3(1), dim3(1024), 0, s, L.blk_ysum, ncomb, w, s_out,
                          t_out);
       if ((st = timed_end(s)) != PP_OK) return st;
@@ -2335,6 +2355,7 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
   }
   if (cv) *cv->iters_done = done;
   const V *last = (done & 1) ? L.y : x0;
+  if (out_done) return PP_OK;
   if (weights || tiled) {
     hipLaunchKernelGGL(k_permute_out<V>, dim3(gNK), dim3(256), 0, s, last,
                        weights ? L.order : nullptr, n32, k, T, r);
