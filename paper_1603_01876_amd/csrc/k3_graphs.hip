@@ -84,6 +84,11 @@ __device__ __forceinline__ T block_sum(T v, T *sh) {
   return r;
 }
 
+template <typename T>
+using GPtr = const T __attribute__((address_space(1))) *;
+template <typename T>
+using GPtrW = T __attribute__((address_space(1))) *;
+
 // Every descriptor has been checked on the host before the launch (n in
 // [1, lds_n], nnz >= 0, the arrays present), so each graph fits the
 // workgroup's two LDS vectors.
@@ -112,9 +117,13 @@ __global__ __launch_bounds__(kT) void k_graphs(const pp_graph *__restrict__ grap
     if (g >= ngraphs) break;
     const pp_graph G = graphs[g];
     const int32_t n = int32_t(G.n), nnz = int32_t(G.nnz);
-    const int32_t *__restrict__ rp = G.row_ptr;
-    const int32_t *__restrict__ col = G.col;
-    const V *__restrict__ val = static_cast<const V *>(G.val);
+    // The descriptor's pointers are generic; these views tell the compiler
+    // they are device (global) memory, so their reads are global loads
+    // rather than flat ones (which also wait on the LDS counter).
+    const GPtr<int32_t> rp = (GPtr<int32_t>)(G.row_ptr);
+    const GPtr<int32_t> col = (GPtr<int32_t>)(G.col);
+    const GPtr<V> val = (GPtr<V>)(G.val);
+    const GPtrW<double> sums = (GPtrW<double>)(G.sums);
     V *x = xa, *y = ya;
 
     // Initial vector: 24-bit draws, exact integer sum, one division each.
@@ -131,7 +140,7 @@ __global__ __launch_bounds__(kT) void k_graphs(const pp_graph *__restrict__ grap
     double ps = 0.0;
     for (int32_t i = tid; i < n; i += kT) ps += double(x[i]);
     double s = block_sum(ps, s_dred);
-    if (tid == 0 && G.sums) G.sums[0] = s;
+    if (tid == 0 && sums) sums[0] = s;
     const double w = (1.0 - c) / double(n);
 
     // This thread's merge-path items, fixed for all iterations.
@@ -163,11 +172,13 @@ __global__ __launch_bounds__(kT) void k_graphs(const pp_graph *__restrict__ grap
       for (int32_t d = d0; d < d1;) {
         int32_t cw[U];
         V vw[U];
+        // Unconditional reads (index clamped; a graph with no entries has
+        // no items left here), so all 2U are in flight together.
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int32_t q = tj + u < nnz ? tj + u : nnz - 1;
-          cw[u] = q >= 0 ? col[q] : 0;
-          vw[u] = q >= 0 ? val[q] : V(0);
+          cw[u] = col[q];
+          vw[u] = val[q];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -226,12 +237,12 @@ __global__ __launch_bounds__(kT) void k_graphs(const pp_graph *__restrict__ grap
         ysum += double(yv);
       }
       s = block_sum(ysum, s_dred);   // contains __syncthreads: y complete
-      if (tid == 0 && G.sums) G.sums[it + 1] = s;
+      if (tid == 0 && sums) sums[it + 1] = s;
       V *t = x;
       x = y;
       y = t;
     }
-    V *r = static_cast<V *>(G.r);
+    const GPtrW<V> r = (GPtrW<V>)(G.r);
     for (int32_t i = tid; i < n; i += kT) r[i] = x[i];
     __syncthreads();
   }
@@ -403,10 +414,10 @@ pp_status launch_graphs(int32_t ngraphs, const pp_graph *graphs, int64_t max_n, 
   if (st != PP_OK) return st;
   if (e_end != hipSuccess) return check_hip(e_end, "hipStreamEndCapture");
   hipError_t e_inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);
   if (e_inst != hipSuccess) return check_hip(e_inst, "hipGraphInstantiate");
   if (g_cache.size() >= 8) {
-    hipGraphExecDestroy(g_cache.front().exec);
+    (void)hipGraphExecDestroy(g_cache.front().exec);
     g_cache.erase(g_cache.begin());
   }
   g_cache.push_back(GraphEntry{ws, s, ngraphs, iters, lds_n, grid, dt, c, exec});
