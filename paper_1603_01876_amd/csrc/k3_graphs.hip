@@ -33,6 +33,7 @@ struct AccD {
 };
 __device__ __forceinline__ AccD merge(AccD a, AccD b) { return AccD{a.s + b.s}; }
 __device__ __forceinline__ AccD shfl_up_acc(AccD a, int o) { return AccD{__shfl_up(a.s, o, kWave)}; }
+__device__ __forceinline__ AccD shfl_acc(AccD a, int src) { return AccD{__shfl(a.s, src, kWave)}; }
 
 struct AccF {
   float s, e;
@@ -53,6 +54,9 @@ __device__ __forceinline__ AccF merge(AccF a, AccF b) {
 }
 __device__ __forceinline__ AccF shfl_up_acc(AccF a, int o) {
   return AccF{__shfl_up(a.s, o, kWave), __shfl_up(a.e, o, kWave)};
+}
+__device__ __forceinline__ AccF shfl_acc(AccF a, int src) {
+  return AccF{__shfl(a.s, src, kWave), __shfl(a.e, src, kWave)};
 }
 
 template <typename V>
@@ -84,6 +88,18 @@ __device__ __forceinline__ T block_sum(T v, T *sh) {
   return r;
 }
 
+constexpr int kU = 4;                  // merge items per lane per round
+constexpr int kRound = kWave * kU;     // merge items per wave round
+
+// Orders a wave's LDS writes before its later reads of other lanes' data
+// (a wave's LDS operations complete in issue order; this keeps the
+// compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename T>
 using GPtr = const T __attribute__((address_space(1))) *;
 template <typename T>
@@ -104,9 +120,10 @@ __global__ __launch_bounds__(kT) void k_graphs(const pp_graph *__restrict__ grap
   __shared__ int32_t s_g;
   __shared__ double s_dred[kW];
   __shared__ unsigned long long s_ured[kW];
-  __shared__ Acc s_pre[kT];
-  __shared__ Acc s_tail[kW];
-  __shared__ int32_t s_first[kW], s_last[kW];
+  __shared__ int32_t s_re[kW][kRound];   // row ends of each wave's round
+  __shared__ Acc s_tail[kW], s_head[kW];
+  __shared__ int32_t s_first[kW], s_last[kW], s_hdone[kW];
+  __shared__ int32_t s_wi[kW + 1], s_wj[kW + 1];
 
   const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
   for (;;) {
@@ -143,97 +160,156 @@ __global__ __launch_bounds__(kT) void k_graphs(const pp_graph *__restrict__ grap
     if (tid == 0 && sums) sums[0] = s;
     const double w = (1.0 - c) / double(n);
 
-    // This thread's merge-path items, fixed for all iterations.
+    // Each wave takes a contiguous range of the merge sequence (row ends and
+    // non-zeros), fixed for all iterations, and walks it in rounds of
+    // kRound items: the round's row ends go to LDS (coalesced reads), each
+    // lane takes kU consecutive items of the round (a merge-path search in
+    // the round's row ends) with its column/value reads adjacent to its
+    // neighbours', and a segmented scan across the wave completes the rows
+    // that span lanes.  The row left open at the end of a round is carried
+    // into the next; rows that span waves are completed after one barrier.
     const int32_t tot = n + nnz;
-    const int32_t per = (tot + kT - 1) / kT;
-    const int32_t d0 = tid * per < tot ? tid * per : tot;
-    const int32_t d1 = d0 + per < tot ? d0 + per : tot;
-    int32_t lo = d0 - nnz > 0 ? d0 - nnz : 0, hi = d0 < n ? d0 : n;
-    while (lo < hi) {
-      const int32_t m = (lo + hi) >> 1;
-      if (rp[m + 1] <= d0 - m - 1)
-        lo = m + 1;
-      else
-        hi = m;
+    const int32_t per = (tot + kW - 1) / kW;
+    if (tid <= kW) {
+      const int32_t d = tid * per < tot ? tid * per : tot;
+      int32_t lo = d - nnz > 0 ? d - nnz : 0, hi = d < n ? d : n;
+      while (lo < hi) {
+        const int32_t m = (lo + hi) >> 1;
+        if (rp[m + 1] <= d - m - 1)
+          lo = m + 1;
+        else
+          hi = m;
+      }
+      s_wi[tid] = lo;
+      s_wj[tid] = d - lo;
     }
-    const int32_t ti0 = lo, tj0 = d0 - lo;
+    __syncthreads();
+    const int32_t wi0 = s_wi[wv], wj0 = s_wj[wv];
+    const int32_t dw0 = wi0 + wj0, dw1 = s_wi[wv + 1] + s_wj[wv + 1];
+    // The wave starts inside a row that earlier waves began.
+    const bool mid = wi0 < n && wj0 > rp[wi0];
+    int32_t *re = s_re[wv];
 
     for (int32_t it = 0; it < iters; ++it) {
       const double tk = w * s;
-      int32_t ti = ti0, tj = tj0;
-      int32_t next_end = ti < n ? rp[ti + 1] : 0;
-      Acc acc{}, first{};
-      int32_t first_row = -1;
       double ysum = 0.0;
-      // Walk the items with a window of U column/value loads in flight
-      // (a thread's non-zeros are contiguous); row ends between them
-      // are handled as they come.
-      constexpr int U = 8;
-      for (int32_t d = d0; d < d1;) {
-        int32_t cw[U];
-        V vw[U];
-        // Unconditional reads (index clamped; a graph with no entries has
-        // no items left here), so all 2U are in flight together.
+      int32_t ri = wi0, rj = wj0;   // coordinate (row, non-zero) of the round's start
+      Acc carry{};                  // row ri's partial from earlier rounds of this wave
+      Acc head{};                   // the wave's part of row wi0 when mid (completed here)
+      bool hdone = false;
+      for (int32_t d = dw0; d < dw1; d += kRound) {
+        const int32_t cnt = dw1 - d < kRound ? dw1 - d : kRound;
+        // Row ends of rows ri, ri + 1, ... as non-zero offsets from rj
+        // (rows past the graph never end).  Reads unconditional.
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int32_t q = tj + u < nnz ? tj + u : nnz - 1;
-          cw[u] = col[q];
-          vw[u] = val[q];
+        for (int u = 0; u < kU; ++u) {
+          const int32_t q = u * kWave + lane;
+          const int32_t row = ri + q < n ? ri + q : n - 1;
+          const int32_t e = rp[row + 1] - rj;
+          re[q] = ri + q < n ? e : INT32_MAX;
         }
+        wave_sync();
+        // This lane's items [o, o + nit) of the round and its start.
+        const int32_t o = lane * kU < cnt ? lane * kU : cnt;
+        const int32_t nit = cnt - o < kU ? cnt - o : kU;
+        int32_t lo = 0, hi = o;
+        while (lo < hi) {
+          const int32_t m = (lo + hi) >> 1;
+          if (re[m] <= o - m - 1)
+            lo = m + 1;
+          else
+            hi = m;
+        }
+        int32_t ti = ri + lo, tj = rj + (o - lo);
+        int32_t cw[kU];
+        V vw[kU];
+        if (nnz > 0) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          while (d < d1 && ti < n && next_end <= tj) {
-            if (first_row < 0) {
-              first_row = ti;
-              first = acc;
-            } else {
-              const V yv = GForm<V>::finish(acc, c, tk);
-              y[ti] = yv;
-              ysum += double(yv);
-            }
-            acc = Acc{};
-            ++ti;
-            next_end = ti < n ? rp[ti + 1] : 0;
-            ++d;
+          for (int u = 0; u < kU; ++u) {
+            const int32_t q = tj + u < nnz ? tj + u : nnz - 1;
+            cw[u] = col[q];
+            vw[u] = val[q];
           }
-          if (d < d1) {
+        }
+        Acc acc{}, first{};
+        int32_t first_row = -1;
+        int32_t left = nit;
+        auto row_end = [&]() {
+          if (first_row < 0) {
+            first_row = ti;
+            first = acc;
+          } else {
+            const V yv = GForm<V>::finish(acc, c, tk);
+            y[ti] = yv;
+            ysum += double(yv);
+          }
+          acc = Acc{};
+          ++ti;
+          --left;
+        };
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          while (left > 0 && re[ti - ri] <= tj - rj) row_end();
+          if (left > 0) {
             acc.add(x[cw[u]] * vw[u]);
             ++tj;
-            ++d;
+            --left;
           }
         }
-      }
-      // Segmented scan of open-row partials (key = open row), as in the
-      // large-graph SpMV, over 16 waves.
-      const int32_t key = ti;
-      Acc v = acc;
+        while (left > 0 && re[ti - ri] <= tj - rj) row_end();
+        // Lane 0 starts in row ri, which earlier rounds may have begun.
+        if (lane == 0) {
+          if (first_row >= 0)
+            first = merge(carry, first);
+          else
+            acc = merge(carry, acc);
+        }
+        // Segmented scan of the open rows' partials across the wave.
+        const int32_t key = ti;
+        Acc v = acc;
 #pragma unroll
-      for (int o = 1; o < kWave; o <<= 1) {
-        const Acc vu = shfl_up_acc(v, o);
-        const int32_t ku = __shfl_up(key, o, kWave);
-        if (lane >= o && ku == key) v = merge(vu, v);
+        for (int off = 1; off < kWave; off <<= 1) {
+          const Acc vu = shfl_up_acc(v, off);
+          const int32_t ku = __shfl_up(key, off, kWave);
+          if (lane >= off && ku == key) v = merge(vu, v);
+        }
+        const Acc pv = shfl_up_acc(v, 1);
+        const int32_t pk = __shfl_up(key, 1, kWave);
+        if (first_row >= 0) {
+          const Acc sum = lane > 0 && pk == first_row ? merge(pv, first) : first;
+          if (mid && first_row == wi0) {
+            head = sum;   // earlier waves hold the rest of this row
+            hdone = true;
+          } else {
+            const V yv = GForm<V>::finish(sum, c, tk);
+            y[first_row] = yv;
+            ysum += double(yv);
+          }
+        }
+        carry = shfl_acc(v, kWave - 1);
+        ri = __shfl(ti, kWave - 1, kWave);
+        rj = __shfl(tj, kWave - 1, kWave);
+        wave_sync();   // every lane is done with re before the next round
       }
-      if (lane == kWave - 1) {
-        s_tail[wv] = v;
-        s_last[wv] = key;
+      // Wave tails and heads; rows that span waves.
+      if (hdone) s_head[wv] = head;
+      const uint64_t hb = __ballot(hdone);
+      if (lane == 0) {
+        s_tail[wv] = carry;
+        s_first[wv] = wi0;
+        s_last[wv] = ri;
+        s_hdone[wv] = hb != 0ull;
       }
-      if (lane == 0) s_first[wv] = key;
       __syncthreads();
-      {
+      if (lane == 0 && s_hdone[wv]) {
         Acc before{};
         for (int q = wv - 1; q >= 0; --q) {
-          if (s_last[q] != key) break;
+          if (s_last[q] != wi0) break;
           before = merge(s_tail[q], before);
-          if (s_first[q] != key) break;
+          if (s_first[q] != wi0) break;
         }
-        v = merge(before, v);
-      }
-      s_pre[tid] = v;
-      __syncthreads();
-      if (first_row >= 0) {
-        const Acc sum = tid > 0 ? merge(s_pre[tid - 1], first) : first;
-        const V yv = GForm<V>::finish(sum, c, tk);
-        y[first_row] = yv;
+        const V yv = GForm<V>::finish(merge(before, s_head[wv]), c, tk);
+        y[wi0] = yv;
         ysum += double(yv);
       }
       s = block_sum(ysum, s_dred);   // contains __syncthreads: y complete
