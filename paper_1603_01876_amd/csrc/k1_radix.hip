@@ -63,19 +63,23 @@ __global__ __launch_bounds__(kThreads) void k_radix_count(RadixIn in, int64_t m,
   const int w = threadIdx.x / kWave;
   const int64_t base = int64_t(blockIdx.x) * kTile + int64_t(w) * kWaveKeys;
   const uint32_t dmask = (1u << bits) - 1u;
+  // All of the thread's reads first (unconditional, index clamped), so they
+  // are in flight together; a read under a per-lane condition would be
+  // waited for before the next is issued.
+  uint64_t keys[kPerThread];
+#pragma unroll
   for (int r = 0; r < kPerThread; ++r) {
     const int64_t i = base + r * kWave + lane_id();
-    const bool valid = i < m;
-    uint64_t key = 0;
-    if (valid) {
-      if constexpr (kSep)
-        key = uint64_t(in.hi[i]) << 32;
-      else
-        key = in.packed[i];
-    }
-    // Counts need no order: one LDS add per key into the wave's own bins.
-    if (valid) atomicAdd(&wh[w][digit_of(key, shift, dmask)], 1u);
+    const int64_t ic = i < m ? i : m - 1;
+    if constexpr (kSep)
+      keys[r] = uint64_t(in.hi[ic]) << 32;
+    else
+      keys[r] = in.packed[ic];
   }
+  // Counts need no order: one LDS add per key into the wave's own bins.
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r)
+    if (base + r * kWave + lane_id() < m) atomicAdd(&wh[w][digit_of(keys[r], shift, dmask)], 1u);
   __syncthreads();
   for (int d = threadIdx.x; d <= int(dmask); d += kThreads)
     counts[int64_t(d) * ntiles + blockIdx.x] = wh[0][d] + wh[1][d] + wh[2][d] + wh[3][d];

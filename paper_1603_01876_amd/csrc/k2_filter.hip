@@ -56,17 +56,31 @@ __device__ __forceinline__ uint64_t from_lane63(uint64_t x) {
 }
 
 // vstart[w] = first sorted position with v >= w, for w = 0..n.
-__global__ __launch_bounds__(256) void k_vstart(const uint64_t *__restrict__ P, int64_t m,
-                                                int32_t n, int32_t *__restrict__ vstart) {
-  const int64_t stride = int64_t(gridDim.x) * 256;
-  for (int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x; p < m; p += stride) {
-    const int32_t v = vof(P[p]);
-    // Lanes holding p are active down to lane 0, so lane - 1 holds p - 1.
+__global__ __launch_bounds__(kThreads) void k_vstart(const uint64_t *__restrict__ P, int64_t m,
+                                                     int32_t n, int32_t *__restrict__ vstart) {
+  // A wave takes kWaveKeys consecutive keys, kPerThread rounds of 64; every
+  // read is issued first (index clamped), then the rounds are processed.
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const int64_t base = int64_t(blockIdx.x) * kTile + int64_t(w) * kWaveKeys;
+  int32_t vv[kPerThread];
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) {
+    const int64_t p = base + r * kWave + lane;
+    vv[r] = vof(P[p < m ? p : m - 1]);
+  }
+  const int32_t vbefore = base > 0 ? vof(P[(base < m ? base : m) - 1]) : -1;
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) {
+    const int64_t p = base + r * kWave + lane;
+    const int32_t v = vv[r];
     const int32_t up = __shfl_up(v, 1, kWave);
-    const int32_t vp = lane_id() > 0 ? up : (p > 0 ? vof(P[p - 1]) : -1);
-    for (int32_t w = vp + 1; w <= v; ++w) vstart[w] = int32_t(p);
-    if (p == m - 1)
-      for (int32_t w = v + 1; w <= n; ++w) vstart[w] = int32_t(m);
+    const int32_t last = __shfl(r > 0 ? vv[r > 0 ? r - 1 : 0] : 0, kWave - 1, kWave);
+    if (p < m) {
+      const int32_t vp = lane > 0 ? up : (r > 0 ? last : vbefore);
+      for (int32_t q = vp + 1; q <= v; ++q) vstart[q] = int32_t(p);
+      if (p == m - 1)
+        for (int32_t q = v + 1; q <= n; ++q) vstart[q] = int32_t(m);
+    }
   }
 }
 
@@ -103,14 +117,21 @@ __global__ __launch_bounds__(256) void k_keepbits(const int32_t *__restrict__ d_
 // d_out[u] += number of edges of u, over the u-ordered input.  A wave
 // covers 64 consecutive edges; each run of equal u inside it is counted by
 // the run's first lane with one popcount and one atomic add.
-__global__ __launch_bounds__(256) void k_dout(const int64_t *__restrict__ u, int64_t m,
-                                              int32_t *__restrict__ d_out) {
-  const int64_t stride = int64_t(gridDim.x) * 256;
-  const int lane = lane_id();
-  for (int64_t p0 = int64_t(blockIdx.x) * 256 + (threadIdx.x & ~63); p0 < m; p0 += stride) {
-    const int64_t p = p0 + lane;
-    const bool valid = p < m;
-    const int32_t uu = valid ? int32_t(u[p]) : -1;
+__global__ __launch_bounds__(kThreads) void k_dout(const int64_t *__restrict__ u, int64_t m,
+                                                   int32_t *__restrict__ d_out) {
+  // Tiles as in k_vstart: all reads first, then one 64-edge round at a time.
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const int64_t base = int64_t(blockIdx.x) * kTile + int64_t(w) * kWaveKeys;
+  int32_t us[kPerThread];
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) {
+    const int64_t p = base + r * kWave + lane;
+    us[r] = int32_t(u[p < m ? p : m - 1]);
+  }
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) {
+    const bool valid = base + r * kWave + lane < m;
+    const int32_t uu = valid ? us[r] : -1;
     const int32_t up = __shfl_up(uu, 1, kWave);
     const bool head = valid && (lane == 0 || up != uu);
     const uint64_t heads = __ballot(head);
@@ -136,11 +157,20 @@ __global__ __launch_bounds__(kThreads) void k_compact_count(const uint64_t *__re
   const int64_t base = int64_t(blockIdx.x) * kTile + int64_t(w) * kWaveKeys;
   uint32_t c = 0;
   uint64_t carry = 0;   // key of the previous round's lane 63
+  // Every read first (index clamped; keys past the end are not counted).
+  uint64_t keys[kPerThread];
+#pragma unroll
   for (int r = 0; r < kPerThread; ++r) {
     const int64_t p = base + r * kWave + lane_id();
-    const uint64_t key = p < m ? P[p] : 0ull;
+    keys[r] = P[p < m ? p : m - 1];
+  }
+  const uint64_t before = base > 0 ? P[(base < m ? base : m) - 1] : ~0ull;
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) {
+    const int64_t p = base + r * kWave + lane_id();
+    const uint64_t key = p < m ? keys[r] : 0ull;
     const uint64_t below = from_lane_below(key);
-    const uint64_t prev = lane_id() > 0 ? below : r > 0 ? carry : p > 0 && p <= m ? P[p - 1] : ~0ull;
+    const uint64_t prev = lane_id() > 0 ? below : r > 0 ? carry : p > 0 && p <= m ? before : ~0ull;
     carry = from_lane63(key);
     if (p < m) {
       const bool distinct = p == 0 || prev != key;
@@ -297,7 +327,8 @@ pp_status launch_filter(int32_t scale, int64_t m, const int64_t *u, const int64_
 
   // 2-4. column starts, in-degrees, maximum, surviving columns.
   const int n32 = int32_t(n);
-  hipLaunchKernelGGL(k_vstart, dim3(grid_for(m, 256, 256 * 32)), dim3(256), 0, s, L.P, m, n32,
+  const int64_t ntiles = (m + kTile - 1) / kTile;
+  hipLaunchKernelGGL(k_vstart, dim3(unsigned(ntiles)), dim3(kThreads), 0, s, L.P, m, n32,
                      L.vstart);
   if ((st = fill_i32(L.mx, 1, 0, s)) != PP_OK) return st;
   hipLaunchKernelGGL(k_din, dim3(grid_for(n, 256, 256 * 32)), dim3(256), 0, s, L.vstart, n32, din,
@@ -308,11 +339,10 @@ pp_status launch_filter(int32_t scale, int64_t m, const int64_t *u, const int64_
 
   // 5. edges per u from the u-ordered input.
   if ((st = fill_i32(dout, n, 0, s)) != PP_OK) return st;
-  hipLaunchKernelGGL(k_dout, dim3(grid_for(m, 256, 256 * 32)), dim3(256), 0, s, u, m, dout);
+  hipLaunchKernelGGL(k_dout, dim3(unsigned(ntiles)), dim3(kThreads), 0, s, u, m, dout);
   PP_LAUNCHED("k_dout");
 
   // 6. compaction into CSR(A^T); removed edges leave d_out here.
-  const int64_t ntiles = (m + kTile - 1) / kTile;
   hipLaunchKernelGGL(k_compact_count, dim3(unsigned(ntiles)), dim3(kThreads), 0, s, L.P, m,
                      L.keepw, L.tile_cnt, dout);
   PP_LAUNCHED("k_compact_count");
