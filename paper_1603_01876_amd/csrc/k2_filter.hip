@@ -184,11 +184,31 @@ __global__ __launch_bounds__(kThreads) void k_compact_count(const uint64_t *__re
   if (threadIdx.x == 0) tile_cnt[blockIdx.x] = tot;
 }
 
+// Out-degrees narrowed to 16 bits (65535 = read the full value), a table
+// half the size of d_out for the emit's scattered reads: twice the
+// vertices per cache line, and small enough to stay in the Infinity Cache.
+__global__ __launch_bounds__(256) void k_narrow(const int32_t *__restrict__ d_out, int32_t n,
+                                                uint16_t *__restrict__ d16) {
+  for (int32_t u = blockIdx.x * 256 + threadIdx.x; u < n; u += gridDim.x * 256) {
+    const int32_t d = d_out[u];
+    d16[u] = uint16_t(d >= 0 && d < 65535 ? d : 65535);
+  }
+}
+
+__device__ __forceinline__ int32_t dout_get(HotTab h, const uint16_t *__restrict__ d16,
+                                            const int32_t *__restrict__ d_out, int32_t u) {
+  const uint64_t e = h.tab[hot_mix(uint32_t(u)) & h.mask];
+  if (uint32_t(e) == uint32_t(u)) return int32_t(uint32_t(e >> 32));
+  const uint32_t d = d16[u];
+  return d != 65535u ? int32_t(d) : d_out[u];
+}
+
 template <typename V>
 __global__ __launch_bounds__(kThreads) void k_compact_emit(
     const uint64_t *__restrict__ P, int64_t m, int32_t n, const uint64_t *__restrict__ keepw,
-    const int32_t *__restrict__ d_out, HotTab hot, const uint32_t *__restrict__ tile_off,
-    int32_t *__restrict__ row_ptr, int32_t *__restrict__ col, V *__restrict__ val) {
+    const int32_t *__restrict__ d_out, const uint16_t *__restrict__ d16, HotTab hot,
+    const uint32_t *__restrict__ tile_off, int32_t *__restrict__ row_ptr, int32_t *__restrict__ col,
+    V *__restrict__ val) {
   __shared__ uint32_t wave_tot[kWaves];
   const int w = threadIdx.x / kWave;
   const int lane = lane_id();
@@ -231,7 +251,7 @@ __global__ __launch_bounds__(kThreads) void k_compact_emit(
         const int32_t u = uof(key);
         int64_t q = p + 1;
         while (q < m && P[q] == key) ++q;
-        const double quot = double(q - p) / double(hot_get(hot, d_out, u));
+        const double quot = double(q - p) / double(dout_get(hot, d16, d_out, u));
         col[excl] = u;
         val[excl] = V(quot);
       }
@@ -351,13 +371,17 @@ pp_status launch_filter(int32_t scale, int64_t m, const int64_t *u, const int64_
   // out-degrees are cached in an L2-sized table in front of it.
   HotTab hot;
   if ((st = hot_build(dout, dout, n32, L.hot, &hot, s)) != PP_OK) return st;
+  // The narrowed out-degrees take the column starts' buffer (free by now).
+  uint16_t *d16 = reinterpret_cast<uint16_t *>(L.vstart);
+  hipLaunchKernelGGL(k_narrow, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, dout, n32, d16);
+  PP_LAUNCHED("k_narrow");
   if (dt == PP_F64)
     hipLaunchKernelGGL(k_compact_emit<double>, dim3(unsigned(ntiles)), dim3(kThreads), 0, s, L.P,
-                       m, n32, L.keepw, dout, hot, L.tile_cnt, AT->row_ptr, AT->col,
+                       m, n32, L.keepw, dout, d16, hot, L.tile_cnt, AT->row_ptr, AT->col,
                        static_cast<double *>(AT->val));
   else
     hipLaunchKernelGGL(k_compact_emit<float>, dim3(unsigned(ntiles)), dim3(kThreads), 0, s, L.P,
-                       m, n32, L.keepw, dout, hot, L.tile_cnt, AT->row_ptr, AT->col,
+                       m, n32, L.keepw, dout, d16, hot, L.tile_cnt, AT->row_ptr, AT->col,
                        static_cast<float *>(AT->val));
   PP_LAUNCHED("k_compact_emit");
 
