@@ -133,3 +133,59 @@ def test_graphs_reject_oversized_and_malformed():
     gb.table[k].col = keep
     pp.pagerank_graphs(gb, use_graph=False)
     check_batch(items, want, "f32")
+
+
+# ------------------------------------------- structured small graphs
+def csr_from_edges(n, edges):
+    """Row form of A (rows u, values 1/out-degree) from (u, v) pairs."""
+    edges = sorted(set(edges))
+    rp = np.zeros(n + 1, np.int64)
+    for u, _ in edges:
+        rp[u + 1] += 1
+    rp = np.cumsum(rp)
+    col = np.array([v for _, v in edges], np.int64)
+    deg = np.diff(rp)
+    val = np.array([1.0 / deg[u] for u, _ in edges], np.float64)
+    return rp, col, val
+
+
+def structured_cases():
+    rng = np.random.default_rng(11)
+    cases = {}
+    n = 5000
+    cases["hub-row"] = (n, [(u, 0) for u in range(1, n)])             # one row of A^T holds every entry
+    cases["hub-column"] = (n, [(0, v) for v in range(1, n)])          # n - 1 rows of one entry
+    cases["no-entries"] = (300, [])
+    cases["one-vertex"] = (1, [])
+    cases["one-self-loop"] = (1, [(0, 0)])
+    lens = [255, 256, 257, 0, 1, 511, 512, 513, 0, 0, 2]               # rows across 256-item rounds
+    n = 2000
+    edges = []
+    for v in range(n):
+        k = lens[v % len(lens)]
+        for u in rng.choice(n, size=min(k, n), replace=False):
+            edges.append((int(u), v))
+    cases["round-edges"] = (n, edges)
+    n = 4096
+    live = rng.choice(n, size=64, replace=False)                        # most rows empty
+    cases["sparse-rows"] = (n, [(int(u), int(v)) for v in live for u in rng.choice(n, 40, replace=False)])
+    return cases
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_graphs_structured_match_oracle(dtype):
+    # Rows that span lanes, rounds and waves, empty graphs, one vertex and
+    # empty rows, all in one batch; each graph against the oracle's K3.
+    items, want = [], []
+    for i, (name, (n, edges)) in enumerate(sorted(structured_cases().items())):
+        rp, col, val = csr_from_edges(n, edges)
+        trp, tcol, tval = oracle.transpose_csr(n, rp, col, val)
+        AT = pp.CSR.from_arrays(n, trp, tcol, tval, dtype)
+        r = torch.empty(n, dtype=torch.float32 if dtype == "f32" else torch.float64, device="cuda")
+        sums = torch.empty(21, dtype=torch.float64, device="cuda")
+        items.append((AT, r, sums, 500 + i))
+        want.append(oracle.pagerank(n, rp, col, val, oracle.init_r(n, 500 + i), 20, C))
+    assert max(AT.n for AT, *_ in items) <= pp.graphs_max_n(dtype)
+    gb = pp.GraphBatch(items, dtype)
+    pp.pagerank_graphs(gb, use_graph=False)
+    check_batch(items, want, dtype)
