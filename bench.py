@@ -163,8 +163,12 @@ def copy_ceiling(torch, nbytes=1 << 31, reps=5):
 def spmv_label(cfg, dt, layout=None):
     v = "float" if dt == "f32" else "double"
     if cfg[2] > 0:
-        ent = ",uint8" if layout and layout.get("scaled") else ""
-        form = " (degree-scaled form: entries stored as counts)" if ent else ""
+        ent = ""
+        if layout and layout.get("scaled"):
+            ent = ",packed" if layout.get("packed") else ",uint8"
+        form = {"": "", ",uint8": " (degree-scaled form: entries stored as counts)",
+                ",packed": " (degree-scaled form: each entry one 4-byte word, column inside the slab"
+                           " and count)"}[ent]
         return (f"segmented SpMV iteration, slabs of 2^{cfg[2]} columns{form}: "
                 f"k_spmv<{v},{cfg[0]},raw{ent}> + k_fix_raw<{v}> + k_seg_combine<{v}> + "
                 f"k_sum_blocks")
@@ -175,11 +179,13 @@ def form_bytes(n: int, nnz: int, dtype: str, layout) -> int | None:
     """Bytes one iteration of the degree-scaled form must move at the
     least: row pointers 4(N+1), columns 4Z, one count byte per entry, the
     gathered vector once and the next one written, and the out-degrees the
-    combine divides by (4N).  None for the value form (spmv_bytes)."""
+    combine divides by (4N).  Packed with the column: 4 bytes per entry.
+    None for the value form (spmv_bytes)."""
     if not layout or not layout.get("scaled"):
         return None
     w = 8 if dtype == "f64" else 4
-    return 4 * (n + 1) + 5 * nnz + 2 * w * n + 4 * n
+    per = 4 if layout.get("packed") else 5
+    return 4 * (n + 1) + per * nnz + 2 * w * n + 4 * n
 
 
 def batched_form(args, pp, workloads, torch):

@@ -363,8 +363,9 @@ pp_status pp_get_k3_config(pp_k3_config *cfg);
 
 /* Layout the most recent pp_pagerank / pp_pagerank_converge call (in this
  * process) iterated on: bit 0 vertices relabelled, bit 1 columns
- * segmented, bit 2 entries stored as counts (degree-scaled form).  0 before
- * any call.  Instrumentation for tests and benchmarks. */
+ * segmented, bit 2 entries stored as counts (degree-scaled form), bit 3
+ * each count packed with its column inside the slab into one 4-byte word.
+ * 0 before any call.  Instrumentation for tests and benchmarks. */
 int32_t pp_k3_last_layout(void);
 
 /* Benchmark instrumentation.  While enabled (enable != 0), each

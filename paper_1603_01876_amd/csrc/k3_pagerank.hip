@@ -146,6 +146,24 @@ __device__ __forceinline__ AccF shfl_up_acc(AccF a, int o) {
   return AccF{__shfl_up(a.s, o, kWave), __shfl_up(a.e, o, kWave)};
 }
 
+// Entry type of the packed count form: seg_col holds the entry's column
+// inside its slab (low 24 bits) and its count (high 8 bits); the slab
+// follows from the entry's position (SlabMap).
+struct PackedCol {};
+template <typename E>
+struct EntryVal {
+  using type = E;
+};
+template <>
+struct EntryVal<PackedCol> {
+  using type = uint32_t;
+};
+struct SlabMap {
+  const int32_t *es;        // first entry of each slab; es[ns] = nnz
+  const int2 *tile_slab;    // per workgroup: slab of its first entry, first entry of the next
+  int32_t sbits, ns;
+};
+
 // With kRaw the rows are (slab, row) pairs of the column-segmented layout
 // below: each completed row stores its raw accumulator into part[] instead
 // of c * sum + t into y, and no sum(y) is formed.  E is the stored entry
@@ -157,8 +175,9 @@ __global__ __launch_bounds__(kThreads) void k_spmv(
     const V *__restrict__ x, V *__restrict__ y, int32_t n, const int2 *__restrict__ coord,
     double c, const double *__restrict__ tele, double *__restrict__ blk_ysum,
     typename Form<V>::Acc *__restrict__ blk_carry, typename Form<V>::Acc *__restrict__ blk_head,
-    typename Form<V>::Part *__restrict__ part) {
+    typename Form<V>::Part *__restrict__ part, SlabMap sm) {
   using Acc = typename Form<V>::Acc;
+  constexpr bool kPacked = std::is_same<E, PackedCol>::value;
   constexpr int kD = kThreads * IPT;
   constexpr int kWaves = kThreads / kWave;
   __shared__ int32_t s_end[kD];
@@ -179,15 +198,37 @@ __global__ __launch_bounds__(kThreads) void k_spmv(
   // all IPT gathers, before it waits on any of them.
   {
     int32_t cc[IPT], ee[IPT];
-    E vv[IPT];
+    typename EntryVal<E>::type vv[IPT];
     V xv[IPT];
     if (nz > 0) {
 #pragma unroll
       for (int r = 0; r < IPT; ++r) {
         const int k = r * kThreads + tid;
         const int kk = k < nz ? k : nz - 1;
-        cc[r] = __builtin_nontemporal_load(col + j0 + kk);
-        vv[r] = __builtin_nontemporal_load(val + j0 + kk);
+        if constexpr (kPacked) {
+          const int32_t pk = __builtin_nontemporal_load(col + j0 + kk);
+          cc[r] = pk & 0xFFFFFF;
+          vv[r] = uint32_t(pk) >> 24;
+        } else {
+          cc[r] = __builtin_nontemporal_load(col + j0 + kk);
+          vv[r] = __builtin_nontemporal_load(val + j0 + kk);
+        }
+      }
+      if constexpr (kPacked) {
+        // Slab of each entry: the workgroup's first slab unless the entry
+        // lies at or past the next slab's start (only at slab boundaries).
+        const int2 ts = sm.tile_slab[b];
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+          const int k = r * kThreads + tid;
+          const int32_t j = j0 + (k < nz ? k : nz - 1);
+          int32_t d = ts.x;
+          if (j >= ts.y) {
+            d = ts.x + 1;
+            while (d + 1 < sm.ns && j >= sm.es[d + 1]) ++d;
+          }
+          cc[r] += d << sm.sbits;
+        }
       }
     }
     if (na > 0) {
@@ -1027,7 +1068,8 @@ struct RelabelSrc {
   const int2 *lab;   // (new label, weight) of every old label
   const void *val0;
   Hot2 hot;          // cache of lab for the heaviest vertices
-  uint32_t *bad;     // set when an entry is not count / weight (scaled form)
+  uint32_t *bad;     // [0] set when an entry is not count / weight (scaled form);
+                     // [1] largest new column of the count form's entries
 };
 
 template <typename V, typename E, bool kScatter, bool kRelabel>
@@ -1036,7 +1078,8 @@ __global__ __launch_bounds__(kThreads) void k_seg_tile(
     RelabelSrc rs, const int2 *__restrict__ coord, int32_t sbits, int32_t ns, int32_t dbits,
     int32_t ntiles, uint32_t *__restrict__ ecnt, uint32_t *__restrict__ pcnt,
     uint32_t *__restrict__ fmask, uint32_t *__restrict__ lmask, int32_t *__restrict__ seg_col,
-    E *__restrict__ seg_val, int32_t *__restrict__ prp, int32_t *__restrict__ pair_row) {
+    E *__restrict__ seg_val, int32_t *__restrict__ prp, int32_t *__restrict__ pair_row,
+    int32_t packed) {
   constexpr bool kCount = !std::is_same<E, V>::value;
   static_assert(!(kScatter && kRelabel), "relabelling happens in the count pass");
   constexpr int kWaves = kThreads / kWave;
@@ -1108,6 +1151,16 @@ __global__ __launch_bounds__(kThreads) void k_seg_tile(
     if constexpr (kCount) {
       const uint64_t any_bad = __ballot(bad);
       if (any_bad && lane == 0) atomicOr(rs.bad, 1u);
+      int32_t cmax = 0;
+#pragma unroll
+      for (int r = 0; r < kSegPer; ++r)
+        if (w * (kSegTile / kWaves) + r * kWave + lane < nz) cmax = cc[r] > cmax ? cc[r] : cmax;
+      cmax = wave_max(cmax);
+      // One address for the whole pass: update it only when it is below
+      // this wave's maximum (it settles early, so few waves write it).
+      int32_t *mp = reinterpret_cast<int32_t *>(rs.bad) + 1;
+      if (lane == 0 && cmax > __hip_atomic_load(mp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(mp, cmax);
     }
 #pragma unroll
     for (int r = 0; r < kSegPer; ++r) {
@@ -1211,8 +1264,13 @@ __global__ __launch_bounds__(kThreads) void k_seg_tile(
         const int32_t cv = s_col[slot];
         const uint32_t dg = slab_of(cv, sbits, ns);
         const int64_t pos = int64_t(s_goff[dg]) + (slot - int32_t(s_toff[dg]));
-        seg_col[pos] = cv;
-        seg_val[pos] = s_val[slot];
+        if (kCount && packed) {
+          // Packed count form: the column inside its slab (< 2^24) and the count.
+          seg_col[pos] = int32_t(uint32_t(cv - int32_t(dg << sbits)) | (uint32_t(s_val[slot]) << 24));
+        } else {
+          seg_col[pos] = cv;
+          seg_val[pos] = s_val[slot];
+        }
         if ((bal[k] >> lane) & 1ull) {
           const uint32_t here = s_pre[k * kWaves + w] + uint32_t(__popcll(bal[k] & lanes_below()));
           const uint32_t pid = s_poff[dg] + here - starts_before(s_toff[dg]);
@@ -1797,6 +1855,8 @@ struct Layout {
   int32_t *seg_col, *prp, *pair_row, *rpp, *pidx;
   int2 *cstart, *seg_coord;
   int64_t *info;
+  int32_t *seg_es;   // slab starts in the segmented entries
+  int2 *tile_slab;   // SpMV workgroups' first slab and the next slab's start
   V *seg_val;
   typename Form<V>::Part *seg_part;
   // run to a convergence test
@@ -1836,7 +1896,7 @@ Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs, size_t *byte
   L.lab = c.take<int2>(size_t(n));
   L.wnew = c.take<int32_t>(size_t(n));
   L.hot = c.take<uint64_t>(size_t(2) << hot_log2(n));
-  L.bad = c.take<uint32_t>(1);
+  L.bad = c.take<uint32_t>(2);
   L.npos = c.take<uint32_t>(1);
   L.rp2 = c.take<int32_t>(size_t(n + 1));
   {
@@ -1877,6 +1937,8 @@ Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs, size_t *byte
     L.seg_scan = c.take<uint32_t>(size_t(scan_ws_elems(scan_n)));
     L.rpp = c.take<int32_t>(size_t(n + 1));
     L.info = c.take<int64_t>(4 + kMaxSlabs);
+    L.seg_es = c.take<int32_t>(kMaxSlabs + 2);
+    L.tile_slab = c.take<int2>(size_t(nb + 1));
     L.cstart = c.take<int2>(size_t((n + z + kCombItems - 1) / kCombItems + 2));
     L.pidx = L.col2;
   }
@@ -1919,16 +1981,42 @@ template <typename V, bool kRaw, typename E = V>
 void launch_spmv(int ipt, int32_t nb, hipStream_t s, const int32_t *rp, const int32_t *col,
                  const E *val, const V *x, V *y, int32_t n, const int2 *coord, double c,
                  const double *tele, double *blk_ysum, typename Form<V>::Acc *blk_carry,
-                 typename Form<V>::Acc *blk_head, typename Form<V>::Part *part) {
+                 typename Form<V>::Acc *blk_head, typename Form<V>::Part *part,
+                 SlabMap sm = SlabMap{}) {
   if (ipt == 4)
     hipLaunchKernelGGL((k_spmv<V, 4, kRaw, E>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x,
-                       y, n, coord, c, tele, blk_ysum, blk_carry, blk_head, part);
+                       y, n, coord, c, tele, blk_ysum, blk_carry, blk_head, part, sm);
   else if (ipt == 16)
     hipLaunchKernelGGL((k_spmv<V, 16, kRaw, E>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x,
-                       y, n, coord, c, tele, blk_ysum, blk_carry, blk_head, part);
+                       y, n, coord, c, tele, blk_ysum, blk_carry, blk_head, part, sm);
   else
     hipLaunchKernelGGL((k_spmv<V, 8, kRaw, E>), dim3(nb), dim3(kThreads), 0, s, rp, col, val, x,
-                       y, n, coord, c, tele, blk_ysum, blk_carry, blk_head, part);
+                       y, n, coord, c, tele, blk_ysum, blk_carry, blk_head, part, sm);
+}
+
+// Per SpMV workgroup b: the slab of its first entry and the next slab's
+// first entry (es holds the slab starts, es[ns] = nnz).
+__global__ __launch_bounds__(256) void k_tile_slab(const int2 *__restrict__ coord, int32_t nb,
+                                                   const int32_t *__restrict__ es, int32_t ns,
+                                                   int2 *__restrict__ ts) {
+  for (int32_t b = blockIdx.x * 256 + threadIdx.x; b < nb; b += gridDim.x * 256) {
+    const int32_t j = coord[b].y;
+    int32_t lo = 0, hi = ns - 1;   // last d with es[d] <= j
+    while (lo < hi) {
+      const int32_t m = (lo + hi + 1) >> 1;
+      if (es[m] <= j)
+        lo = m;
+      else
+        hi = m - 1;
+    }
+    ts[b] = make_int2(lo, es[lo + 1]);
+  }
+}
+
+// es[d] = first segmented entry of slab d (tile 0's offset), es[ns] = nnz.
+__global__ void k_slab_starts(const uint32_t *__restrict__ eoff, int32_t ns, int64_t nnz,
+                              int32_t *__restrict__ es) {
+  for (int d = threadIdx.x; d <= ns; d += blockDim.x) es[d] = d < ns ? int32_t(eoff[d]) : int32_t(nnz);
 }
 
 // info[0] = P, info[1 + d] = first pair of slab d (d <= ns; slab ns = the
@@ -1951,6 +2039,7 @@ struct SegInfo {
   int64_t P = 0;
   bool relabelled = false;   // the count pass wrote the relabelled entries
   bool scaled = false;       // ... as counts (degree-scaled form), stored so by the scatter
+  bool packed = false;       // ... packed with their column inside the slab (seg_col only)
 };
 
 // In-place slab-major offsets of a tile-by-tile count matrix (k_col_sums,
@@ -1999,27 +2088,29 @@ pp_status build_segments(const Layout<V> &L, const int32_t *rp, int32_t *col, V 
   hipLaunchKernelGGL(k_partition, dim3(grid_for(int64_t(ntiles) + 1, 256, 4096)), dim3(256), 0, s,
                      rp, n32, int32_t(nnz), ntiles, kSegTile, L.seg_coord);
   bool counts = false;
+  int32_t maxcol = 0;
   if (rl && scaled) {
-    pp_status st = fill_i32(reinterpret_cast<int32_t *>(rl->bad), 1, 0, s);
+    pp_status st = fill_i32(reinterpret_cast<int32_t *>(rl->bad), 2, 0, s);
     if (st != PP_OK) return st;
     hipLaunchKernelGGL((k_seg_tile<V, uint8_t, false, true>), dim3(ntiles), dim3(kThreads), 0, s,
                        rp, col, cnt, n32, *rl, L.seg_coord, sbits, ns, dbits, ntiles, L.seg_cnt,
-                       L.seg_pcnt, L.seg_fmask, L.seg_lmask, nullptr, nullptr, nullptr, nullptr);
+                       L.seg_pcnt, L.seg_fmask, L.seg_lmask, nullptr, nullptr, nullptr, nullptr, 0);
     PP_LAUNCHED("k_seg_tile (count, scaled)");
-    uint32_t bad = 1;
-    PP_HIP(hipMemcpyAsync(&bad, rl->bad, sizeof(bad), hipMemcpyDeviceToHost, s));
+    uint32_t flags[2] = {1u, 0u};
+    PP_HIP(hipMemcpyAsync(flags, rl->bad, sizeof(flags), hipMemcpyDeviceToHost, s));
     PP_HIP(hipStreamSynchronize(s));
-    counts = bad == 0;
+    counts = flags[0] == 0;
+    maxcol = int32_t(flags[1]);
   }
   if (rl && !counts) {
     hipLaunchKernelGGL((k_seg_tile<V, V, false, true>), dim3(ntiles), dim3(kThreads), 0, s, rp,
                        col, val, n32, *rl, L.seg_coord, sbits, ns, dbits, ntiles, L.seg_cnt,
-                       L.seg_pcnt, L.seg_fmask, L.seg_lmask, nullptr, nullptr, nullptr, nullptr);
+                       L.seg_pcnt, L.seg_fmask, L.seg_lmask, nullptr, nullptr, nullptr, nullptr, 0);
   } else if (!rl) {
     hipLaunchKernelGGL((k_seg_tile<V, V, false, false>), dim3(ntiles), dim3(kThreads), 0, s, rp,
                        col, val, n32, RelabelSrc{}, L.seg_coord, sbits, ns, dbits, ntiles,
                        L.seg_cnt, L.seg_pcnt, L.seg_fmask, L.seg_lmask, nullptr, nullptr, nullptr,
-                       nullptr);
+                       nullptr, 0);
   }
   out->relabelled = rl != nullptr;
   hipLaunchKernelGGL(k_seg_cont, dim3(grid_for(ntiles, 256, 4096)), dim3(256), 0, s, rp, n32,
@@ -2029,16 +2120,23 @@ pp_status build_segments(const Layout<V> &L, const int32_t *rp, int32_t *col, V 
   if (st != PP_OK) return st;
   st = col_offsets(L.seg_pcnt, ntiles, ns, L.seg_bsum, L.seg_scan, L.total, s);
   if (st != PP_OK) return st;
+  // Slab starts in the segmented entries (tile 0's offsets), for the raw
+  // SpMV of the packed count form.
+  hipLaunchKernelGGL(k_slab_starts, dim3(1), dim3(256), 0, s, L.seg_cnt, ns, nnz, L.seg_es);
+  // Counts are packed with their column inside the slab when every such
+  // column fits 24 bits (the last slab takes all columns beyond it).
+  const int32_t packed =
+      counts && sbits <= 24 && int64_t(maxcol) - (int64_t(ns - 1) << sbits) < (int64_t(1) << 24);
   if (counts)
     hipLaunchKernelGGL((k_seg_tile<V, uint8_t, true, false>), dim3(ntiles), dim3(kThreads), 0, s,
                        rp, col, cnt, n32, RelabelSrc{}, L.seg_coord, sbits, ns, dbits, ntiles,
                        L.seg_cnt, L.seg_pcnt, L.seg_fmask, nullptr, L.seg_col,
-                       reinterpret_cast<uint8_t *>(L.seg_val), L.prp, L.pair_row);
+                       reinterpret_cast<uint8_t *>(L.seg_val), L.prp, L.pair_row, packed);
   else
     hipLaunchKernelGGL((k_seg_tile<V, V, true, false>), dim3(ntiles), dim3(kThreads), 0, s, rp,
                        col, val, n32, RelabelSrc{}, L.seg_coord, sbits, ns, dbits, ntiles,
                        L.seg_cnt, L.seg_pcnt, L.seg_fmask, nullptr, L.seg_col, L.seg_val, L.prp,
-                       L.pair_row);
+                       L.pair_row, 0);
   hipLaunchKernelGGL(k_seg_info, dim3(1), dim3(256), 0, s, L.seg_pcnt, ns, nnz, L.total, L.prp,
                      L.info);
   PP_LAUNCHED("k_seg_tile (scatter)/k_seg_info");
@@ -2053,6 +2151,7 @@ pp_status build_segments(const Layout<V> &L, const int32_t *rp, int32_t *col, V 
   SegInfo si;
   si.relabelled = out->relabelled;
   si.scaled = counts;
+  si.packed = packed != 0;
   si.sbits = sbits;
   si.ns = ns;
   si.P = P;
@@ -2220,7 +2319,8 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
     PP_LAUNCHED("k_relabel_copy");
   }
   const bool scaled = si.P > 0 && si.scaled;
-  g_last_layout = (weights ? 1 : 0) | (si.P > 0 ? 2 : 0) | (scaled ? 4 : 0);
+  g_last_layout = (weights ? 1 : 0) | (si.P > 0 ? 2 : 0) | (scaled ? 4 : 0) |
+                  (scaled && si.packed ? 8 : 0);
   if (weights) {
     // r into the new labels; in the degree-scaled form divided by the
     // weights (the gathered vector is r_u / w[u]).
@@ -2245,6 +2345,9 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
                          s, L.prp, int32_t(Pr), int32_t(nnz), nbp, D, L.coord);
       hipLaunchKernelGGL(k_block_flags, dim3(grid_for(nbp, 256, 4096)), dim3(256), 0, s, L.prp,
                          int32_t(Pr), nbp, L.coord, L.carry_row, L.closes);
+      if (si.packed)
+        hipLaunchKernelGGL(k_tile_slab, dim3(grid_for(nbp, 256, 4096)), dim3(256), 0, s, L.coord,
+                           nbp, L.seg_es, si.ns, L.tile_slab);
       PP_LAUNCHED("k_partition/k_block_flags (pairs)");
 
     }
@@ -2289,7 +2392,12 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
     done = it + 1;
     if ((st = timed_begin(s)) != PP_OK) return st;
     if (si.P > 0) {
-      if (scaled)
+      if (scaled && si.packed)
+        launch_spmv<V, true, PackedCol>(ipt, nbp, s, L.prp, L.seg_col, nullptr, x, nullptr,
+                                        int32_t(Pr), L.coord, c, t_in, nullptr, L.blk_carry,
+                                        L.blk_head, L.seg_part,
+                                        SlabMap{L.seg_es, L.tile_slab, si.sbits, si.ns});
+      else if (scaled)
         launch_spmv<V, true, uint8_t>(ipt, nbp, s, L.prp, L.seg_col,
                                       reinterpret_cast<const uint8_t *>(L.seg_val), x, nullptr,
                                       int32_t(Pr), L.coord, c, t_in, nullptr, L.blk_carry,

@@ -447,7 +447,8 @@ def get_k3_config() -> tuple[int, int, int, int, int]:
 def k3_last_layout() -> dict:
     """What the last pagerank() call iterated on (see pp_k3_last_layout)."""
     v = int(lib().pp_k3_last_layout())
-    return {"relabelled": bool(v & 1), "segmented": bool(v & 2), "scaled": bool(v & 4)}
+    return {"relabelled": bool(v & 1), "segmented": bool(v & 2), "scaled": bool(v & 4),
+            "packed": bool(v & 8)}
 
 
 def set_kernel_timing(enable: bool) -> None:

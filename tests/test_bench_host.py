@@ -84,7 +84,7 @@ def test_spmv_label_names_the_timed_launches():
 def test_scaled_form_bytes_and_label():
     # Degree-scaled form: row pointers, columns, one count byte per entry,
     # the gathered vector read and the next one written, the out-degrees.
-    lay = {"relabelled": True, "segmented": True, "scaled": True}
+    lay = {"relabelled": True, "segmented": True, "scaled": True, "packed": False}
     n, z = 1 << 26, 1051749331
     assert bench.form_bytes(n, z, "f64", lay) == 4 * (n + 1) + 5 * z + 16 * n + 4 * n
     assert bench.form_bytes(n, z, "f32", lay) == 4 * (n + 1) + 5 * z + 8 * n + 4 * n
@@ -94,6 +94,13 @@ def test_scaled_form_bytes_and_label():
         "segmented SpMV iteration, slabs of 2^18 columns (degree-scaled form: entries stored as "
         "counts): k_spmv<double,16,raw,uint8> + k_fix_raw<double> + k_seg_combine<double> + "
         "k_sum_blocks")
+    # Packed with the column inside the slab: 4 bytes per entry.
+    pk = dict(lay, packed=True)
+    assert bench.form_bytes(n, z, "f64", pk) == 4 * (n + 1) + 4 * z + 16 * n + 4 * n
+    assert bench.spmv_label((16, 0, 18, 1), "f64", pk) == (
+        "segmented SpMV iteration, slabs of 2^18 columns (degree-scaled form: each entry one "
+        "4-byte word, column inside the slab and count): k_spmv<double,16,raw,packed> + "
+        "k_fix_raw<double> + k_seg_combine<double> + k_sum_blocks")
 
 
 def test_more_than_one_gpu_is_refused():

@@ -262,9 +262,11 @@ def test_scaled_form_kronecker(scale, dtype):
     w = torch.as_tensor(f.d_out).to(torch.int32).cuda()
     for slab in (scale - 4, scale - 2):
         got_s, sums_s, lay_s = scaled_run(AT, f.n, dtype, slab, w, 1)
-        assert lay_s == {"relabelled": True, "segmented": True, "scaled": True}, slab
+        assert lay_s == {"relabelled": True, "segmented": True, "scaled": True,
+                         "packed": True}, slab
         got_v, sums_v, lay_v = scaled_run(AT, f.n, dtype, slab, w, 0)
-        assert lay_v == {"relabelled": True, "segmented": True, "scaled": False}, slab
+        assert lay_v == {"relabelled": True, "segmented": True, "scaled": False,
+                         "packed": False}, slab
         for got, sums in ((got_s, sums_s), (got_v, sums_v)):
             assert rel_l1(got, want) <= TOL[dtype], (slab, rel_l1(got, want))
             assert np.abs(sums / wsums - 1).max() <= TOL[dtype], slab
@@ -309,7 +311,7 @@ def test_scaled_form_falls_back_to_values(case, dtype):
     want, wsums = oracle.pagerank(n, rp, col, val, oracle.init_r(n, 7), 20, C)
     w = torch.as_tensor(d).to(torch.int32).cuda()
     got, sums, lay = scaled_run(AT, n, dtype, scale - 3, w, 1)
-    assert lay == {"relabelled": True, "segmented": True, "scaled": False}
+    assert lay == {"relabelled": True, "segmented": True, "scaled": False, "packed": False}
     assert rel_l1(got, want) <= TOL[dtype], rel_l1(got, want)
     assert np.abs(sums / wsums - 1).max() <= TOL[dtype]
     # The same weights with the form off give the same ranks bit for bit.
