@@ -1062,7 +1062,10 @@ __device__ __forceinline__ uint32_t slab_of(int32_t c, int32_t sbits, int32_t ns
 // column, k = rint(val * w), and accepts the entry only if k is in [1, 255]
 // and V(k / w) reproduces the value bit for bit (the IEEE FP64 quotient,
 // rounded to FP32 in the FP32 form); any other entry sets *bad, and the
-// caller falls back to storing values.
+// caller falls back to storing values.  The count pass also keeps the
+// largest new column (bad[1]); with packed set, the scatter pass stores
+// each count entry as one word, its column inside the slab (< 2^24) in the
+// low 24 bits and the count in the high 8, into seg_col alone.
 struct RelabelSrc {
   const int32_t *rp0, *col0, *order;
   const int2 *lab;   // (new label, weight) of every old label
