@@ -94,7 +94,10 @@ __global__ __launch_bounds__(256) void k_din(const int32_t *__restrict__ vstart,
     best = d > best ? d : best;
   }
   best = wave_max(best);
-  if (lane_id() == 0) atomicMax(mx, best);
+  // One address for the whole grid: update it only when this wave's maximum
+  // exceeds it (it settles early, so few waves write it).
+  if (lane_id() == 0 && best > __hip_atomic_load(mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    atomicMax(mx, best);
 }
 
 // One 64-bit word per wave: bit (w mod 64) set iff column w survives.

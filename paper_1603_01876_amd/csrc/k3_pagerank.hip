@@ -704,8 +704,15 @@ __global__ __launch_bounds__(256) void k_init_sum(int64_t n, int32_t nrhs, uint3
     const U4 w = philox10(U4{uint32_t(i), uint32_t(j), 0u, 2u}, k0, k1);
     acc += w.x >> 8;
   }
+  // One atomic per workgroup (integer sums, so the order does not matter).
+  __shared__ unsigned long long sh[4];
   acc = wave_sum(acc);
-  if (lane_id() == 0 && acc) atomicAdd(ksum + j, acc);
+  if (lane_id() == 0) sh[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long t = sh[0] + sh[1] + sh[2] + sh[3];
+    if (t) atomicAdd(ksum + j, t);
+  }
 }
 
 template <typename V>

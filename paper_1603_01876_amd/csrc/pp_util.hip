@@ -39,9 +39,15 @@ __global__ __launch_bounds__(256) void k_hot_max(const int32_t *__restrict__ deg
                                                  uint32_t mask) {
   for (int32_t u = blockIdx.x * 256 + threadIdx.x; u < n; u += gridDim.x * 256) {
     const int32_t d = deg[u];
-    if (d >= 8)
-      atomicMax(&tab[hot_mix(uint32_t(u)) & mask],
-                (static_cast<unsigned long long>(uint32_t(d)) << 32) | uint32_t(u));
+    if (d >= 8) {
+      // Most vertices lose to a heavier one in their slot: read it first
+      // and write only when this key is larger.
+      unsigned long long *slot = &tab[hot_mix(uint32_t(u)) & mask];
+      const unsigned long long key =
+          (static_cast<unsigned long long>(uint32_t(d)) << 32) | uint32_t(u);
+      if (key > __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(slot, key);
+    }
   }
 }
 
