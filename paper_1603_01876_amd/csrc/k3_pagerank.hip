@@ -739,11 +739,15 @@ __global__ __launch_bounds__(256) void k_init_write(int64_t n, int32_t nrhs, uin
 // Rows are permuted with the same map, so x and y stay in one numbering; r
 // is permuted in before the first iteration and out after the last.
 
-// Bucket of a weight: clz(weight + 1), so heavier vertices sort first and
-// weights <= 0 take bucket 31, after every positive weight.
-__device__ __forceinline__ uint32_t weight_bucket(int32_t w) {
-  const int32_t wv = w > 0 ? w : 0;
-  return uint32_t(__clz(int(uint32_t(wv) + 1u)));
+// Bucket of a vertex: clz(weight + 1) for a weight > 0 (0 .. 30), so
+// heavier vertices sort first; weights <= 0 come after every positive one,
+// those with entries in their row of A^T (bucket 31) before those without
+// (bucket 32): in the degree-scaled form the latter are isolated, no entry
+// gathers them and nothing adds into their row.
+constexpr int kBuckets = 33;
+__device__ __forceinline__ uint32_t vertex_bucket(int32_t w, int32_t rowlen) {
+  if (w > 0) return uint32_t(__clz(int(uint32_t(w) + 1u)));
+  return rowlen > 0 ? 31u : 32u;
 }
 
 // The new order is a stable counting sort of the vertices by bucket, in
@@ -754,25 +758,28 @@ constexpr int kRelPer = kRelTile / kThreads;
 
 // Bucket counts of each block, bucket-major: hist[c * nblk + b].
 __global__ __launch_bounds__(kThreads) void k_bucket_count(const int32_t *__restrict__ w,
+                                                           const int32_t *__restrict__ rp,
                                                            int32_t n, int32_t nblk,
                                                            uint32_t *__restrict__ hist) {
   constexpr int kWaves = kThreads / kWave;
-  __shared__ uint32_t wh[kWaves][32];
+  __shared__ uint32_t wh[kWaves][64];
   const int tid = threadIdx.x, wv = tid / kWave, lane = lane_id();
-  if (tid < kWaves * 32) (&wh[0][0])[tid] = 0u;
+  (&wh[0][0])[tid] = 0u;
   __syncthreads();
   const int64_t base = int64_t(blockIdx.x) * kRelTile + wv * (kRelTile / kWaves);
-  int32_t ww[kRelPer];
+  int32_t ww[kRelPer], len[kRelPer];
 #pragma unroll
   for (int r = 0; r < kRelPer; ++r) {
     const int64_t v = base + r * kWave + lane;
-    ww[r] = w[v < n ? v : 0];
+    const int64_t vc = v < n ? v : 0;
+    ww[r] = w[vc];
+    len[r] = rp[vc + 1] - rp[vc];
   }
 #pragma unroll
   for (int r = 0; r < kRelPer; ++r)
-    wave_digit_rank(weight_bucket(ww[r]), base + r * kWave + lane < n, 5, wh[wv]);
+    wave_digit_rank(vertex_bucket(ww[r], len[r]), base + r * kWave + lane < n, 6, wh[wv]);
   __syncthreads();
-  if (tid < 32) {
+  if (tid < kBuckets) {
     uint32_t t = 0;
 #pragma unroll
     for (int q = 0; q < kWaves; ++q) t += wh[q][tid];
@@ -790,11 +797,11 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scatter(
     const uint32_t *__restrict__ off, int32_t *__restrict__ order, int2 *__restrict__ lab,
     int32_t *__restrict__ wnew, uint32_t *__restrict__ len2) {
   constexpr int kWaves = kThreads / kWave;
-  __shared__ uint32_t wh[kWaves][32];
-  __shared__ uint32_t s_off[32];
+  __shared__ uint32_t wh[kWaves][64];
+  __shared__ uint32_t s_off[kBuckets];
   const int tid = threadIdx.x, wv = tid / kWave, lane = lane_id();
-  if (tid < kWaves * 32) (&wh[0][0])[tid] = 0u;
-  if (tid < 32) s_off[tid] = off[int64_t(tid) * nblk + blockIdx.x];
+  (&wh[0][0])[tid] = 0u;
+  if (tid < kBuckets) s_off[tid] = off[int64_t(tid) * nblk + blockIdx.x];
   __syncthreads();
   const int64_t base = int64_t(blockIdx.x) * kRelTile + wv * (kRelTile / kWaves);
   int32_t ww[kRelPer], r0[kRelPer], r1[kRelPer];
@@ -809,13 +816,14 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scatter(
   }
 #pragma unroll
   for (int r = 0; r < kRelPer; ++r)
-    rank[r] = wave_digit_rank(weight_bucket(ww[r]), base + r * kWave + lane < n, 5, wh[wv]);
+    rank[r] = wave_digit_rank(vertex_bucket(ww[r], r1[r] - r0[r]), base + r * kWave + lane < n,
+                              6, wh[wv]);
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kRelPer; ++r) {
     const int64_t v = base + r * kWave + lane;
     if (v >= n) continue;
-    const uint32_t c = weight_bucket(ww[r]);
+    const uint32_t c = vertex_bucket(ww[r], r1[r] - r0[r]);
     uint32_t p = s_off[c] + rank[r];
     for (int q = 0; q < wv; ++q) p += wh[q][c];
     order[p] = int32_t(v);
@@ -908,13 +916,16 @@ __global__ __launch_bounds__(256) void k_hot2_fill(const uint64_t *__restrict__ 
   }
 }
 
-// rp2[n] = the entry count; npos = the vertices of weight > 0, which take
-// the new labels [0, npos) (the start of bucket 31 in the new order).
+// rp2[n] = the entry count; npos[0] = the vertices of weight > 0, which
+// take the new labels [0, npos[0]) (the start of bucket 31 in the new
+// order); npos[1] = the start of bucket 32 (weight <= 0, empty row).
 __global__ void k_set_total(int32_t *rp2, int32_t n, const int64_t *total,
-                            const uint32_t *__restrict__ start31, uint32_t *npos) {
+                            const uint32_t *__restrict__ start31,
+                            const uint32_t *__restrict__ start32, uint32_t *npos) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     rp2[n] = int32_t(*total);
-    *npos = *start31;
+    npos[0] = *start31;
+    npos[1] = *start32;
   }
 }
 
@@ -1608,8 +1619,9 @@ __global__ __launch_bounds__(kThreads) void k_pair_index(
 // queue on a shared arrival counter).
 //
 // With wdiv (degree-scaled form, every iteration but the last) the block
-// stores y[v] / wdiv[v] (0 where wdiv[v] <= 0), the vector the next
-// iteration gathers, instead of y[v]; sum(y) is formed from y either way.
+// stores y[v] / wdiv[v], the vector the next iteration gathers, instead of
+// y[v], and nothing where wdiv[v] <= 0 (such a column holds no entries, its
+// value is never gathered); sum(y) is formed from y either way.
 // With perm (the last iteration of a relabelled run) y[v] goes to
 // y[perm[v]]: the result in the caller's labels, with no pass of its own.
 template <typename V>
@@ -1666,7 +1678,7 @@ __global__ __launch_bounds__(kThreads) void k_seg_combine(
     const V yv = Form<V>::finish(acc, c, tk);
     if (wdiv) {
       const int32_t d = wdiv[R0 + i];
-      y[R0 + i] = d > 0 ? V(double(yv) / double(d)) : V(0);
+      if (d > 0) y[R0 + i] = V(double(yv) / double(d));
     } else if (perm) {
       y[perm[R0 + i]] = yv;
     } else {
@@ -1679,11 +1691,15 @@ __global__ __launch_bounds__(kThreads) void k_seg_combine(
 }
 
 // sum(y) = the nblk workgroup partials added in a fixed order by one
-// workgroup of 1024 threads; stores it and the next teleport scalar.  Each
-// thread keeps 8 running sums over interleaved partials (8 reads in flight),
-// added in a fixed order at the end.
+// workgroup of 1024 threads, plus niso rows without entries left out of
+// the combine (each y = the teleport term tele_in, rounded to FP32 when
+// f32); stores it and the next teleport scalar.  Each thread keeps 8
+// running sums over interleaved partials (8 reads in flight), added in a
+// fixed order at the end.
 __global__ __launch_bounds__(1024) void k_sum_blocks(const double *__restrict__ blk_ysum,
-                                                     int32_t nblk, double w, double *sum_out,
+                                                     int32_t nblk, int64_t niso,
+                                                     const double *__restrict__ tele_in,
+                                                     int32_t f32, double w, double *sum_out,
                                                      double *tele_out) {
   __shared__ double sh[1024 / kWave];
   double acc[8] = {};
@@ -1702,9 +1718,24 @@ __global__ __launch_bounds__(1024) void k_sum_blocks(const double *__restrict__ 
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int q = 0; q < 1024 / kWave; ++q) s += sh[q];
+    if (niso > 0) {
+      const double t = *tele_in;
+      s += double(niso) * (f32 ? double(float(t)) : t);
+    }
     if (sum_out) *sum_out = s;
     *tele_out = w * s;
   }
+}
+
+// The last iteration's rows [p0, n) in the new order, which hold no entries:
+// y = the teleport term, stored at dst[order[p]] (the caller's labels).
+template <typename V>
+__global__ __launch_bounds__(256) void k_iso_out(const int32_t *__restrict__ order, int32_t p0,
+                                                 int32_t n, const double *__restrict__ tele_in,
+                                                 V *__restrict__ dst) {
+  const V t = V(*tele_in);
+  for (int32_t p = p0 + blockIdx.x * 256 + threadIdx.x; p < n; p += gridDim.x * 256)
+    dst[order[p]] = t;
 }
 
 // ------------------------------------------------ run to a convergence test
@@ -1901,13 +1932,13 @@ Layout<V> carve(void *ws, int64_t n, int64_t nnz_cap, int32_t nrhs, size_t *byte
   L.blk_ysum = c.take<double>(size_t(nb) * nrhs);
   L.part = c.take<double>(size_t(G > G0 ? G : G0) * nrhs);
   L.keys_in = c.take<uint64_t>(size_t(n));
-  L.bucket_off = c.take<uint32_t>(size_t(32) * size_t((n + kRelTile - 1) / kRelTile));
+  L.bucket_off = c.take<uint32_t>(size_t(kBuckets) * size_t((n + kRelTile - 1) / kRelTile));
   L.order = c.take<int32_t>(size_t(n));
   L.lab = c.take<int2>(size_t(n));
   L.wnew = c.take<int32_t>(size_t(n));
   L.hot = c.take<uint64_t>(size_t(2) << hot_log2(n));
   L.bad = c.take<uint32_t>(2);
-  L.npos = c.take<uint32_t>(1);
+  L.npos = c.take<uint32_t>(2);
   L.rp2 = c.take<int32_t>(size_t(n + 1));
   {
     // One region for the relabelled entries; when the columns are
@@ -2050,6 +2081,8 @@ struct SegInfo {
   bool relabelled = false;   // the count pass wrote the relabelled entries
   bool scaled = false;       // ... as counts (degree-scaled form), stored so by the scatter
   bool packed = false;       // ... packed with their column inside the slab (seg_col only)
+  int32_t nlive = 0;         // the combine covers rows [0, nlive)
+  int32_t ncomb = 0;         // combine blocks
 };
 
 // In-place slab-major offsets of a tile-by-tile count matrix (k_col_sums,
@@ -2069,7 +2102,8 @@ pp_status col_offsets(uint32_t *cnt, int32_t ntiles, int32_t ns, uint32_t *bsum,
 
 // Segmented layout of the matrix (rp, col, val): see the kernels above.
 // The slabs cover columns [0, ncols) (columns beyond fall into the last
-// slab).  With rl the matrix is the relabelled one, whose entries (col, val) the
+// slab).  Rows [nlive, n) must have no entries: in the count form the
+// combine leaves them out (out->nlive; otherwise it covers all n).  With rl the matrix is the relabelled one, whose entries (col, val) the
 // count pass writes from rl's source matrix (out->relabelled tells whether
 // it ran).  With scaled (and rl) the count pass first tries the
 // degree-scaled form, writing the entries' counts (as bytes, into val's
@@ -2083,8 +2117,8 @@ pp_status col_offsets(uint32_t *cnt, int32_t ntiles, int32_t ns, uint32_t *bsum,
 // once more.
 template <typename V>
 pp_status build_segments(const Layout<V> &L, const int32_t *rp, int32_t *col, V *val, int64_t n,
-                         int64_t ncols, int64_t nnz, int slab_log2, const RelabelSrc *rl,
-                         bool scaled, SegInfo *out, hipStream_t s) {
+                         int64_t ncols, int64_t nlive, int64_t nnz, int slab_log2,
+                         const RelabelSrc *rl, bool scaled, SegInfo *out, hipStream_t s) {
   *out = SegInfo{};
   int sbits = slab_log2;
   if (ncols < 1) ncols = 1;
@@ -2165,6 +2199,10 @@ pp_status build_segments(const Layout<V> &L, const int32_t *rp, int32_t *col, V 
   si.sbits = sbits;
   si.ns = ns;
   si.P = P;
+  // In the count form rows [nlive, n) hold no entries and their gathered
+  // values are never read (weight <= 0): the combine leaves them out.
+  const int32_t nrow = counts ? int32_t(nlive) : n32;
+  si.nlive = nrow;
 
   // Row-major index of the pairs for the combine: per-row pair counts,
   // their scan (rpp), the combine blocks, then one workgroup per block
@@ -2183,9 +2221,10 @@ pp_status build_segments(const Layout<V> &L, const int32_t *rp, int32_t *col, V 
   st = exscan_u32(reinterpret_cast<uint32_t *>(L.rpp), reinterpret_cast<uint32_t *>(L.rpp), n + 1,
                   L.seg_scan, nullptr, s);
   if (st != PP_OK) return st;
-  const int32_t ncomb = int32_t((n + P + kCombItems - 1) / kCombItems);
+  const int32_t ncomb = int32_t((nrow + P + kCombItems - 1) / kCombItems);
+  si.ncomb = ncomb;
   hipLaunchKernelGGL(k_comb_bounds, dim3(grid_for(int64_t(ncomb) + 1, 256, 4096)), dim3(256), 0, s,
-                     L.rpp, n32, ncomb, L.cstart);
+                     L.rpp, nrow, ncomb, L.cstart);
   if ((st = fill_i32(reinterpret_cast<int32_t *>(L.bad), 1, 0, s)) != PP_OK) return st;
   hipLaunchKernelGGL(k_pair_bounds, dim3(grid_for((int64_t(ncomb) + 1) * ns, 256, 16384)),
                      dim3(256), 0, s, L.pair_row, L.seg_pcnt, L.info + 1, rp, n32, ntiles, ns,
@@ -2257,9 +2296,9 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
   Hot2 hot{nullptr, 0};
   if (weights) {
     const int32_t nrb = int32_t((n + kRelTile - 1) / kRelTile);
-    hipLaunchKernelGGL(k_bucket_count, dim3(nrb), dim3(kThreads), 0, s, weights, n32, nrb,
-                       L.bucket_off);
-    st = exscan_u32(L.bucket_off, L.bucket_off, int64_t(32) * nrb,
+    hipLaunchKernelGGL(k_bucket_count, dim3(nrb), dim3(kThreads), 0, s, weights, AT0.row_ptr, n32,
+                       nrb, L.bucket_off);
+    st = exscan_u32(L.bucket_off, L.bucket_off, int64_t(kBuckets) * nrb,
                     reinterpret_cast<uint32_t *>(L.keys_in), nullptr, s);
     if (st != PP_OK) return st;
     hipLaunchKernelGGL(k_bucket_scatter, dim3(nrb), dim3(kThreads), 0, s, weights, AT0.row_ptr,
@@ -2270,7 +2309,8 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
                     reinterpret_cast<uint32_t *>(L.keys_in), L.total, s);
     if (st != PP_OK) return st;
     hipLaunchKernelGGL(k_set_total, dim3(1), dim3(64), 0, s, L.rp2, n32, L.total,
-                       L.bucket_off + int64_t(31) * nrb, L.npos);
+                       L.bucket_off + int64_t(31) * nrb, L.bucket_off + int64_t(32) * nrb,
+                       L.npos);
     // Every entry's column goes through lab at random; the heaviest
     // sources' entries are cached in an L2-sized table in front of it (the
     // winners are picked into keys_in, free once rp2 is scanned).
@@ -2303,23 +2343,27 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
   const bool segment = k == 1 && slab_log2 > 0 && iters > 0;
   SegInfo si;
   int32_t nbp = 0, ncomb = 0;
-  int64_t Pr = 0;   // pairs (and their entries) left to the raw SpMV
+  int64_t Pr = 0;     // pairs (and their entries) left to the raw SpMV
+  int64_t npos = n;   // after relabelling: vertices of weight > 0 ...
+  int64_t nlive = n;  // ... and those with weight > 0 or entries in their row
   if (segment) {
     // The degree-scaled form needs the relabelled, segmented path and is
     // left out of runs to a convergence test (their pass reads x as ranks).
     const RelabelSrc rl{AT0.row_ptr, AT0.col, L.order, L.lab, AT0.val, hot, L.bad};
     // The slabs need only cover the columns that can hold entries: after
-    // relabelling, the vertices of weight > 0 come first (one more stream
-    // synchronisation to read their count).
-    int64_t ncols = n;
+    // relabelling, the vertices of weight > 0 come first; the vertices of
+    // weight <= 0 with an empty row come last (one more stream
+    // synchronisation to read both counts).
     if (weights) {
-      uint32_t npos = 0;
-      PP_HIP(hipMemcpyAsync(&npos, L.npos, sizeof(npos), hipMemcpyDeviceToHost, s));
+      uint32_t cnt[2] = {0u, 0u};
+      PP_HIP(hipMemcpyAsync(cnt, L.npos, sizeof(cnt), hipMemcpyDeviceToHost, s));
       PP_HIP(hipStreamSynchronize(s));
-      ncols = int64_t(npos);
+      npos = int64_t(cnt[0]);
+      nlive = int64_t(cnt[1]);
     }
-    st = build_segments<V>(L, rp, const_cast<int32_t *>(col), const_cast<V *>(val), n, ncols, nnz,
-                           slab_log2, weights ? &rl : nullptr, g_cfg.scaled != 0 && !cv, &si, s);
+    st = build_segments<V>(L, rp, const_cast<int32_t *>(col), const_cast<V *>(val), n, npos,
+                           nlive, nnz, slab_log2, weights ? &rl : nullptr,
+                           g_cfg.scaled != 0 && !cv, &si, s);
     if (st != PP_OK) return st;
   }
   if (weights && !si.relabelled) {
@@ -2333,10 +2377,11 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
                   (scaled && si.packed ? 8 : 0);
   if (weights) {
     // r into the new labels; in the degree-scaled form divided by the
-    // weights (the gathered vector is r_u / w[u]).
+    // weights (the gathered vector is r_u / w[u]), for the vertices of
+    // weight > 0 only: no entry gathers the others.
     if (scaled)
-      hipLaunchKernelGGL(k_permute_in_scaled<V>, dim3(gN), dim3(256), 0, s, r, L.order, L.wnew,
-                         n32, L.x2);
+      hipLaunchKernelGGL(k_permute_in_scaled<V>, dim3(grid_for(npos, 256, 8192)), dim3(256), 0, s,
+                         r, L.order, L.wnew, int32_t(npos), L.x2);
     else
       hipLaunchKernelGGL(k_permute_in<V>, dim3(gNK), dim3(256), 0, s, r, L.order, n32, k, T,
                          L.x2);
@@ -2350,7 +2395,7 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
     if (si.P > 0) {
       Pr = si.P;
       nbp = int32_t((Pr + nnz + D - 1) / D);
-      ncomb = int32_t((n + si.P + kCombItems - 1) / kCombItems);
+      ncomb = si.ncomb;
       hipLaunchKernelGGL(k_partition, dim3(grid_for(int64_t(nbp) + 1, 256, 4096)), dim3(256), 0,
                          s, L.prp, int32_t(Pr), int32_t(nnz), nbp, D, L.coord);
       hipLaunchKernelGGL(k_block_flags, dim3(grid_for(nbp, 256, 4096)), dim3(256), 0, s, L.prp,
@@ -2427,8 +2472,15 @@ pp_status run_pagerank(const pp_csr &AT0, int32_t nrhs, int32_t iters, double c,
                          scaled && it + 1 < iters ? L.wnew : nullptr,
                          last_out ? L.order : nullptr);
       out_done = last_out;
-      hipLaunchKernelGGL(k_sum_blocks, dim3(1), dim3(1024), 0, s, L.blk_ysum, ncomb, w, s_out,
-                         t_out);
+      // Rows [nlive, n) (count form only, whose last iteration is always
+      // last_out) hold y = the teleport term: added to the sum as a count,
+      // stored by the last iteration alone.
+      const int64_t niso = n - si.nlive;
+      if (last_out && niso > 0)
+        hipLaunchKernelGGL(k_iso_out<V>, dim3(grid_for(niso, 256, 8192)), dim3(256), 0, s, L.order,
+                           si.nlive, n32, t_in, r);
+      hipLaunchKernelGGL(k_sum_blocks, dim3(1), dim3(1024), 0, s, L.blk_ysum, ncomb, niso, t_in,
+                         int32_t(sizeof(V) == 4), w, s_out, t_out);
       if ((st = timed_end(s)) != PP_OK) return st;
       PP_LAUNCHED("k_spmv raw/k_fix_raw/k_seg_combine");
     } else if (k == 1) {
