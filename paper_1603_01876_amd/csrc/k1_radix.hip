@@ -28,6 +28,15 @@ constexpr int kTile = kThreads * kPerThread;     // 2048 keys
 constexpr int kWaves = kThreads / kWave;         // 4
 constexpr int kWaveKeys = kTile / kWaves;        // 512
 
+// Tile of workgroup i of g.  Workgroups are dealt to the 8 XCDs in turn
+// (workgroup i runs on XCD i mod 8); this gives each XCD one contiguous
+// range of tiles, so the short runs that neighbouring tiles store next to
+// each other (a digit's keys, a digit's counts) meet in one XCD's L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t i, int64_t g) {
+  const int64_t q = g >> 3, r = g & 7, x = i & 7;
+  return x * q + (x < r ? x : r) + (i >> 3);
+}
+
 __device__ __forceinline__ uint32_t digit_of(uint64_t key, int shift, uint32_t dmask) {
   return uint32_t(key >> (32 + shift)) & dmask;
 }
@@ -61,7 +70,8 @@ __global__ __launch_bounds__(kThreads) void k_radix_count(RadixIn in, int64_t m,
   for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&wh[0][0])[i] = 0u;
   __syncthreads();
   const int w = threadIdx.x / kWave;
-  const int64_t base = int64_t(blockIdx.x) * kTile + int64_t(w) * kWaveKeys;
+  const int64_t tile = xcd_tile(blockIdx.x, ntiles);
+  const int64_t base = tile * kTile + int64_t(w) * kWaveKeys;
   const uint32_t dmask = (1u << bits) - 1u;
   // All of the thread's reads first (unconditional, index clamped), so they
   // are in flight together; a read under a per-lane condition would be
@@ -82,7 +92,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_count(RadixIn in, int64_t m,
     if (base + r * kWave + lane_id() < m) atomicAdd(&wh[w][digit_of(keys[r], shift, dmask)], 1u);
   __syncthreads();
   for (int d = threadIdx.x; d <= int(dmask); d += kThreads)
-    counts[int64_t(d) * ntiles + blockIdx.x] = wh[0][d] + wh[1][d] + wh[2][d] + wh[3][d];
+    counts[int64_t(d) * ntiles + tile] = wh[0][d] + wh[1][d] + wh[2][d] + wh[3][d];
 }
 
 // Scatter: every key's position is (digit's global offset for this tile) +
@@ -109,7 +119,8 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(RadixIn in, RadixOut
   for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&wh[0][0])[i] = 0u;
   __syncthreads();
   const int w = threadIdx.x / kWave;
-  const int64_t tile0 = int64_t(blockIdx.x) * kTile;
+  const int64_t tile = xcd_tile(blockIdx.x, ntiles);
+  const int64_t tile0 = tile * kTile;
   const int64_t base = tile0 + int64_t(w) * kWaveKeys;
   uint64_t keys[kPerThread];
   uint32_t rank[kPerThread];
@@ -150,7 +161,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(RadixIn in, RadixOut
   const uint32_t first = block_exscan256(total, s_scan, &all);
   if (d <= int(dmask)) {
     s_tile_off[d] = first;
-    s_glob[d] = offsets[int64_t(d) * ntiles + blockIdx.x];
+    s_glob[d] = offsets[int64_t(d) * ntiles + tile];
   }
   __syncthreads();
 #pragma unroll
