@@ -28,15 +28,6 @@ constexpr int kTile = kThreads * kPerThread;     // 2048 keys
 constexpr int kWaves = kThreads / kWave;         // 4
 constexpr int kWaveKeys = kTile / kWaves;        // 512
 
-// Tile of workgroup i of g.  Workgroups are dealt to the 8 XCDs in turn
-// (workgroup i runs on XCD i mod 8); this gives each XCD one contiguous
-// range of tiles, so the short runs that neighbouring tiles store next to
-// each other (a digit's keys, a digit's counts) meet in one XCD's L2.
-__device__ __forceinline__ int64_t xcd_tile(int64_t i, int64_t g) {
-  const int64_t q = g >> 3, r = g & 7, x = i & 7;
-  return x * q + (x < r ? x : r) + (i >> 3);
-}
-
 __device__ __forceinline__ uint32_t digit_of(uint64_t key, int shift, uint32_t dmask) {
   return uint32_t(key >> (32 + shift)) & dmask;
 }
@@ -70,7 +61,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_count(RadixIn in, int64_t m,
   for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&wh[0][0])[i] = 0u;
   __syncthreads();
   const int w = threadIdx.x / kWave;
-  const int64_t tile = xcd_tile(blockIdx.x, ntiles);
+  const int64_t tile = xcd_block(blockIdx.x, ntiles);
   const int64_t base = tile * kTile + int64_t(w) * kWaveKeys;
   const uint32_t dmask = (1u << bits) - 1u;
   // All of the thread's reads first (unconditional, index clamped), so they
@@ -119,7 +110,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(RadixIn in, RadixOut
   for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&wh[0][0])[i] = 0u;
   __syncthreads();
   const int w = threadIdx.x / kWave;
-  const int64_t tile = xcd_tile(blockIdx.x, ntiles);
+  const int64_t tile = xcd_block(blockIdx.x, ntiles);
   const int64_t tile0 = tile * kTile;
   const int64_t base = tile0 + int64_t(w) * kWaveKeys;
   uint64_t keys[kPerThread];

@@ -60,6 +60,17 @@ __device__ __forceinline__ uint64_t lanes_below() {
   return (1ull << lane_id()) - 1ull;
 }
 
+// Logical block of workgroup i of g.  Workgroups are dealt to the 8 XCDs in
+// turn (workgroup i runs on XCD i mod 8); this gives each XCD one contiguous
+// range of blocks, so the short runs that neighbouring blocks store next to
+// each other (a digit's keys or counts) meet in one XCD's L2 instead of
+// being written back by several.  (Blocks whose reads are the bottleneck
+// measured slower this way.)
+__device__ __forceinline__ int64_t xcd_block(int64_t i, int64_t g) {
+  const int64_t q = g >> 3, r = g & 7, x = i & 7;
+  return x * q + (x < r ? x : r) + (i >> 3);
+}
+
 // Rank of this lane's digit d among the earlier lanes of the wave holding
 // the same digit, plus the wave's running count wh[d] of that digit from
 // earlier calls; advances wh[d] by the digit's lanes in this call.  Digits
