@@ -318,3 +318,55 @@ def test_scaled_form_falls_back_to_values(case, dtype):
     got_v, sums_v, _ = scaled_run(AT, n, dtype, scale - 3, w, 0)
     assert got.tobytes() == got_v.tobytes() and sums.tobytes() == sums_v.tobytes()
 
+
+
+def count_matrix(n, rng, src_frac, dst_frac, max_deg=40):
+    """CSR(A) of a count matrix normalised by out-degree (val = count / d_out,
+    one IEEE FP64 quotient per entry, as K2 builds it): sources are a random
+    src_frac of the vertices, each sending 1..max_deg edges (repeats allowed)
+    to targets drawn from a random dst_frac of them."""
+    src = np.flatnonzero(rng.random(n) < src_frac)
+    dst = np.flatnonzero(rng.random(n) < dst_frac)
+    deg = rng.integers(1, max_deg + 1, src.size)
+    rows = np.repeat(src, deg)
+    cols = dst[rng.integers(0, dst.size, rows.size)]
+    key, cnt = np.unique(rows * n + cols, return_counts=True)
+    rows, cols = key // n, key % n
+    rp = np.concatenate([[0], np.cumsum(np.bincount(rows, minlength=n))]).astype(np.int64)
+    d_out = np.bincount(rows, weights=cnt, minlength=n).astype(np.int64)
+    val = cnt / d_out[rows].astype(np.float64)
+    return rp, cols.astype(np.int32), val, d_out
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["mixed", "none-isolated", "mostly-isolated"])
+def test_scaled_form_isolated_vertices(case, dtype):
+    # In the count form the vertices of weight 0 with no entries in their
+    # row of A^T are sorted last and left out of the combine: their y is the
+    # teleport term, added to sum(y) as a count and stored by the last
+    # iteration alone.  Cases: all four kinds of vertex (weight > 0 or 0,
+    # row empty or not); every vertex a target (nothing isolated); few
+    # sources and targets (most vertices isolated).
+    n = 30011
+    rng = np.random.default_rng({"mixed": 41, "none-isolated": 42, "mostly-isolated": 43}[case])
+    fr = {"mixed": (0.4, 0.5), "none-isolated": (0.5, 1.0), "mostly-isolated": (0.03, 0.02)}[case]
+    rp, col, val, d_out = count_matrix(n, rng, *fr)
+    indeg = np.bincount(col, minlength=n)
+    if case == "none-isolated":
+        assert ((d_out > 0) | (indeg > 0)).all()
+    else:
+        assert ((d_out == 0) & (indeg == 0)).sum() > n // 10
+    trp, tcol, tval = oracle.transpose_csr(n, rp, col, val)
+    AT = pp.CSR.from_arrays(n, trp, tcol, tval, dtype)
+    want, wsums = oracle.pagerank(n, rp, col, val, oracle.init_r(n, 7), 20, C)
+    w = torch.as_tensor(d_out).to(torch.int32).cuda()
+    # slabs narrow enough for several of them over the vertices of weight > 0
+    for slab in ((5, 8) if case == "mostly-isolated" else (8, 11)):
+        got, sums, lay = scaled_run(AT, n, dtype, slab, w, 1)
+        assert lay == {"relabelled": True, "segmented": True, "scaled": True, "packed": True}
+        assert rel_l1(got, want) <= TOL[dtype], (slab, rel_l1(got, want))
+        assert np.abs(sums / wsums - 1).max() <= TOL[dtype], slab
+        # The isolated vertices hold the teleport term of the last step.
+        iso = (d_out == 0) & (indeg == 0)
+        if iso.any():
+            assert np.abs(got[iso] / want[iso] - 1).max() <= TOL[dtype]
