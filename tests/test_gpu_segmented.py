@@ -245,10 +245,10 @@ def test_segmented_structured_more(case, dtype):
 # entry as its integer count and gathers r_i / d_out[i] (A = D^-1 C, Sec.
 # IV.C); any entry that is not count / weight with a count in [1, 255] keeps
 # the values.  Either way the ranks meet the oracle's tolerance.
-def scaled_run(AT, n, dtype, slab, w, scaled, seed=7):
+def scaled_run(AT, n, dtype, slab, w, scaled, seed=7, iters=20):
     pp.set_k3_config(8, 0, slab, scaled)
     r = pp.init_r(n, seed, dtype)
-    sums = pp.pagerank(AT, r, iters=20, c=C, weights=w)
+    sums = pp.pagerank(AT, r, iters=iters, c=C, weights=w)
     return host(r), host(sums), pp.k3_last_layout()
 
 
@@ -339,8 +339,9 @@ def count_matrix(n, rng, src_frac, dst_frac, max_deg=40):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("case", ["mixed", "none-isolated", "mostly-isolated"])
-def test_scaled_form_isolated_vertices(case, dtype):
+@pytest.mark.parametrize("case,iters", [("mixed", 20), ("mixed", 1), ("mixed", 2),
+                                        ("none-isolated", 20), ("mostly-isolated", 20)])
+def test_scaled_form_isolated_vertices(case, iters, dtype):
     # In the count form the vertices of weight 0 with no entries in their
     # row of A^T are sorted last and left out of the combine: their y is the
     # teleport term, added to sum(y) as a count and stored by the last
@@ -358,11 +359,11 @@ def test_scaled_form_isolated_vertices(case, dtype):
         assert ((d_out == 0) & (indeg == 0)).sum() > n // 10
     trp, tcol, tval = oracle.transpose_csr(n, rp, col, val)
     AT = pp.CSR.from_arrays(n, trp, tcol, tval, dtype)
-    want, wsums = oracle.pagerank(n, rp, col, val, oracle.init_r(n, 7), 20, C)
+    want, wsums = oracle.pagerank(n, rp, col, val, oracle.init_r(n, 7), iters, C)
     w = torch.as_tensor(d_out).to(torch.int32).cuda()
     # slabs narrow enough for several of them over the vertices of weight > 0
     for slab in ((5, 8) if case == "mostly-isolated" else (8, 11)):
-        got, sums, lay = scaled_run(AT, n, dtype, slab, w, 1)
+        got, sums, lay = scaled_run(AT, n, dtype, slab, w, 1, iters=iters)
         assert lay == {"relabelled": True, "segmented": True, "scaled": True, "packed": True}
         assert rel_l1(got, want) <= TOL[dtype], (slab, rel_l1(got, want))
         assert np.abs(sums / wsums - 1).max() <= TOL[dtype], slab
