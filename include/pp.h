@@ -226,8 +226,9 @@ pp_status pp_init_r(int64_t n, int32_t nrhs, uint64_t seed, pp_dtype dt, void *r
  * order_weights (device, n int32, may be NULL): per-vertex weights, e.g.
  * pp_filter's d_out.  When given, the iterations run on a copy of the
  * matrix (in the workspace) whose vertices are relabelled by decreasing
- * floor(log2(weight + 1)), ties in label order, so that frequently gathered
- * ranks share cache lines; r is permuted in and out, so inputs and outputs
+ * floor(log2(weight + 1)) for weights > 0, then weights <= 0 with entries
+ * in their row of A^T, then weights <= 0 without, ties in label order, so
+ * that frequently gathered ranks share cache lines; r is permuted in and out, so inputs and outputs
  * keep the original labels.  When the weights are pp_filter's d_out for
  * this matrix, a segmented run also stores the entries as integer counts
  * and gathers r_i / d_out[i] (the degree-scaled form; see scaled_form in
