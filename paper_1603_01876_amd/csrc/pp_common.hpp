@@ -104,10 +104,11 @@ struct U4 {
 __device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t a = 0xD2511F53u * c.x;
-    const uint32_t ah = __umulhi(0xD2511F53u, c.x);
-    const uint32_t b = 0xCD9E8D57u * c.z;
-    const uint32_t bh = __umulhi(0xCD9E8D57u, c.z);
+    // Each 32 x 32 -> 64-bit product in one instruction (low and high words).
+    const uint64_t pa = uint64_t(0xD2511F53u) * c.x;
+    const uint64_t pb = uint64_t(0xCD9E8D57u) * c.z;
+    const uint32_t a = uint32_t(pa), ah = uint32_t(pa >> 32);
+    const uint32_t b = uint32_t(pb), bh = uint32_t(pb >> 32);
     c = U4{bh ^ c.y ^ k0, b, ah ^ c.w ^ k1, a};
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
