@@ -106,34 +106,62 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(RadixIn in, RadixOut
   __shared__ uint32_t s_glob[256];       // global position of that slot
   __shared__ uint32_t s_scan[4];
   __shared__ uint64_t s_keys[kTile];
+  // While the keys are ranked, s_keys holds each wave's 256 digit masks.
+  static_assert(kWaves * 256 <= kTile, "digit masks alias the key staging");
+  unsigned long long *masks = reinterpret_cast<unsigned long long *>(s_keys) + (threadIdx.x / kWave) * 256;
   const uint32_t dmask = (1u << bits) - 1u;
-  for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&wh[0][0])[i] = 0u;
+  for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) {
+    (&wh[0][0])[i] = 0u;
+    s_keys[i] = 0ull;
+  }
   __syncthreads();
   const int w = threadIdx.x / kWave;
   const int64_t tile = xcd_block(blockIdx.x, ntiles);
   const int64_t tile0 = tile * kTile;
   const int64_t base = tile0 + int64_t(w) * kWaveKeys;
+  // All of the thread's reads first (indices clamped into range, so every
+  // read is unconditional and they are in flight together), then the ranks.
   uint64_t keys[kPerThread];
   uint32_t rank[kPerThread];
   uint32_t bad = 0;
+  if constexpr (kSrcSep) {
+    if (check_n > 0) {
+      int64_t hv[kPerThread], lv[kPerThread], pv[kPerThread];
 #pragma unroll
-  for (int r = 0; r < kPerThread; ++r) {
-    const int64_t i = base + r * kWave + lane_id();
-    const bool valid = i < m;
-    if constexpr (kSrcSep) {
-      if (valid && check_n > 0) {
-        const int64_t hi = in.hi[i], lo = in.lo[i];
-        if (hi < 0 || hi >= check_n || lo < 0 || lo >= check_n) bad |= 1u;
-        if (check_sorted && i > 0 && in.lo[i - 1] > lo) bad |= 2u;
-        keys[r] = (uint64_t(hi) << 32) | (uint64_t(lo) & 0xFFFFFFFFull);
-      } else {
-        keys[r] = valid ? load_key<kSrcSep>(in, i) : 0ull;
+      for (int r = 0; r < kPerThread; ++r) {
+        const int64_t i = base + r * kWave + lane_id();
+        const int64_t ic = i < m ? i : m - 1;
+        hv[r] = in.hi[ic];
+        lv[r] = in.lo[ic];
+        pv[r] = in.lo[ic > 0 ? ic - 1 : 0];
+      }
+#pragma unroll
+      for (int r = 0; r < kPerThread; ++r) {
+        const int64_t i = base + r * kWave + lane_id();
+        if (i < m) {
+          if (hv[r] < 0 || hv[r] >= check_n || lv[r] < 0 || lv[r] >= check_n) bad |= 1u;
+          if (check_sorted && i > 0 && pv[r] > lv[r]) bad |= 2u;
+        }
+        keys[r] = (uint64_t(hv[r]) << 32) | (uint64_t(lv[r]) & 0xFFFFFFFFull);
       }
     } else {
-      keys[r] = valid ? load_key<kSrcSep>(in, i) : 0ull;
+#pragma unroll
+      for (int r = 0; r < kPerThread; ++r) {
+        const int64_t i = base + r * kWave + lane_id();
+        keys[r] = load_key<kSrcSep>(in, i < m ? i : m - 1);
+      }
     }
-    rank[r] = wave_digit_rank(digit_of(keys[r], shift, dmask), valid, bits, wh[w]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r) {
+      const int64_t i = base + r * kWave + lane_id();
+      keys[r] = load_key<kSrcSep>(in, i < m ? i : m - 1);
+    }
   }
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r)
+    rank[r] = wave_digit_rank_lds(digit_of(keys[r], shift, dmask),
+                                  base + r * kWave + lane_id() < m, wh[w], masks);
   if (bad && flag) atomicOr(flag, bad);
   __syncthreads();
   // Per digit: prefix over waves (in place), tile total, then an exclusive

@@ -95,6 +95,32 @@ __device__ __forceinline__ uint32_t wave_digit_rank(uint32_t d, bool valid, int 
   return before + uint32_t(__popcll(below));
 }
 
+// The same rank with the lanes of equal digit found through LDS instead of
+// one ballot per digit bit: every lane ORs its own bit into its digit's
+// 64-bit word of masks (the wave's own 2^bits words, zero on entry), reads
+// the word back (the lanes holding that digit), and the digit's lowest lane
+// clears it again.  A wave's LDS instructions execute in order, and the
+// fences keep the compiler from moving one lane's clear past another's read.
+__device__ __forceinline__ uint32_t wave_digit_rank_lds(uint32_t d, bool valid, uint32_t *wh,
+                                                        unsigned long long *masks) {
+  if (valid) atomicOr(&masks[d], 1ull << lane_id());
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const uint64_t match = valid ? uint64_t(masks[d]) : 0ull;
+  const uint64_t below = match & lanes_below();
+  uint32_t before = 0;
+  if (valid) before = wh[d];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (valid && below == 0) {
+    wh[d] = before + uint32_t(__popcll(match));
+    masks[d] = 0ull;
+  }
+  return before + uint32_t(__popcll(below));
+}
+
 // Philox4x32-10 block (Salmon et al., SC'11): ten rounds; each round
 // multiplies counter words 0 and 2 by fixed odd constants, swaps the halves
 // across the state and mixes in a key that advances by a Weyl step.
