@@ -108,7 +108,8 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(RadixIn in, RadixOut
   __shared__ uint64_t s_keys[kTile];
   // While the keys are ranked, s_keys holds each wave's 256 digit masks.
   static_assert(kWaves * 256 <= kTile, "digit masks alias the key staging");
-  unsigned long long *masks = reinterpret_cast<unsigned long long *>(s_keys) + (threadIdx.x / kWave) * 256;
+  unsigned long long *masks =
+      reinterpret_cast<unsigned long long *>(s_keys) + (threadIdx.x / kWave) * 256;
   const uint32_t dmask = (1u << bits) - 1u;
   for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) {
     (&wh[0][0])[i] = 0u;
