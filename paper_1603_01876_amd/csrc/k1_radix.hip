@@ -6,12 +6,13 @@
 // over ceil(S/8) passes).  A pass is three launches with no waiting between
 // workgroups: per-tile digit counts, a device-wide exclusive scan of the
 // digit-major count table, and a scatter that ranks each key inside its
-// tile.  A tile is 2048 keys; each of the four waves owns 512 contiguous
-// keys and walks them in 8 rounds of 64, so every load is a contiguous
+// tile.  A tile is 4096 keys; each of the four waves owns 1024 contiguous
+// keys and walks them in 16 rounds of 64, so every load is a contiguous
 // 512 B wave access and the rank of a key among equal digits follows the
 // input order (stability).  Inside a round the lanes holding the same digit
-// are found with one ballot per digit bit; the lowest such lane advances the
-// wave's LDS counter for that digit by the group's population count.
+// are found through per-wave digit mask words in LDS; the lowest such lane
+// advances the wave's LDS counter for that digit by the group's population
+// count.  Each XCD takes one contiguous range of tiles.
 //
 // The first pass can read two int64 arrays (packing on the fly) and the
 // last pass can write two int64 arrays (unpacking), so K1 reads and writes
@@ -23,10 +24,10 @@ namespace pp {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kPerThread = 8;                    // 4096-key tiles: 2-3% slower at S = 26
-constexpr int kTile = kThreads * kPerThread;     // 2048 keys
+constexpr int kPerThread = 16;                   // 2048, 6144, 8192-key tiles slower
+constexpr int kTile = kThreads * kPerThread;     // 4096 keys
 constexpr int kWaves = kThreads / kWave;         // 4
-constexpr int kWaveKeys = kTile / kWaves;        // 512
+constexpr int kWaveKeys = kTile / kWaves;        // 1024
 
 __device__ __forceinline__ uint32_t digit_of(uint64_t key, int shift, uint32_t dmask) {
   return uint32_t(key >> (32 + shift)) & dmask;
