@@ -200,8 +200,9 @@ __global__ __launch_bounds__(256) void k_narrow(const int32_t *__restrict__ d_ou
 
 __device__ __forceinline__ int32_t dout_get(HotTab h, const uint16_t *__restrict__ d16,
                                             const int32_t *__restrict__ d_out, int32_t u) {
-  const uint64_t e = h.tab[hot_mix(uint32_t(u)) & h.mask];
-  if (uint32_t(e) == uint32_t(u)) return int32_t(uint32_t(e >> 32));
+  const uint32_t m = hot_mix(uint32_t(u));
+  const uint32_t e = h.tab[m & h.mask];
+  if (((e ^ m) & ~h.mask) == 0u && (e & h.mask) != h.mask) return int32_t(e & h.mask);
   const uint32_t d = d16[u];
   return d != 65535u ? int32_t(d) : d_out[u];
 }

@@ -211,13 +211,15 @@ __device__ __forceinline__ T load_acquire(const T *p) {
 // int32 table that a kernel reads at random once per matrix entry.  Random
 // reads that miss L2 run about five times slower than ones that hit it,
 // whether or not the big table fits the Infinity Cache; the cache is sized
-// to stay in one XCD's L2.  Slot hot_mix(u) & mask holds the vertex of
-// highest degree hashed there as (value << 32 | u), or a key no vertex has.
-// A lookup that finds another vertex reads the big table, so results never
-// depend on what the cache holds.  hot_mix is the "lowbias32" integer
-// finaliser (C. Wellons, 2018).
+// to stay in one XCD's L2.  Slot m & mask, m = hot_mix(u), holds the vertex
+// of highest degree hashed there in 32 bits: the bits of m above mask (which
+// with the slot identify u) and below them min(value, mask), mask meaning
+// "read the big table" (an empty slot is all ones, which at worst sends a
+// lookup to the big table).  A lookup that finds another vertex reads the
+// big table too, so results never depend on what the cache holds.  hot_mix
+// is the "lowbias32" integer finaliser (C. Wellons, 2018).
 struct HotTab {
-  const uint64_t *tab;
+  const uint32_t *tab;
   uint32_t mask;
 };
 
@@ -230,11 +232,6 @@ __device__ __forceinline__ uint32_t hot_mix(uint32_t x) {
   return x;
 }
 
-__device__ __forceinline__ int32_t hot_get(HotTab h, const int32_t *__restrict__ full, int32_t u) {
-  const uint64_t e = h.tab[hot_mix(uint32_t(u)) & h.mask];
-  return uint32_t(e) == uint32_t(u) ? int32_t(uint32_t(e >> 32)) : full[u];
-}
-
 // ------------------------------------------------------ host launchers
 // Each .hip file exposes plain host functions that enqueue its kernels.
 
@@ -243,9 +240,11 @@ pp_status fill_i32(int32_t *p, int64_t n, int32_t value, hipStream_t s);
 pp_status fill_u64(uint64_t *p, int64_t n, uint64_t value, hipStream_t s);
 pp_status copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t s);
 
-// Hot-vertex cache (pp_util.hip): 2^hot_log2(n) slots (at most 2^17,
-// 1 MiB), filled from degrees deg[0..n) (vertices of degree < 8 are left
-// out) with values full[u]; hot_bytes(n) is the table's size.
+// Hot-vertex cache (pp_util.hip): hot_log2(n) sizes the selection (about
+// n / 4 slots, at most 2^17); hot_build's 32-bit table has twice as many
+// slots (at most 2^18, 1 MiB), filled from degrees deg[0..n) (vertices of
+// degree < 8 are left out) with values full[u]; hot_bytes(n) is its
+// workspace (the winners' 64-bit keys, then the table).
 int hot_log2(int64_t n);
 size_t hot_bytes(int64_t n);
 // hot_select only picks the winners: tab[slot] = (deg[u] << 32 | u) of the

@@ -32,7 +32,10 @@ int hot_log2(int64_t n) {
   return lg;
 }
 
-size_t hot_bytes(int64_t n) { return sizeof(uint64_t) << hot_log2(n); }
+// hot_build's table: twice the slots of hot_log2, 32 bits each.
+static int hot32_log2(int64_t n) { return hot_log2(n) + 1; }
+
+size_t hot_bytes(int64_t n) { return size_t(8 + 4) << hot32_log2(n); }
 
 __global__ __launch_bounds__(256) void k_hot_max(const int32_t *__restrict__ deg, int32_t n,
                                                  unsigned long long *__restrict__ tab,
@@ -51,14 +54,21 @@ __global__ __launch_bounds__(256) void k_hot_max(const int32_t *__restrict__ deg
   }
 }
 
-// Winner (degree << 32 | u) -> (full[u] << 32 | u); empty slots get key
-// 0xFFFFFFFF, which no vertex label (< 2^31) equals.
+// Winner key (degree << 32 | u) of slot k -> the 32-bit slot: the bits of
+// hot_mix(u) above mask, min(full[u], mask) below them; an empty slot is
+// all ones.
 __global__ __launch_bounds__(256) void k_hot_fill(const int32_t *__restrict__ full,
-                                                  uint64_t *__restrict__ tab, uint32_t slots) {
-  for (uint32_t k = blockIdx.x * 256 + threadIdx.x; k < slots; k += gridDim.x * 256) {
-    const uint64_t e = tab[k];
+                                                  const uint64_t *__restrict__ win,
+                                                  uint32_t *__restrict__ tab, uint32_t mask) {
+  for (uint32_t k = blockIdx.x * 256 + threadIdx.x; k <= mask; k += gridDim.x * 256) {
+    const uint64_t e = win[k];
     const uint32_t u = uint32_t(e);
-    tab[k] = e ? (uint64_t(uint32_t(full[u])) << 32) | u : 0xFFFFFFFFull;
+    if (!e) {
+      tab[k] = 0xFFFFFFFFu;
+    } else {
+      const uint32_t v = uint32_t(full[u]);
+      tab[k] = (hot_mix(u) & ~mask) | (v < mask ? v : mask);
+    }
   }
 }
 
@@ -75,14 +85,15 @@ pp_status hot_select(const int32_t *deg, int32_t n, uint64_t *tab, int lg, hipSt
 
 pp_status hot_build(const int32_t *deg, const int32_t *full, int32_t n, uint64_t *tab, HotTab *h,
                     hipStream_t s) {
-  const int lg = hot_log2(n);
+  const int lg = hot32_log2(n);
   const uint32_t slots = 1u << lg;
   pp_status st;
   if ((st = hot_select(deg, n, tab, lg, s)) != PP_OK) return st;
+  uint32_t *tab32 = reinterpret_cast<uint32_t *>(tab + slots);
   hipLaunchKernelGGL(k_hot_fill, dim3(grid_for(slots, 256, 1024)), dim3(256), 0, s, full, tab,
-                     slots);
+                     tab32, slots - 1u);
   PP_LAUNCHED("k_hot_max/k_hot_fill");
-  h->tab = tab;
+  h->tab = tab32;
   h->mask = slots - 1u;
   return PP_OK;
 }
